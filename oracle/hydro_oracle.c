@@ -1,0 +1,640 @@
+/*
+ * hydro_oracle.c -- TEST INFRASTRUCTURE ONLY (see hydro_oracle.h).
+ *
+ * Plain FP64 reference of the Godunov step of arXiv 2501.02317, Sec. 3.
+ * Every function follows the paper's order of operations:
+ *   cons -> prim (Sec. 3.1), ghost zones from the boundary rules (Sec. 3.1.1),
+ *   PLM with minmod on primitive variables (eq. minmod, Sec. 3.2.2),
+ *   HLLC with the subtraction-safe wave speeds (eqs. hllc-contact-spd and
+ *   hllc-mixed-dvel; star states and fluxes from Toro's HLLC, which the paper
+ *   cites for the solver), flux-divergence update and the Heun integrator
+ *   (Sec. 3.3), CFL time step on the first sub-step (Sec. 3.1).
+ *
+ * No blocking, fusion or reordering: each face flux is computed once from the
+ * padded primitive array, and each cell sums its face differences in axis
+ * order x, y, z.  Built without FMA contraction.  The OpenMP pragmas only
+ * distribute independent faces and cells over threads; the arithmetic of each
+ * value is unchanged, so results do not depend on the thread count.
+ */
+#include "hydro_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NGH 2   /* ghost layers: PLM is second order (Sec. 3.1, n_gh = spatial order) */
+#define MAXC 5  /* largest ncomp (3-D) */
+
+enum { VM_NONE = 0, VM_NEG = 1, VM_CLIP_LO = 2, VM_CLIP_HI = 3 };
+
+/* ------------------------------------------------------------------ mesh */
+
+static int mesh_ok(const orc_mesh* m) {
+    if (!m || m->ndim < 1 || m->ndim > 3) return 0;
+    if (!(m->gamma > 1.0) || !isfinite(m->gamma)) return 0;
+    for (int d = 0; d < 3; ++d) {
+        if (d < m->ndim) {
+            if (m->n[d] < 1 || !(m->hi[d] > m->lo[d])) return 0;
+            for (int s = 0; s < 2; ++s)
+                if (m->bc[d][s] < ORC_BC_PERIODIC || m->bc[d][s] > ORC_BC_REFLECT) return 0;
+            int per0 = m->bc[d][0] == ORC_BC_PERIODIC, per1 = m->bc[d][1] == ORC_BC_PERIODIC;
+            if (per0 != per1) return 0;
+            /* periodic and reflecting ghosts read n_gh distinct interior cells */
+            if ((per0 || m->bc[d][0] == ORC_BC_REFLECT || m->bc[d][1] == ORC_BC_REFLECT) &&
+                m->n[d] < NGH)
+                return 0;
+        } else if (m->n[d] != 1) {
+            return 0;
+        }
+    }
+    return 1;
+}
+
+int orc_ncomp(const orc_mesh* m) { return mesh_ok(m) ? m->ndim + 2 : -1; }
+
+static int64_t ncells(const orc_mesh* m) { return (int64_t)m->n[0] * m->n[1] * m->n[2]; }
+
+static double cell_width(const orc_mesh* m, int d) { return (m->hi[d] - m->lo[d]) / m->n[d]; }
+
+/* ------------------------------------------------------- pointwise physics */
+
+double orc_minmod(double a, double b) {
+    /* eq. minmod: the smaller-magnitude argument when both have the same
+     * strict sign, zero otherwise (including when either is zero). */
+    if ((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0)) return fabs(a) < fabs(b) ? a : b;
+    return 0.0;
+}
+
+static int admissible(int nc, const double* u, double rho, double p) {
+    for (int c = 0; c < nc; ++c)
+        if (!isfinite(u[c])) return 0;
+    return rho > 0.0 && p > 0.0 && isfinite(p);
+}
+
+/* v_d = m_d / rho ; p = (gamma - 1) (E - (1/2) sum_d m_d v_d)   (Sec. 3.1) */
+static int cons_to_prim_cell(int ndim, double g, const double* u, double* w) {
+    double rho = u[0];
+    double ke2 = 0.0; /* twice the kinetic energy density, summed in axis order */
+    w[0] = rho;
+    for (int d = 0; d < ndim; ++d) {
+        double v = u[1 + d] / rho;
+        w[1 + d] = v;
+        ke2 = ke2 + u[1 + d] * v;
+    }
+    double p = (g - 1.0) * (u[ndim + 1] - 0.5 * ke2);
+    w[ndim + 1] = p;
+    return admissible(ndim + 2, u, rho, p);
+}
+
+/* m_d = rho v_d ; E = p / (gamma - 1) + (1/2) sum_d m_d v_d   (eq. hydro) */
+static void prim_to_cons_cell(int ndim, double g, const double* w, double* u) {
+    double rho = w[0];
+    double ke2 = 0.0;
+    u[0] = rho;
+    for (int d = 0; d < ndim; ++d) {
+        double mom = rho * w[1 + d];
+        u[1 + d] = mom;
+        ke2 = ke2 + mom * w[1 + d];
+    }
+    u[ndim + 1] = w[ndim + 1] / (g - 1.0) + 0.5 * ke2;
+}
+
+void orc_prim_to_cons(const orc_mesh* m, const double* W, double* U) {
+    if (!mesh_ok(m)) return;
+    int nc = m->ndim + 2;
+    int64_t N = ncells(m);
+    for (int64_t i = 0; i < N; ++i) {
+        double w[MAXC] = {0}, u[MAXC] = {0};
+        for (int c = 0; c < nc; ++c) w[c] = W[c * N + i];
+        prim_to_cons_cell(m->ndim, m->gamma, w, u);
+        for (int c = 0; c < nc; ++c) U[c * N + i] = u[c];
+    }
+}
+
+int orc_cons_to_prim(const orc_mesh* m, const double* U, double* W) {
+    if (!mesh_ok(m)) return -1;
+    int nc = m->ndim + 2;
+    int64_t N = ncells(m);
+    int bad = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        double w[MAXC] = {0}, u[MAXC] = {0};
+        for (int c = 0; c < nc; ++c) u[c] = U[c * N + i];
+        if (!cons_to_prim_cell(m->ndim, m->gamma, u, w)) ++bad;
+        for (int c = 0; c < nc; ++c) W[c * N + i] = w[c];
+    }
+    return bad;
+}
+
+/* ------------------------------------------------------------------ HLLC */
+
+/* Conserved state and physical flux of a normal-frame primitive state
+ * (rho, u, t_1..t_nt, p): U = (rho, rho u, rho t, E), F = (rho u, rho u u + p,
+ * rho u t, (E + p) u), with E = p/(gamma-1) + (1/2)(rho u u + (sum rho t t)).
+ * The tangential terms are summed first (two at most, so their order does
+ * not matter): interchanging the two tangential axes leaves E bitwise equal. */
+static void state_and_flux(double g, int nt, const double* W, double* U, double* F) {
+    int nc = nt + 3;
+    double rho = W[0], u = W[1], p = W[nc - 1];
+    double mu = rho * u;
+    double ket = 0.0;
+    U[0] = rho;
+    U[1] = mu;
+    for (int k = 0; k < nt; ++k) {
+        double mt = rho * W[2 + k];
+        U[2 + k] = mt;
+        ket = ket + mt * W[2 + k];
+    }
+    double ke2 = mu * u + ket;
+    double E = p / (g - 1.0) + 0.5 * ke2;
+    U[nc - 1] = E;
+    F[0] = mu;
+    F[1] = mu * u + p;
+    for (int k = 0; k < nt; ++k) F[2 + k] = mu * W[2 + k];
+    F[nc - 1] = (E + p) * u;
+}
+
+/* HLLC star state of side K (Toro's form): chi = rho_K ds_K / (s_K - s_*),
+ * U* = chi (1, s_*, t_K, E_K/rho_K + (s_* - u_K)(s_* + p_K/(rho_K ds_K))). */
+static void star_state(int nt, const double* W, const double* U, double sK, double dsK,
+                       double ss, double* Us) {
+    int nc = nt + 3;
+    double rho = W[0], u = W[1], p = W[nc - 1];
+    double chi = rho * dsK / (sK - ss);
+    Us[0] = chi;
+    Us[1] = chi * ss;
+    for (int k = 0; k < nt; ++k) Us[2 + k] = chi * W[2 + k];
+    Us[nc - 1] = chi * (U[nc - 1] / rho + (ss - u) * (ss + p / (rho * dsK)));
+}
+
+void orc_hllc(double g, int nt, const double* WL, const double* WR, double* F, double* detail) {
+    int nc = nt + 3;
+    double UL[MAXC], UR[MAXC], FL[MAXC], FR[MAXC];
+    double UsL[MAXC], UsR[MAXC], FsL[MAXC], FsR[MAXC];
+    state_and_flux(g, nt, WL, UL, FL);
+    state_and_flux(g, nt, WR, UR, FR);
+
+    double rl = WL[0], ul = WL[1], pl = WL[nc - 1];
+    double rr = WR[0], ur = WR[1], pr = WR[nc - 1];
+    double cl = sqrt(g * pl / rl);
+    double cr = sqrt(g * pr / rr);
+
+    /* pressure estimate for the wave speeds: primitive-variable guess, >= 0 */
+    double ppv = 0.5 * (pl + pr) - 0.125 * (ur - ul) * (rl + rr) * (cl + cr);
+    double ps = ppv > 0.0 ? ppv : 0.0;
+
+    /* eq. hllc-mixed-dvel: ds_L = -c_L q_L, ds_R = c_R q_R */
+    double z = (g + 1.0) / (2.0 * g);
+    double ratl = ps / pl, ratr = ps / pr;
+    double ql = sqrt(1.0 + z * ((ratl > 1.0 ? ratl : 1.0) - 1.0));
+    double qr = sqrt(1.0 + z * ((ratr > 1.0 ? ratr : 1.0) - 1.0));
+    double dsl = -cl * ql;
+    double dsr = cr * qr;
+    double sl = ul + dsl;
+    double sr = ur + dsr;
+
+    /* eq. hllc-contact-spd with (s_K - u_K) replaced by ds_K */
+    double ss = ((pr - rr * ur * dsr) - (pl - rl * ul * dsl)) / (rl * dsl - rr * dsr);
+
+    star_state(nt, WL, UL, sl, dsl, ss, UsL);
+    star_state(nt, WR, UR, sr, dsr, ss, UsR);
+    for (int c = 0; c < nc; ++c) {
+        FsL[c] = FL[c] + sl * (UsL[c] - UL[c]);
+        FsR[c] = FR[c] + sr * (UsR[c] - UR[c]);
+    }
+
+    const double* pick;
+    if (sl >= 0.0)
+        pick = FL;
+    else if (ss >= 0.0)
+        pick = FsL;
+    else if (sr > 0.0)
+        pick = FsR;
+    else
+        pick = FR;
+    for (int c = 0; c < nc; ++c) F[c] = pick[c];
+
+    if (detail) {
+        double* o = detail;
+        *o++ = sl;
+        *o++ = ss;
+        *o++ = sr;
+        *o++ = ps;
+        const double* blocks[8] = {UL, UR, FL, FR, UsL, UsR, FsL, FsR};
+        for (int b = 0; b < 8; ++b)
+            for (int c = 0; c < nc; ++c) *o++ = blocks[b][c];
+    }
+}
+
+/* ------------------------------------------------------------------- PLM */
+
+void orc_plm_face(const double w[4], double* wl, double* wr) {
+    double dj = orc_minmod(w[1] - w[0], w[2] - w[1]);  /* slope of cell j   */
+    double dj1 = orc_minmod(w[2] - w[1], w[3] - w[2]); /* slope of cell j+1 */
+    *wl = w[1] + 0.5 * dj;
+    *wr = w[2] - 0.5 * dj1;
+}
+
+/* Flux through the face between w4[1] and w4[2] along axis d, from the
+ * global-frame primitive states of the four cells around it: reconstruct each
+ * component, rotate so the face normal is the first velocity, solve, rotate back. */
+static void face_flux(int ndim, double g, int d, const double (*w4)[MAXC], double* F) {
+    int nc = ndim + 2;
+    double wl[MAXC], wr[MAXC];
+    for (int c = 0; c < nc; ++c) {
+        double col[4] = {w4[0][c], w4[1][c], w4[2][c], w4[3][c]};
+        orc_plm_face(col, &wl[c], &wr[c]);
+    }
+    double WLn[MAXC], WRn[MAXC], Fn[MAXC];
+    WLn[0] = wl[0];
+    WRn[0] = wr[0];
+    WLn[1] = wl[1 + d];
+    WRn[1] = wr[1 + d];
+    int k = 2;
+    for (int e = 0; e < ndim; ++e) {
+        if (e == d) continue;
+        WLn[k] = wl[1 + e];
+        WRn[k] = wr[1 + e];
+        ++k;
+    }
+    WLn[nc - 1] = wl[nc - 1];
+    WRn[nc - 1] = wr[nc - 1];
+    orc_hllc(g, ndim - 1, WLn, WRn, Fn, NULL);
+    F[0] = Fn[0];
+    F[1 + d] = Fn[1];
+    k = 2;
+    for (int e = 0; e < ndim; ++e) {
+        if (e == d) continue;
+        F[1 + e] = Fn[k++];
+    }
+    F[nc - 1] = Fn[nc - 1];
+}
+
+/* ------------------------------------------------------------ boundaries */
+
+/* Interior cell copied into the ghost at position g (g < 0 or g >= N) along an
+ * axis, and the treatment of the normal velocity there (Sec. 3.1.1, each side
+ * read as the left-x case after rotation). */
+static int ghost_src(const orc_mesh* m, int d, int g, int* vmode) {
+    int N = m->n[d];
+    *vmode = VM_NONE;
+    if (g < 0) {
+        switch (m->bc[d][0]) {
+            case ORC_BC_PERIODIC: return g + N;
+            case ORC_BC_FREE: return 0;
+            case ORC_BC_OUTFLOW: *vmode = VM_CLIP_LO; return 0;
+            default: *vmode = VM_NEG; return -1 - g;
+        }
+    }
+    switch (m->bc[d][1]) {
+        case ORC_BC_PERIODIC: return g - N;
+        case ORC_BC_FREE: return N - 1;
+        case ORC_BC_OUTFLOW: *vmode = VM_CLIP_HI; return N - 1;
+        default: *vmode = VM_NEG; return 2 * N - 1 - g;
+    }
+}
+
+static double apply_vmode(double v, int vmode) {
+    switch (vmode) {
+        case VM_NEG: return -v;
+        case VM_CLIP_LO: return v > 0.0 ? 0.0 : v; /* min{v, 0}: no inflow at the low side  */
+        case VM_CLIP_HI: return v < 0.0 ? 0.0 : v; /* max{v, 0}: no inflow at the high side */
+        default: return v;
+    }
+}
+
+/* padded geometry */
+typedef struct {
+    int pad[3];
+    int64_t P[3];
+    int64_t total;
+} padgeo;
+
+static padgeo pad_geometry(const orc_mesh* m) {
+    padgeo p;
+    p.total = 1;
+    for (int d = 0; d < 3; ++d) {
+        p.pad[d] = d < m->ndim ? NGH : 0;
+        p.P[d] = m->n[d] + 2 * p.pad[d];
+        p.total *= p.P[d];
+    }
+    return p;
+}
+
+static int64_t pidx(const padgeo* p, int i, int j, int k) {
+    return ((int64_t)(k + p->pad[2]) * p->P[1] + (j + p->pad[1])) * p->P[0] + (i + p->pad[0]);
+}
+
+int orc_fill_ghosts(const orc_mesh* m, double* Wpad) {
+    if (!mesh_ok(m)) return -1;
+    int nc = m->ndim + 2;
+    padgeo pg = pad_geometry(m);
+    for (int d = 0; d < m->ndim; ++d) {
+        int N = m->n[d];
+        int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
+        int ghosts[4] = {-2, -1, N, N + 1};
+        /* lines along d through interior transverse positions only: the
+         * axis-aligned stencil never reads corner ghosts */
+        for (int a = 0; a < m->n[e1]; ++a)
+            for (int b = 0; b < m->n[e2]; ++b)
+                for (int q = 0; q < 4; ++q) {
+                    int vmode;
+                    int src = ghost_src(m, d, ghosts[q], &vmode);
+                    int gi[3], si[3];
+                    gi[d] = ghosts[q];
+                    si[d] = src;
+                    gi[e1] = si[e1] = a;
+                    gi[e2] = si[e2] = b;
+                    int64_t go = pidx(&pg, gi[0], gi[1], gi[2]);
+                    int64_t so = pidx(&pg, si[0], si[1], si[2]);
+                    for (int c = 0; c < nc; ++c) Wpad[c * pg.total + go] = Wpad[c * pg.total + so];
+                    Wpad[(1 + d) * pg.total + go] = apply_vmode(Wpad[(1 + d) * pg.total + go], vmode);
+                }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------- stage rhs */
+
+int orc_rhs(const orc_mesh* m, const double* U, double dt, double* dU) {
+    if (!mesh_ok(m)) return -1;
+    int ndim = m->ndim, nc = ndim + 2;
+    double g = m->gamma;
+    int64_t N = ncells(m);
+    int n0 = m->n[0], n1 = m->n[1], n2 = m->n[2];
+    padgeo pg = pad_geometry(m);
+
+    double* Wp = (double*)calloc((size_t)(nc * pg.total), sizeof(double));
+    if (!Wp) return -1;
+    int bad = 0;
+    for (int k = 0; k < n2; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n0; ++i) {
+                int64_t cell = ((int64_t)k * n1 + j) * n0 + i;
+                double u[MAXC], w[MAXC];
+                for (int c = 0; c < nc; ++c) u[c] = U[c * N + cell];
+                if (!cons_to_prim_cell(ndim, g, u, w)) ++bad;
+                int64_t o = pidx(&pg, i, j, k);
+                for (int c = 0; c < nc; ++c) Wp[c * pg.total + o] = w[c];
+            }
+    if (bad) {
+        free(Wp);
+        return bad;
+    }
+    orc_fill_ghosts(m, Wp);
+
+    /* face fluxes: axis d has n_d + 1 faces per line; face f separates cells f-1 and f */
+    double* Fd[3] = {NULL, NULL, NULL};
+    int64_t fext[3][3];
+    for (int d = 0; d < ndim; ++d) {
+        for (int e = 0; e < 3; ++e) fext[d][e] = m->n[e] + (e == d ? 1 : 0);
+        int64_t nf = fext[d][0] * fext[d][1] * fext[d][2];
+        Fd[d] = (double*)malloc((size_t)(nc * nf) * sizeof(double));
+        if (!Fd[d]) {
+            for (int e = 0; e < d; ++e) free(Fd[e]);
+            free(Wp);
+            return -1;
+        }
+#pragma omp parallel for schedule(static)
+        for (int fk = 0; fk < (int)fext[d][2]; ++fk)
+            for (int fj = 0; fj < (int)fext[d][1]; ++fj)
+                for (int fi = 0; fi < (int)fext[d][0]; ++fi) {
+                    int f[3] = {fi, fj, fk};
+                    double w4[4][MAXC];
+                    for (int s = 0; s < 4; ++s) {
+                        int c3[3] = {fi, fj, fk};
+                        c3[d] = f[d] - 2 + s;
+                        int64_t o = pidx(&pg, c3[0], c3[1], c3[2]);
+                        for (int c = 0; c < nc; ++c) w4[s][c] = Wp[c * pg.total + o];
+                    }
+                    double F[MAXC];
+                    face_flux(ndim, g, d, w4, F);
+                    int64_t fo = ((int64_t)fk * fext[d][1] + fj) * fext[d][0] + fi;
+                    for (int c = 0; c < nc; ++c) Fd[d][c * (nf) + fo] = F[c];
+                }
+    }
+
+    /* dU_i = sum over d (in order) of dt/dx_d (F_{d,i-1/2} - F_{d,i+1/2}) */
+    double lam[3];
+    for (int d = 0; d < ndim; ++d) lam[d] = dt / cell_width(m, d);
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n2; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n0; ++i) {
+                int64_t cell = ((int64_t)k * n1 + j) * n0 + i;
+                int c3[3] = {i, j, k};
+                for (int c = 0; c < nc; ++c) {
+                    double acc = 0.0;
+                    for (int d = 0; d < ndim; ++d) {
+                        int64_t nf = fext[d][0] * fext[d][1] * fext[d][2];
+                        int lo3[3] = {c3[0], c3[1], c3[2]};
+                        int hi3[3] = {c3[0], c3[1], c3[2]};
+                        hi3[d] += 1;
+                        int64_t flo = ((int64_t)lo3[2] * fext[d][1] + lo3[1]) * fext[d][0] + lo3[0];
+                        int64_t fhi = ((int64_t)hi3[2] * fext[d][1] + hi3[1]) * fext[d][0] + hi3[0];
+                        acc = acc + lam[d] * (Fd[d][c * nf + flo] - Fd[d][c * nf + fhi]);
+                    }
+                    dU[c * N + cell] = acc;
+                }
+            }
+    for (int d = 0; d < ndim; ++d) free(Fd[d]);
+    free(Wp);
+    return 0;
+}
+
+/* ------------------------------------------------------------ integrator */
+
+int orc_heun_step(const orc_mesh* m, double* U, double dt) {
+    if (!mesh_ok(m) || !(dt > 0.0) || !isfinite(dt)) return -1;
+    int nc = m->ndim + 2;
+    int64_t N = ncells(m), tot = nc * N;
+    double* U1 = (double*)malloc((size_t)tot * sizeof(double));
+    double* dU = (double*)malloc((size_t)tot * sizeof(double));
+    if (!U1 || !dU) {
+        free(U1);
+        free(dU);
+        return -1;
+    }
+    int rc = orc_rhs(m, U, dt, dU);
+    if (rc == 0) {
+        /* predictor U1 = U^n + dU(U^n), kept in full precision (Sec. 3.3) */
+        for (int64_t q = 0; q < tot; ++q) U1[q] = U[q] + dU[q];
+        rc = orc_rhs(m, U1, dt, dU);
+    }
+    if (rc == 0) {
+        /* corrector U^{n+1} = (1/2) U^n + (1/2) (U1 + dU(U1)) */
+        for (int64_t q = 0; q < tot; ++q) U[q] = 0.5 * U[q] + 0.5 * (U1[q] + dU[q]);
+    }
+    free(U1);
+    free(dU);
+    return rc;
+}
+
+double orc_cfl_dt(const orc_mesh* m, const double* U, double cfl) {
+    if (!mesh_ok(m) || !(cfl > 0.0)) return -1.0;
+    int ndim = m->ndim, nc = ndim + 2;
+    double g = m->gamma;
+    int64_t N = ncells(m);
+    double best = INFINITY;
+    for (int64_t i = 0; i < N; ++i) {
+        double u[MAXC], w[MAXC];
+        for (int c = 0; c < nc; ++c) u[c] = U[c * N + i];
+        if (!cons_to_prim_cell(ndim, g, u, w)) return -1.0;
+        double cs = sqrt(g * w[nc - 1] / w[0]);
+        for (int d = 0; d < ndim; ++d) {
+            double cand = cell_width(m, d) / (fabs(w[1 + d]) + cs);
+            if (cand < best) best = cand;
+        }
+    }
+    return cfl * best;
+}
+
+int orc_run(const orc_mesh* m, double* U, double cfl, int max_steps, double t_end, double* t,
+            int* steps_done, double* dts) {
+    if (!mesh_ok(m) || !t) return -1;
+    if (max_steps <= 0 && !(t_end > 0.0)) return -1;
+    int s = 0;
+    int rc = 0;
+    while (max_steps <= 0 || s < max_steps) {
+        if (t_end > 0.0 && !(*t < t_end)) break;
+        double dt = orc_cfl_dt(m, U, cfl);
+        if (!(dt > 0.0)) {
+            rc = 1;
+            break;
+        }
+        int last = 0;
+        if (t_end > 0.0 && dt >= t_end - *t) {
+            dt = t_end - *t;
+            last = 1;
+        }
+        rc = orc_heun_step(m, U, dt);
+        if (rc) break;
+        if (dts) dts[s] = dt;
+        *t = last ? t_end : *t + dt;
+        ++s;
+    }
+    if (steps_done) *steps_done = s;
+    return rc;
+}
+
+void orc_totals(const orc_mesh* m, const double* U, double* totals) {
+    if (!mesh_ok(m)) return;
+    int nc = m->ndim + 2;
+    int64_t N = ncells(m);
+    double dV = 1.0;
+    for (int d = 0; d < m->ndim; ++d) dV *= cell_width(m, d);
+    for (int c = 0; c < nc; ++c) {
+        double sum = 0.0, comp = 0.0;
+        for (int64_t i = 0; i < N; ++i) {
+            double x = U[c * N + i];
+            double t = sum + x;
+            if (fabs(sum) >= fabs(x))
+                comp += (sum - t) + x;
+            else
+                comp += (x - t) + sum;
+            sum = t;
+        }
+        totals[c] = dV * (sum + comp);
+    }
+}
+
+/* --------------------------------------------------- sampled evaluation */
+
+/* Field source for the sampled path: the full U^n array, or U^n plus one
+ * stage-1 update evaluated on demand (the predictor U1 at any cell). */
+typedef struct {
+    const orc_mesh* m;
+    const double* U;
+    double dt;
+    int predictor;
+} field_src;
+
+static int cell_rhs(const field_src* f, int64_t cell, double* dU);
+
+static int field_get(const field_src* f, int64_t cell, double* u) {
+    int nc = f->m->ndim + 2;
+    int64_t N = ncells(f->m);
+    for (int c = 0; c < nc; ++c) u[c] = f->U[c * N + cell];
+    if (!f->predictor) return 0;
+    field_src base = {f->m, f->U, f->dt, 0};
+    double dU[MAXC];
+    int rc = cell_rhs(&base, cell, dU);
+    if (rc) return rc;
+    for (int c = 0; c < nc; ++c) u[c] = u[c] + dU[c];
+    return 0;
+}
+
+/* Stage rhs at one interior cell from its axis-aligned 5-cell crosses, with
+ * the same face_flux and ghost rules as the full-mesh path. */
+static int cell_rhs(const field_src* f, int64_t cell, double* dU) {
+    const orc_mesh* m = f->m;
+    int ndim = m->ndim, nc = ndim + 2;
+    int n0 = m->n[0], n1 = m->n[1];
+    int idx[3] = {(int)(cell % n0), (int)((cell / n0) % n1), (int)(cell / ((int64_t)n0 * n1))};
+    double acc[MAXC];
+    for (int c = 0; c < nc; ++c) acc[c] = 0.0;
+    for (int d = 0; d < ndim; ++d) {
+        double w5[5][MAXC];
+        for (int s = 0; s < 5; ++s) {
+            int q = idx[d] - 2 + s;
+            int vmode = VM_NONE;
+            if (q < 0 || q >= m->n[d]) q = ghost_src(m, d, q, &vmode);
+            int c3[3] = {idx[0], idx[1], idx[2]};
+            c3[d] = q;
+            int64_t src = ((int64_t)c3[2] * n1 + c3[1]) * n0 + c3[0];
+            double u[MAXC];
+            int rc = field_get(f, src, u);
+            if (rc) return rc;
+            if (!cons_to_prim_cell(ndim, m->gamma, u, w5[s])) return 1;
+            w5[s][1 + d] = apply_vmode(w5[s][1 + d], vmode);
+        }
+        double Fm[MAXC], Fp[MAXC];
+        face_flux(ndim, m->gamma, d, (const double(*)[MAXC])&w5[0], Fm);
+        face_flux(ndim, m->gamma, d, (const double(*)[MAXC])&w5[1], Fp);
+        double lam = f->dt / cell_width(m, d);
+        for (int c = 0; c < nc; ++c) acc[c] = acc[c] + lam * (Fm[c] - Fp[c]);
+    }
+    for (int c = 0; c < nc; ++c) dU[c] = acc[c];
+    return 0;
+}
+
+static int check_cells(const orc_mesh* m, int ns, const int64_t* cells) {
+    int64_t N = ncells(m);
+    for (int s = 0; s < ns; ++s)
+        if (cells[s] < 0 || cells[s] >= N) return 0;
+    return 1;
+}
+
+int orc_rhs_cells(const orc_mesh* m, const double* U, double dt, int ns, const int64_t* cells,
+                  double* out) {
+    if (!mesh_ok(m) || ns < 0 || !check_cells(m, ns, cells)) return -1;
+    int nc = m->ndim + 2;
+    field_src f = {m, U, dt, 0};
+    for (int s = 0; s < ns; ++s) {
+        double dU[MAXC];
+        int rc = cell_rhs(&f, cells[s], dU);
+        if (rc) return rc;
+        for (int c = 0; c < nc; ++c) out[c * ns + s] = dU[c];
+    }
+    return 0;
+}
+
+int orc_step_cells(const orc_mesh* m, const double* U, double dt, int ns, const int64_t* cells,
+                   double* out) {
+    if (!mesh_ok(m) || ns < 0 || !check_cells(m, ns, cells)) return -1;
+    int nc = m->ndim + 2;
+    int64_t N = ncells(m);
+    field_src base = {m, U, dt, 0};
+    field_src pred = {m, U, dt, 1};
+    for (int s = 0; s < ns; ++s) {
+        double dU1[MAXC], dU2[MAXC];
+        int rc = cell_rhs(&base, cells[s], dU1);
+        if (!rc) rc = cell_rhs(&pred, cells[s], dU2);
+        if (rc) return rc;
+        for (int c = 0; c < nc; ++c) {
+            double un = U[c * N + cells[s]];
+            double u1 = un + dU1[c];
+            out[c * ns + s] = 0.5 * un + 0.5 * (u1 + dU2[c]);
+        }
+    }
+    return 0;
+}

@@ -1,0 +1,167 @@
+/*
+ * hydro.h -- C ABI of the MI355X (gfx950) Godunov hydrodynamics library.
+ *
+ * The library advances the Euler equations of a gamma-law gas (eq. hydro of
+ * Wang, "The Kratos Framework for Heterogeneous Astrophysical Simulations",
+ * arXiv 2501.02317) on a uniform Cartesian mesh with the method of its
+ * Sec. 3: primitive-variable PLM reconstruction with the minmod limiter
+ * (eq. minmod), the HLLC Riemann solver with subtraction-safe wave speeds
+ * (eqs. hllc-contact-spd and hllc-mixed-dvel), a flux-divergence update in
+ * the Heun two-stage integrator (Sec. 3.3), and a global CFL time step taken
+ * at the first sub-step (Sec. 3.1).  Ghost zones follow Sec. 3.1.1 and are
+ * resolved inside the kernels' loads; no ghost layers are stored.
+ *
+ * Data conventions
+ *   - ndim in {1,2,3}; n[d] interior cells on axis d; axes d >= ndim must
+ *     have n[d] == 1.  ncomp = 2 + ndim.
+ *   - Conserved state U = (rho, m_1..m_ndim, E), primitive W = (rho,
+ *     v_1..v_ndim, p): only in-plane momenta are carried.
+ *   - Host and device fields are FP64, layout [comp][k][j][i] with i (x)
+ *     fastest, interior cells only (ncomp * n[0] * n[1] * n[2] doubles).
+ *   - Precision (Sec. 3.2.2): HYDRO_FP64 does everything in FP64.
+ *     HYDRO_MIXED converts to primitive variables in FP64, rounds them to
+ *     FP32, does PLM and HLLC in FP32, and keeps the flux difference, the
+ *     Heun combine, the predictor, dt and the totals in FP64.
+ *
+ * Memory, streams and threads
+ *   - Device memory is owned by the caller: hydro_create carves its state
+ *     out of a caller-provided device workspace of at least
+ *     hydro_workspace_bytes(cfg) bytes (256-byte aligned), which must outlive
+ *     the handle.  The handle itself owns only host metadata and a small
+ *     pinned host staging buffer.
+ *   - All device work is enqueued on the caller's HIP stream given at
+ *     creation (NULL = the legacy default stream).
+ *   - hydro_step / hydro_step_auto return after enqueueing.  hydro_cfl_dt,
+ *     hydro_conserved_totals, hydro_time, hydro_get_state and the setters
+ *     block until the stream has drained.
+ *   - A handle is not thread safe; serialise calls per handle.
+ *
+ * Errors
+ *   Every call returns HYDRO_OK (0) or a negative status; nothing throws or
+ *   aborts across the ABI.  Invalid arguments return HYDRO_E_INVAL without
+ *   side effects.  A non-physical state met by a kernel (rho <= 0, p <= 0 or
+ *   a non-finite value in a stage input) sets a sticky device flag that the
+ *   next blocking call reports as HYDRO_E_NONPHYSICAL.  A failed HIP call
+ *   returns HYDRO_E_DEVICE; the handle then only accepts hydro_destroy.
+ */
+#ifndef HYDRO_H
+#define HYDRO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hydro_ctx* hydro_t;
+typedef struct hydro_batch_ctx* hydro_batch_t;
+
+enum hydro_status {
+    HYDRO_OK = 0,
+    HYDRO_E_INVAL = -1,
+    HYDRO_E_NOMEM = -2,
+    HYDRO_E_DEVICE = -3,
+    HYDRO_E_NONPHYSICAL = -4,
+    HYDRO_E_STATE = -5
+};
+
+enum hydro_precision { HYDRO_FP64 = 0, HYDRO_MIXED = 1 };
+
+/* Boundary rules per axis side (Sec. 3.1.1): periodic (both sides of an
+ * axis), free (zero gradient), outflow (free, normal velocity clipped so no
+ * fluid enters), reflecting (mirror with the normal velocity negated). */
+enum hydro_bc { HYDRO_BC_PERIODIC = 0, HYDRO_BC_FREE = 1, HYDRO_BC_OUTFLOW = 2, HYDRO_BC_REFLECT = 3 };
+
+typedef struct {
+    int32_t ndim;      /* 1, 2 or 3 */
+    int32_t n[3];      /* interior cells per axis, n[d] = 1 for d >= ndim */
+    double lo[3];      /* domain lower corner (active axes) */
+    double hi[3];      /* domain upper corner, hi > lo */
+    double gamma;      /* adiabatic index, > 1 */
+    double cfl;        /* Courant number in (0, 1] */
+    int32_t precision; /* enum hydro_precision */
+    int32_t bc[3][2];  /* enum hydro_bc per axis side (low, high) */
+} hydro_config;
+
+/* Device bytes a handle for cfg needs; 0 when cfg is invalid. */
+size_t hydro_workspace_bytes(const hydro_config* cfg);
+
+/* Validate cfg, carve the workspace, and bind the stream.  The state is zero
+ * until hydro_set_state / hydro_set_primitive.  *out receives the handle. */
+int hydro_create(const hydro_config* cfg, void* d_workspace, size_t nbytes, void* hip_stream,
+                 hydro_t* out);
+
+/* Copy a host conserved state in (layout above) and reset t to 0. */
+int hydro_set_state(hydro_t h, const double* U_host);
+
+/* Copy a host primitive state in and convert it to conserved variables on
+ * the device (m = rho v, E = p/(gamma-1) + (1/2) sum m v); reset t to 0. */
+int hydro_set_primitive(hydro_t h, const double* W_host);
+
+/* Copy the current conserved state out (blocks). */
+int hydro_get_state(hydro_t h, double* U_host);
+
+/* Device address of the current conserved state (valid until the next step). */
+int hydro_state_device(hydro_t h, const double** d_U);
+
+/* CFL step of the current state, cfl * min over cells and active axes of
+ * dx_d / (|v_d| + sqrt(gamma p / rho)) (Sec. 3.1).  Blocks. */
+int hydro_cfl_dt(hydro_t h, double* dt);
+
+/* One Heun step of length dt > 0 (async): stage 1 U1 = U + L(U) dt, stage 2
+ * U = U/2 + (U1 + L(U1) dt)/2, each stage fused into one kernel. */
+int hydro_step(hydro_t h, double dt);
+
+/* nsteps Heun steps with the CFL dt kept on the device (async, no host
+ * synchronisation).  The dt of each step comes from the previous step's
+ * stage-2 epilogue (the first from a standalone reduction).  When t_end > 0
+ * the step that would pass t_end is shortened to land on it and later steps
+ * are no-ops. */
+int hydro_step_auto(hydro_t h, int nsteps, double t_end);
+
+/* dV-weighted conserved totals, ncomp values: deterministic compensated
+ * FP64 sums in a fixed order (blocks). */
+int hydro_conserved_totals(hydro_t h, double* totals);
+
+/* Simulation time and completed step count (blocks). */
+int hydro_time(hydro_t h, double* t);
+int hydro_steps_done(hydro_t h, int64_t* steps);
+
+/* One stage right-hand side dU = sum_d dt/dx_d (F_{d,i-1/2} - F_{d,i+1/2})
+ * of the current state, copied to the host (blocks).  Same kernel as the
+ * stages, writing the increment instead of the update. */
+int hydro_stage_rhs(hydro_t h, double dt, double* dU_host);
+
+/* Primitive state with the two ghost layers of every active axis resolved
+ * by the boundary rules, as the kernels see it (FP64 mode: exact; mixed:
+ * the FP32-rounded values), copied to the host in a padded [comp][K][J][I]
+ * array with n_d + 4 cells on active axes; corner ghosts are set to 0. */
+int hydro_padded_primitive(hydro_t h, double* Wpad_host);
+
+/* Event timing of the stage kernels, for measurement: after
+ * hydro_profile(h, cap) the next cap launches of each stage kernel are
+ * bracketed by HIP events on the handle's stream (cap = 0 turns timing off
+ * and frees the events).  hydro_profile_read blocks, returns the summed
+ * durations in milliseconds of the recorded stage-1 and stage-2 launches and
+ * their counts (launches[0], launches[1]), and restarts the recording. */
+int hydro_profile(hydro_t h, int cap);
+int hydro_profile_read(hydro_t h, double* ms_stage1, double* ms_stage2, int64_t* launches);
+
+int hydro_destroy(hydro_t h);
+
+const char* hydro_strerror(int status);
+
+/* HLLC fluxes of nfaces face-normal state pairs on the device (async on
+ * stream): WL, WR, F are device arrays [ntan+3][nfaces] of FP64 holding
+ * (rho, u, t_1..t_ntan, p) and the (mass, normal momentum, tangential
+ * momenta, energy) fluxes; precision selects FP64 or FP32 arithmetic.  The
+ * same device function the stage kernels use. */
+int hydro_riemann_fluxes(int precision, int ntan, double gamma, int64_t nfaces, const double* d_WL,
+                         const double* d_WR, double* d_F, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,86 @@
+// Internal interface between the host runtime (runtime.hip) and the device
+// kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hydro {
+
+constexpr int kMaxComp = 5;
+
+// Device control block, one per mesh, in the caller's workspace.
+struct Ctrl {
+    double dt_raw;                  // cfl * min CFL candidate of the current state
+    double t;                       // simulation time
+    unsigned long long dtmin_bits;  // min accumulator: positive doubles order as integers
+    unsigned int flags;             // sticky error flags
+    unsigned int dt_valid;          // dt_raw belongs to the current state
+    unsigned long long steps;       // completed steps
+    double sums[2 * kMaxComp];      // totals: (sum, compensation) per component
+    double pad[9];
+};
+static_assert(sizeof(Ctrl) == 192, "control block layout");
+
+enum : unsigned int { FLAG_NONPHYSICAL = 1u };
+
+enum CtrlOp : int {
+    CTRL_INIT = 0,           // t = a0, steps = 0, flags = 0, dt invalid
+    CTRL_RESET_MIN = 1,      // dtmin = +inf
+    CTRL_FINALIZE_DT = 2,    // dt_raw = cfl * dtmin, dt valid
+    CTRL_FINALIZE_STEP = 3,  // t += clamped dt (t_end = a1), dt_raw = cfl * dtmin, reset min
+    CTRL_ADVANCE_T = 4,      // t += a0 (host dt), dt invalid
+};
+
+// Geometry in kernel axes.  Kernel axis 0 is x.  For 3-D, kernel axes
+// (0, 1, 2) are (x, y, z); for 2-D, kernel axis 2 (the marching axis)
+// is the physical y axis and kernel axis 1 has extent 1; for 1-D only
+// kernel axis 0 is active.  The cell index (k * n1 + j) * n0 + i is the
+// physical storage index in every case.
+struct Geo {
+    int ndim;
+    int n[3];
+    double dx[3];
+    int bc[3][2];
+    double gamma;
+    double cfl;
+    long long ncells;
+};
+
+struct Tile {
+    int tx, ty, kz;
+};
+
+struct StageArgs {
+    const double* in;    // stencil source: U^n (stage 1 / rhs) or U1 (stage 2)
+    const double* base;  // U^n for the stage-2 combine (may alias out)
+    double* out;         // U1, U^{n+1} (in place over base) or the increment
+    Ctrl* ctrl;
+    Geo geo;
+    double dt_host;      // dt when use_device_dt == 0
+    double t_end;        // clamp target for the device dt (0: none)
+    int use_device_dt;
+    int want_dt;         // stage 2: accumulate the next CFL candidate
+    int tiles_x, tiles_y, chunks_z, kz;
+};
+
+enum StageMode : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2 };
+
+hipError_t launch_stage(int precision, int mode, const Tile& tile, StageArgs a, hipStream_t s);
+hipError_t launch_dt(const Geo& g, const double* U, Ctrl* ctrl, hipStream_t s);
+hipError_t launch_ctrl(Ctrl* c, int op, double a0, double a1, double cfl, hipStream_t s);
+hipError_t launch_totals(const Geo& g, const double* U, double* partials, int nparts, Ctrl* ctrl,
+                         hipStream_t s);
+hipError_t launch_prim_to_cons(const Geo& g, const double* W, double* U, hipStream_t s);
+hipError_t launch_padded_prim(const Geo& g, int precision, const double* U, double* Wpad, Ctrl* ctrl,
+                              hipStream_t s);
+hipError_t launch_riemann(int precision, int ntan, double gamma, long long n, const double* WL,
+                          const double* WR, double* F, hipStream_t s);
+
+// Default tile for a mesh (kernel axes) and precision.
+Tile default_tile(const Geo& g, int precision);
+// Number of totals partials the runtime reserves.
+constexpr int kTotalsParts = 1024;
+
+}  // namespace hydro

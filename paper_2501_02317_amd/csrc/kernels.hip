@@ -1,0 +1,924 @@
+// Device kernels of the Godunov hydro step for gfx950 (CDNA4, wave64).
+//
+// Method (Wang, arXiv 2501.02317, Sec. 3): conserved -> primitive in FP64
+// (Sec. 3.1), ghost cells from the boundary rules of Sec. 3.1.1 resolved at
+// load time, PLM with minmod on primitive variables (eq. minmod), HLLC with
+// the subtraction-safe wave speeds (eqs. hllc-contact-spd, hllc-mixed-dvel),
+// flux-divergence update and Heun combine in FP64 (Sec. 3.3), CFL dt
+// reduction (Sec. 3.1).
+//
+// Layout: SoA FP64 U[c][k][j][i], interior only.  The stage kernel is a
+// 2.5-D sweep: a work-group owns a TX x TY tile of the (kernel) x-y plane and
+// marches along the kernel z axis over a chunk of kz planes.  The z stencil
+// (five planes of primitive variables) lives in registers, the in-plane
+// stencil in an LDS plane with a two-cell halo.  Every face flux is computed
+// once per work-group and is one value shared by both neighbouring cells.
+//
+// No floating-point contraction: each FP64 operation is the IEEE operation
+// written here, so the FP64 path reproduces a plain serial evaluation of the
+// same formulas.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+
+#include "hydro_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace hydro {
+namespace {
+
+enum { BC_PERIODIC = 0, BC_FREE = 1, BC_OUTFLOW = 2, BC_REFLECT = 3 };
+enum { VM_NONE = 0, VM_NEG = 1, VM_CLIP_LO = 2, VM_CLIP_HI = 3 };
+
+constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
+
+__device__ __forceinline__ double dabs(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ float dabs(float x) { return __builtin_fabsf(x); }
+__device__ __forceinline__ double dsqrt(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
+
+// Velocity component (index into W/U) along kernel axis ax.
+template <int NDIM>
+__device__ __forceinline__ constexpr int vcomp(int ax) {
+    return ax == 0 ? 1 : (ax == 1 ? 2 : NDIM);
+}
+
+// ----------------------------------------------------------------- physics
+
+template <typename R>
+__device__ __forceinline__ R minmod(R a, R b) {
+    // eq. minmod; zero unless both slopes have the same strict sign
+    const bool same = (a > R(0) && b > R(0)) || (a < R(0) && b < R(0));
+    const R m = dabs(a) < dabs(b) ? a : b;
+    return same ? m : R(0);
+}
+
+// v_d = m_d / rho, p = (gamma - 1)(E - (1/2) sum_d m_d v_d); returns admissibility.
+template <int NDIM>
+__device__ __forceinline__ bool cons_to_prim(double g, const double (&u)[NDIM + 2],
+                                             double (&w)[NDIM + 2]) {
+    const double rho = u[0];
+    double ke2 = 0.0;
+    w[0] = rho;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+        const double v = u[1 + d] / rho;
+        w[1 + d] = v;
+        ke2 = ke2 + u[1 + d] * v;
+    }
+    const double p = (g - 1.0) * (u[NDIM + 1] - 0.5 * ke2);
+    w[NDIM + 1] = p;
+    bool fin = true;
+#pragma unroll
+    for (int c = 0; c < NDIM + 2; ++c) fin = fin && __builtin_isfinite(u[c]);
+    return fin && rho > 0.0 && p > 0.0 && __builtin_isfinite(p);
+}
+
+// HLLC flux in the face-normal frame, W = (rho, u, t_1..t_NT, p).  Wave
+// speeds s_K = u_K + ds_K with ds_L = -c_L q_L, ds_R = c_R q_R and
+// q_K = sqrt(1 + (g+1)/(2g) (max(p*/p_K, 1) - 1)), p* the primitive-variable
+// pressure guess clipped at 0; contact speed from the bracketed form of
+// eq. hllc-contact-spd.  Only the side the selection picks is evaluated.
+template <typename R, int NT>
+__device__ __forceinline__ void hllc(const R g, const R (&WL)[NT + 3], const R (&WR)[NT + 3],
+                                     R (&F)[NT + 3]) {
+    constexpr int NC = NT + 3;
+    const R rl = WL[0], ul = WL[1], pl = WL[NC - 1];
+    const R rr = WR[0], ur = WR[1], pr = WR[NC - 1];
+    const R cl = dsqrt(g * pl / rl);
+    const R cr = dsqrt(g * pr / rr);
+    const R ppv = R(0.5) * (pl + pr) - R(0.125) * (ur - ul) * (rl + rr) * (cl + cr);
+    const R ps = ppv > R(0) ? ppv : R(0);
+    const R z = (g + R(1)) / (R(2) * g);
+    const R ratl = ps / pl, ratr = ps / pr;
+    const R ql = dsqrt(R(1) + z * ((ratl > R(1) ? ratl : R(1)) - R(1)));
+    const R qr = dsqrt(R(1) + z * ((ratr > R(1) ? ratr : R(1)) - R(1)));
+    const R dsl = -cl * ql;
+    const R dsr = cr * qr;
+    const R sl = ul + dsl;
+    const R sr = ur + dsr;
+    const R ss = ((pr - rr * ur * dsr) - (pl - rl * ul * dsl)) / (rl * dsl - rr * dsr);
+
+    // s_L >= 0: F_L ; s_* >= 0: F*_L ; s_R > 0: F*_R ; else F_R
+    const bool left = (sl >= R(0)) || (ss >= R(0));
+    const bool star = left ? !(sl >= R(0)) : (sr > R(0));
+    const R sK = left ? sl : sr;
+    const R dsK = left ? dsl : dsr;
+    R W[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) W[c] = left ? WL[c] : WR[c];
+
+    const R rho = W[0], u = W[1], p = W[NC - 1];
+    const R mu = rho * u;
+    R ket = R(0);
+    R Uk[NC], Fk[NC];
+    Uk[0] = rho;
+    Uk[1] = mu;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        const R mt = rho * W[2 + k];
+        Uk[2 + k] = mt;
+        ket = ket + mt * W[2 + k];
+    }
+    const R ke2 = mu * u + ket;
+    const R E = p / (g - R(1)) + R(0.5) * ke2;
+    Uk[NC - 1] = E;
+    Fk[0] = mu;
+    Fk[1] = mu * u + p;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) Fk[2 + k] = mu * W[2 + k];
+    Fk[NC - 1] = (E + p) * u;
+
+    // star state chi (1, s_*, t, E/rho + (s_* - u)(s_* + p/(rho ds))), chi = rho ds / (s - s_*)
+    const R chi = rho * dsK / (sK - ss);
+    R Us[NC];
+    Us[0] = chi;
+    Us[1] = chi * ss;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) Us[2 + k] = chi * W[2 + k];
+    Us[NC - 1] = chi * (E / rho + (ss - u) * (ss + p / (rho * dsK)));
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const R fs = Fk[c] + sK * (Us[c] - Uk[c]);
+        F[c] = star ? fs : Fk[c];
+    }
+}
+
+// Flux through the face between cells w1 and w2 along kernel axis AX from the
+// global-frame primitive states of the four cells around it: PLM per
+// component, rotate the face normal to the first velocity slot, HLLC, rotate
+// back.  Tangential velocities keep increasing component order.
+template <int NDIM, int AX, typename R>
+__device__ __forceinline__ void face_flux(const R g, const R (&w0)[NDIM + 2], const R (&w1)[NDIM + 2],
+                                          const R (&w2)[NDIM + 2], const R (&w3)[NDIM + 2],
+                                          R (&F)[NDIM + 2]) {
+    constexpr int NC = NDIM + 2;
+    constexpr int NT = NDIM - 1;
+    constexpr int VN = vcomp<NDIM>(AX);
+    R wl[NC], wr[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const R dj = minmod(w1[c] - w0[c], w2[c] - w1[c]);
+        const R dj1 = minmod(w2[c] - w1[c], w3[c] - w2[c]);
+        wl[c] = w1[c] + R(0.5) * dj;
+        wr[c] = w2[c] - R(0.5) * dj1;
+    }
+    R L[NT + 3], Rs[NT + 3], Fn[NT + 3];
+    L[0] = wl[0];
+    Rs[0] = wr[0];
+    L[1] = wl[VN];
+    Rs[1] = wr[VN];
+    {
+        int k = 2;
+#pragma unroll
+        for (int e = 1; e <= NDIM; ++e) {
+            if (e == VN) continue;
+            L[k] = wl[e];
+            Rs[k] = wr[e];
+            ++k;
+        }
+    }
+    L[NT + 2] = wl[NC - 1];
+    Rs[NT + 2] = wr[NC - 1];
+    hllc<R, NT>(g, L, Rs, Fn);
+    F[0] = Fn[0];
+    F[VN] = Fn[1];
+    {
+        int k = 2;
+#pragma unroll
+        for (int e = 1; e <= NDIM; ++e) {
+            if (e == VN) continue;
+            F[e] = Fn[k++];
+        }
+    }
+    F[NC - 1] = Fn[NT + 2];
+}
+
+// ---------------------------------------------------------------- boundaries
+
+// Interior index for coordinate q on kernel axis ax and the treatment of
+// the normal velocity (Sec. 3.1.1; each side read as the left-x case).
+__device__ __forceinline__ int resolve(const Geo& g, int ax, int q, int& vmode) {
+    const int N = g.n[ax];
+    vmode = VM_NONE;
+    if (q >= 0 && q < N) return q;
+    if (q < 0) {
+        switch (g.bc[ax][0]) {
+            case BC_PERIODIC: return q + N;
+            case BC_FREE: return 0;
+            case BC_OUTFLOW: vmode = VM_CLIP_LO; return 0;
+            default: vmode = VM_NEG; return -1 - q;
+        }
+    }
+    switch (g.bc[ax][1]) {
+        case BC_PERIODIC: return q - N;
+        case BC_FREE: return N - 1;
+        case BC_OUTFLOW: vmode = VM_CLIP_HI; return N - 1;
+        default: vmode = VM_NEG; return 2 * N - 1 - q;
+    }
+}
+
+__device__ __forceinline__ double apply_vmode(double v, int vmode) {
+    switch (vmode) {
+        case VM_NEG: return -v;
+        case VM_CLIP_LO: return v > 0.0 ? 0.0 : v;
+        case VM_CLIP_HI: return v < 0.0 ? 0.0 : v;
+        default: return v;
+    }
+}
+
+// Primitive state at kernel coordinates (x, y, z), at most one of which lies
+// outside the mesh (the axis-aligned stencil never needs corner ghosts).
+template <int NDIM, typename R>
+__device__ __forceinline__ void load_w(const Geo& g, const double* __restrict__ U, int x, int y, int z,
+                                       R (&W)[NDIM + 2], bool& bad) {
+    constexpr int NC = NDIM + 2;
+    int vm = VM_NONE, ax = -1;
+    if (x < 0 || x >= g.n[0]) {
+        x = resolve(g, 0, x, vm);
+        ax = 0;
+    } else if (y < 0 || y >= g.n[1]) {
+        y = resolve(g, 1, y, vm);
+        ax = 1;
+    } else if (z < 0 || z >= g.n[2]) {
+        z = resolve(g, 2, z, vm);
+        ax = 2;
+    }
+    const long long cell = ((long long)z * g.n[1] + y) * g.n[0] + x;
+    double u[NC], w[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) u[c] = U[c * g.ncells + cell];
+    bad |= !cons_to_prim<NDIM>(g.gamma, u, w);
+    if (ax >= 0) {
+        const int vc = ax == 0 ? 1 : (ax == 1 ? 2 : NDIM);
+#pragma unroll
+        for (int c = 1; c <= NDIM; ++c)
+            if (c == vc) w[c] = apply_vmode(w[c], vm);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) W[c] = (R)w[c];
+}
+
+// CFL candidate of one cell: min over active kernel axes of dx/(|v| + c).
+template <int NDIM>
+__device__ __forceinline__ double cfl_candidate(const Geo& g, const double (&w)[NDIM + 2]) {
+    const double cs = dsqrt(g.gamma * w[NDIM + 1] / w[0]);
+    double best = g.dx[0] / (dabs(w[1]) + cs);
+    if (NDIM == 3) {
+        const double c1 = g.dx[1] / (dabs(w[2]) + cs);
+        best = c1 < best ? c1 : best;
+    }
+    if (NDIM >= 2) {
+        const double c2 = g.dx[2] / (dabs(w[NDIM]) + cs);
+        best = c2 < best ? c2 : best;
+    }
+    return best;
+}
+
+__device__ __forceinline__ double device_dt(const Ctrl* c, double t_end) {
+    double dt = c->dt_raw;
+    if (t_end > 0.0) {
+        const double rem = t_end - c->t;
+        if (dt >= rem) dt = rem;
+    }
+    return dt > 0.0 ? dt : 0.0;
+}
+
+// Work-groups are dispatched round-robin over the 8 XCDs; hand each XCD a
+// contiguous range of tiles so neighbouring tiles share one L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+    constexpr int X = 8;
+    const int q = nb / X, r = nb % X;
+    const int x = bid % X, i = bid / X;
+    return x * q + (x < r ? x : r) + i;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// ------------------------------------------------------------- stage kernel
+
+template <int NDIM, typename R, int MODE, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
+    constexpr int NC = NDIM + 2;
+    constexpr bool HY = (NDIM == 3);
+    constexpr bool HZ = (NDIM >= 2);
+    constexpr int NT = TX * TY;
+    static_assert(HY || TY == 1, "tile rows need a second in-plane axis");
+
+    const Geo& g = a.geo;
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    const long long N = g.ncells;
+
+    int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int tix = b % a.tiles_x;
+    b /= a.tiles_x;
+    const int tiy = b % a.tiles_y;
+    b /= a.tiles_y;
+    const int x0 = tix * TX, y0 = tiy * TY, z0 = b * a.kz;
+    const int z1 = min(z0 + a.kz, n2);
+    const int ax = min(TX, n0 - x0);
+    const int ay = min(TY, n1 - y0);
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly = tid / TX;
+    const bool act = lx < ax && ly < ay;
+    const int gx = x0 + lx, gy = y0 + ly;
+
+    const double dt = a.use_device_dt ? device_dt(a.ctrl, a.t_end) : a.dt_host;
+    const double lam0 = dt / g.dx[0];
+    const double lam1 = dt / g.dx[1];
+    const double lam2 = dt / g.dx[2];
+    const R gr = (R)g.gamma;
+
+    __shared__ R sW[NC][TY + 4][TX + 4];
+    __shared__ R sFx[NC][TY][TX + 1];
+    __shared__ R sFy[HY ? NC : 1][HY ? TY + 1 : 1][TX];
+
+    bool bad = false;
+    double dtmin = __longlong_as_double((long long)kInfBits);
+    R wq[5][NC];
+    R fzl[NC];
+    if (HZ && act) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) load_w<NDIM, R>(g, a.in, gx, gy, z0 - 2 + s, wq[s], bad);
+        face_flux<NDIM, 2, R>(gr, wq[0], wq[1], wq[2], wq[3], fzl);
+    }
+
+    for (int k = z0; k < z1; ++k) {
+        R wc[NC];
+        if (act) {
+            if (HZ) {
+                load_w<NDIM, R>(g, a.in, gx, gy, k + 2, wq[4], bad);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) wc[c] = wq[2][c];
+            } else {
+                load_w<NDIM, R>(g, a.in, gx, gy, k, wc, bad);
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sW[c][ly + 2][lx + 2] = wc[c];
+        }
+        // halo of plane k: two columns left/right of each active row, two
+        // rows below/above each active column
+        {
+            const int nhx = 4 * ay;
+            const int nhy = HY ? 4 * ax : 0;
+            for (int h = tid; h < nhx + nhy; h += NT) {
+                int hx, hy;
+                if (h < nhx) {
+                    const int q = h & 3;
+                    hy = h >> 2;
+                    hx = q < 2 ? q - 2 : ax + (q - 2);
+                } else {
+                    const int h2 = h - nhx, q = h2 & 3;
+                    hx = h2 >> 2;
+                    hy = q < 2 ? q - 2 : ay + (q - 2);
+                }
+                R wh[NC];
+                load_w<NDIM, R>(g, a.in, x0 + hx, y0 + hy, k, wh, bad);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) sW[c][hy + 2][hx + 2] = wh[c];
+            }
+        }
+        __syncthreads();
+
+        // x faces: face i separates tile columns i-1 and i; LDS columns i..i+3
+        if (ly < ay && lx <= ax) {
+            R w0[NC], w1[NC], w2[NC], w3[NC], F[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                w0[c] = sW[c][ly + 2][lx];
+                w1[c] = sW[c][ly + 2][lx + 1];
+                w2[c] = sW[c][ly + 2][lx + 2];
+                w3[c] = sW[c][ly + 2][lx + 3];
+            }
+            face_flux<NDIM, 0, R>(gr, w0, w1, w2, w3, F);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sFx[c][ly][lx] = F[c];
+        }
+        if (HY && lx < ax && ly <= ay) {
+            R w0[NC], w1[NC], w2[NC], w3[NC], F[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                w0[c] = sW[c][ly][lx + 2];
+                w1[c] = sW[c][ly + 1][lx + 2];
+                w2[c] = sW[c][ly + 2][lx + 2];
+                w3[c] = sW[c][ly + 3][lx + 2];
+            }
+            face_flux<NDIM, 1, R>(gr, w0, w1, w2, w3, F);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sFy[HY ? c : 0][HY ? ly : 0][lx] = F[c];
+        }
+        // faces past the last thread column / row of a full tile
+        {
+            const int ex = (ax == TX) ? ay : 0;
+            const int ey = (HY && ay == TY) ? ax : 0;
+            for (int e = tid; e < ex + ey; e += NT) {
+                R w0[NC], w1[NC], w2[NC], w3[NC], F[NC];
+                if (e < ex) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        w0[c] = sW[c][e + 2][TX];
+                        w1[c] = sW[c][e + 2][TX + 1];
+                        w2[c] = sW[c][e + 2][TX + 2];
+                        w3[c] = sW[c][e + 2][TX + 3];
+                    }
+                    face_flux<NDIM, 0, R>(gr, w0, w1, w2, w3, F);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) sFx[c][e][TX] = F[c];
+                } else if (HY) {
+                    const int col = e - ex;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        w0[c] = sW[c][TY][col + 2];
+                        w1[c] = sW[c][TY + 1][col + 2];
+                        w2[c] = sW[c][TY + 2][col + 2];
+                        w3[c] = sW[c][TY + 3][col + 2];
+                    }
+                    face_flux<NDIM, 1, R>(gr, w0, w1, w2, w3, F);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) sFy[HY ? c : 0][HY ? TY : 0][col] = F[c];
+                }
+            }
+        }
+        R fzh[NC];
+        if (HZ && act) face_flux<NDIM, 2, R>(gr, wq[1], wq[2], wq[3], wq[4], fzh);
+        __syncthreads();
+
+        if (act) {
+            const long long cell = ((long long)k * n1 + gy) * n0 + gx;
+            double unew[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                double acc = 0.0;
+                acc = acc + lam0 * ((double)sFx[c][ly][lx] - (double)sFx[c][ly][lx + 1]);
+                if (HY)
+                    acc = acc + lam1 * ((double)sFy[HY ? c : 0][HY ? ly : 0][lx] -
+                                        (double)sFy[HY ? c : 0][HY ? ly + 1 : 0][lx]);
+                if (HZ) acc = acc + lam2 * ((double)fzl[c] - (double)fzh[c]);
+                const long long o = c * N + cell;
+                double r;
+                if (MODE == MODE_RHS)
+                    r = acc;
+                else if (MODE == MODE_STAGE1)
+                    r = a.in[o] + acc;
+                else
+                    r = 0.5 * a.base[o] + 0.5 * (a.in[o] + acc);
+                a.out[o] = r;
+                unew[c] = r;
+            }
+            if (MODE == MODE_STAGE2 && a.want_dt) {
+                double w[NC];
+                bad |= !cons_to_prim<NDIM>(g.gamma, unew, w);
+                const double cand = cfl_candidate<NDIM>(g, w);
+                dtmin = cand < dtmin ? cand : dtmin;
+            }
+        }
+        if (HZ) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) fzl[c] = fzh[c];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) wq[s][c] = wq[s + 1][c];
+        }
+    }
+
+    if (bad) atomicOr(&a.ctrl->flags, FLAG_NONPHYSICAL);
+    if (MODE == MODE_STAGE2 && a.want_dt) {
+        __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
+        dtmin = wave_min(dtmin);
+        if ((tid & 63) == 0) red[tid >> 6] = dtmin;
+        __syncthreads();
+        if (tid == 0) {
+            double m = red[0];
+            for (int i = 1; i < NT / 64; ++i) m = red[i] < m ? red[i] : m;
+            atomicMin(&a.ctrl->dtmin_bits, (unsigned long long)__double_as_longlong(m));
+        }
+    }
+}
+
+// ------------------------------------------------------------- small kernels
+
+template <int NDIM>
+__global__ __launch_bounds__(256) void dt_kernel(Geo g, const double* __restrict__ U, Ctrl* ctrl) {
+    constexpr int NC = NDIM + 2;
+    double best = __longlong_as_double((long long)kInfBits);
+    bool bad = false;
+    for (long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x; cell < g.ncells;
+         cell += (long long)gridDim.x * blockDim.x) {
+        double u[NC], w[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) u[c] = U[c * g.ncells + cell];
+        bad |= !cons_to_prim<NDIM>(g.gamma, u, w);
+        const double cand = cfl_candidate<NDIM>(g, w);
+        best = cand < best ? cand : best;
+    }
+    if (bad) atomicOr(&ctrl->flags, FLAG_NONPHYSICAL);
+    __shared__ double red[4];
+    best = wave_min(best);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int i = 1; i < 4; ++i) m = red[i] < m ? red[i] : m;
+        atomicMin(&ctrl->dtmin_bits, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+__global__ void ctrl_kernel(Ctrl* c, int op, double a0, double a1, double cfl) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    switch (op) {
+        case CTRL_INIT:
+            c->t = a0;
+            c->steps = 0;
+            c->flags = 0;
+            c->dt_valid = 0;
+            c->dt_raw = 0.0;
+            c->dtmin_bits = kInfBits;
+            break;
+        case CTRL_RESET_MIN:
+            c->dtmin_bits = kInfBits;
+            break;
+        case CTRL_FINALIZE_DT:
+            c->dt_raw = cfl * __longlong_as_double((long long)c->dtmin_bits);
+            c->dt_valid = 1;
+            c->dtmin_bits = kInfBits;
+            break;
+        case CTRL_FINALIZE_STEP: {
+            const double t_end = a1;
+            const double dt = device_dt(c, t_end);
+            const bool last = t_end > 0.0 && c->dt_raw >= t_end - c->t;
+            if (dt > 0.0) {
+                c->t = last ? t_end : c->t + dt;
+                c->steps += 1;
+            }
+            c->dt_raw = cfl * __longlong_as_double((long long)c->dtmin_bits);
+            c->dt_valid = 1;
+            c->dtmin_bits = kInfBits;
+            break;
+        }
+        case CTRL_ADVANCE_T:
+            c->t = c->t + a0;
+            c->steps += 1;
+            c->dt_valid = 0;
+            break;
+        default:
+            break;
+    }
+}
+
+// Neumaier-compensated accumulator combined pairwise in a fixed tree.
+struct Comp {
+    double s, c;
+};
+__device__ __forceinline__ Comp comp_add(Comp a, double x) {
+    const double t = a.s + x;
+    if (dabs(a.s) >= dabs(x))
+        a.c += (a.s - t) + x;
+    else
+        a.c += (x - t) + a.s;
+    a.s = t;
+    return a;
+}
+__device__ __forceinline__ Comp comp_merge(Comp a, Comp b) {
+    Comp r = comp_add(a, b.s);
+    r.c += b.c;
+    return r;
+}
+
+template <int NC>
+__global__ __launch_bounds__(256) void totals_pass1(long long ncells, const double* __restrict__ U,
+                                                    double* __restrict__ parts) {
+    __shared__ double ss[NC][256], sc[NC][256];
+    const long long per = (ncells + gridDim.x - 1) / gridDim.x;
+    const long long lo = (long long)blockIdx.x * per;
+    const long long hi = lo + per < ncells ? lo + per : ncells;
+    Comp acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = Comp{0.0, 0.0};
+    for (long long i = lo + threadIdx.x; i < hi; i += 256)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = comp_add(acc[c], U[c * ncells + i]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        ss[c][threadIdx.x] = acc[c].s;
+        sc[c][threadIdx.x] = acc[c].c;
+    }
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                Comp r = comp_merge(Comp{ss[c][threadIdx.x], sc[c][threadIdx.x]},
+                                    Comp{ss[c][threadIdx.x + w], sc[c][threadIdx.x + w]});
+                ss[c][threadIdx.x] = r.s;
+                sc[c][threadIdx.x] = r.c;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            parts[(blockIdx.x * NC + c) * 2] = ss[c][0];
+            parts[(blockIdx.x * NC + c) * 2 + 1] = sc[c][0];
+        }
+}
+
+template <int NC>
+__global__ __launch_bounds__(256) void totals_pass2(int nparts, const double* __restrict__ parts,
+                                                    Ctrl* ctrl) {
+    __shared__ double ss[NC][256], sc[NC][256];
+    Comp acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = Comp{0.0, 0.0};
+    for (int p = threadIdx.x; p < nparts; p += 256)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            acc[c] = comp_merge(acc[c], Comp{parts[(p * NC + c) * 2], parts[(p * NC + c) * 2 + 1]});
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        ss[c][threadIdx.x] = acc[c].s;
+        sc[c][threadIdx.x] = acc[c].c;
+    }
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                Comp r = comp_merge(Comp{ss[c][threadIdx.x], sc[c][threadIdx.x]},
+                                    Comp{ss[c][threadIdx.x + w], sc[c][threadIdx.x + w]});
+                ss[c][threadIdx.x] = r.s;
+                sc[c][threadIdx.x] = r.c;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            ctrl->sums[2 * c] = ss[c][0];
+            ctrl->sums[2 * c + 1] = sc[c][0];
+        }
+}
+
+// m_d = rho v_d, E = p/(gamma - 1) + (1/2) sum_d m_d v_d
+template <int NDIM>
+__global__ __launch_bounds__(256) void prim_to_cons_kernel(Geo g, const double* __restrict__ W,
+                                                           double* __restrict__ U) {
+    constexpr int NC = NDIM + 2;
+    for (long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x; cell < g.ncells;
+         cell += (long long)gridDim.x * blockDim.x) {
+        const double rho = W[cell];
+        double ke2 = 0.0;
+        U[cell] = rho;
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) {
+            const double v = W[(1 + d) * g.ncells + cell];
+            const double mom = rho * v;
+            U[(1 + d) * g.ncells + cell] = mom;
+            ke2 = ke2 + mom * v;
+        }
+        U[(NC - 1) * g.ncells + cell] = W[(NC - 1) * g.ncells + cell] / (g.gamma - 1.0) + 0.5 * ke2;
+    }
+}
+
+// Padded primitive export: physical padded layout [c][K][J][I] with two ghost
+// layers on every active physical axis, corners zero.
+template <int NDIM, typename R>
+__global__ __launch_bounds__(256) void padded_prim_kernel(Geo g, const double* __restrict__ U,
+                                                          double* __restrict__ Wp, Ctrl* ctrl) {
+    constexpr int NC = NDIM + 2;
+    // physical extents: axis p of NDIM -> kernel axis (3-D identity; 2-D y is kernel z)
+    int nph[3] = {g.n[0], NDIM == 3 ? g.n[1] : (NDIM == 2 ? g.n[2] : 1), NDIM == 3 ? g.n[2] : 1};
+    int P[3];
+    for (int d = 0; d < 3; ++d) P[d] = nph[d] + (d < NDIM ? 4 : 0);
+    const long long total = (long long)P[0] * P[1] * P[2];
+    bool bad = false;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int I = (int)(q % P[0]);
+        const int J = (int)((q / P[0]) % P[1]);
+        const int K = (int)(q / ((long long)P[0] * P[1]));
+        int pc[3] = {I - (NDIM >= 1 ? 2 : 0), J - (NDIM >= 2 ? 2 : 0), K - (NDIM >= 3 ? 2 : 0)};
+        int outside = 0;
+        for (int d = 0; d < NDIM; ++d) outside += (pc[d] < 0 || pc[d] >= nph[d]);
+        double out[NC];
+        if (outside > 1) {
+            for (int c = 0; c < NC; ++c) out[c] = 0.0;
+        } else {
+            R w[NC];
+            int kx = pc[0], ky = NDIM == 3 ? pc[1] : 0, kzc = NDIM == 3 ? pc[2] : (NDIM == 2 ? pc[1] : 0);
+            load_w<NDIM, R>(g, U, kx, ky, kzc, w, bad);
+            for (int c = 0; c < NC; ++c) out[c] = (double)w[c];
+        }
+        for (int c = 0; c < NC; ++c) Wp[c * total + q] = out[c];
+    }
+    if (bad) atomicOr(&ctrl->flags, FLAG_NONPHYSICAL);
+}
+
+template <typename R, int NT>
+__global__ __launch_bounds__(256) void riemann_kernel(double gamma, long long n,
+                                                      const double* __restrict__ WL,
+                                                      const double* __restrict__ WR,
+                                                      double* __restrict__ F) {
+    constexpr int NC = NT + 3;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        R L[NC], Rr[NC], Fo[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            L[c] = (R)WL[c * n + i];
+            Rr[c] = (R)WR[c * n + i];
+        }
+        hllc<R, NT>((R)gamma, L, Rr, Fo);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) F[c * n + i] = (double)Fo[c];
+    }
+}
+
+int grid_for(long long work, int block, int cap) {
+    long long gb = (work + block - 1) / block;
+    if (gb < 1) gb = 1;
+    return (int)(gb < cap ? gb : cap);
+}
+
+template <int NDIM, typename R, int MODE, int TX, int TY>
+hipError_t launch_stage_t(StageArgs a, hipStream_t s) {
+    const int nb = a.tiles_x * a.tiles_y * a.chunks_z;
+    hipLaunchKernelGGL((stage_kernel<NDIM, R, MODE, TX, TY>), dim3(nb), dim3(TX * TY), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int NDIM, typename R, int MODE>
+hipError_t launch_stage_tile(const Tile& t, StageArgs a, hipStream_t s) {
+    if constexpr (NDIM == 3) {
+        if (t.tx == 32 && t.ty == 8) return launch_stage_t<NDIM, R, MODE, 32, 8>(a, s);
+        if (t.tx == 64 && t.ty == 4) return launch_stage_t<NDIM, R, MODE, 64, 4>(a, s);
+        if (t.tx == 16 && t.ty == 16) return launch_stage_t<NDIM, R, MODE, 16, 16>(a, s);
+        return hipErrorInvalidValue;
+    } else {
+        if (t.ty != 1) return hipErrorInvalidValue;
+        if (t.tx == 64) return launch_stage_t<NDIM, R, MODE, 64, 1>(a, s);
+        if (t.tx == 128) return launch_stage_t<NDIM, R, MODE, 128, 1>(a, s);
+        if (t.tx == 256) return launch_stage_t<NDIM, R, MODE, 256, 1>(a, s);
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int NDIM, typename R>
+hipError_t launch_stage_mode(int mode, const Tile& t, StageArgs a, hipStream_t s) {
+    switch (mode) {
+        case MODE_RHS: return launch_stage_tile<NDIM, R, MODE_RHS>(t, a, s);
+        case MODE_STAGE1: return launch_stage_tile<NDIM, R, MODE_STAGE1>(t, a, s);
+        case MODE_STAGE2: return launch_stage_tile<NDIM, R, MODE_STAGE2>(t, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int NDIM>
+hipError_t launch_stage_prec(int precision, int mode, const Tile& t, StageArgs a, hipStream_t s) {
+    if (precision == 0) return launch_stage_mode<NDIM, double>(mode, t, a, s);
+    return launch_stage_mode<NDIM, float>(mode, t, a, s);
+}
+
+}  // namespace
+
+Tile default_tile(const Geo& g, int precision) {
+    (void)precision;
+    Tile t;
+    if (g.ndim == 3) {
+        t.tx = 32;
+        t.ty = 8;
+        t.kz = 32;
+    } else if (g.ndim == 2) {
+        t.tx = g.n[0] >= 256 ? 256 : (g.n[0] >= 128 ? 128 : 64);
+        t.ty = 1;
+        t.kz = 32;
+    } else {
+        t.tx = 64;
+        t.ty = 1;
+        t.kz = 1;
+    }
+    return t;
+}
+
+hipError_t launch_stage(int precision, int mode, const Tile& t, StageArgs a, hipStream_t s) {
+    const Geo& g = a.geo;
+    a.tiles_x = (g.n[0] + t.tx - 1) / t.tx;
+    a.tiles_y = (g.n[1] + t.ty - 1) / t.ty;
+    a.kz = t.kz < 1 ? 1 : (t.kz > g.n[2] ? g.n[2] : t.kz);
+    a.chunks_z = (g.n[2] + a.kz - 1) / a.kz;
+    switch (g.ndim) {
+        case 1: return launch_stage_prec<1>(precision, mode, t, a, s);
+        case 2: return launch_stage_prec<2>(precision, mode, t, a, s);
+        case 3: return launch_stage_prec<3>(precision, mode, t, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_dt(const Geo& g, const double* U, Ctrl* ctrl, hipStream_t s) {
+    const int nb = grid_for(g.ncells, 256, 2048);
+    switch (g.ndim) {
+        case 1: hipLaunchKernelGGL(dt_kernel<1>, dim3(nb), dim3(256), 0, s, g, U, ctrl); break;
+        case 2: hipLaunchKernelGGL(dt_kernel<2>, dim3(nb), dim3(256), 0, s, g, U, ctrl); break;
+        case 3: hipLaunchKernelGGL(dt_kernel<3>, dim3(nb), dim3(256), 0, s, g, U, ctrl); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ctrl(Ctrl* c, int op, double a0, double a1, double cfl, hipStream_t s) {
+    hipLaunchKernelGGL(ctrl_kernel, dim3(1), dim3(64), 0, s, c, op, a0, a1, cfl);
+    return hipGetLastError();
+}
+
+hipError_t launch_totals(const Geo& g, const double* U, double* parts, int nparts, Ctrl* ctrl,
+                         hipStream_t s) {
+    const int nb = grid_for(g.ncells, 256, nparts);
+    const int NC = g.ndim + 2;
+    switch (NC) {
+        case 3:
+            hipLaunchKernelGGL(totals_pass1<3>, dim3(nb), dim3(256), 0, s, g.ncells, U, parts);
+            hipLaunchKernelGGL(totals_pass2<3>, dim3(1), dim3(256), 0, s, nb, parts, ctrl);
+            break;
+        case 4:
+            hipLaunchKernelGGL(totals_pass1<4>, dim3(nb), dim3(256), 0, s, g.ncells, U, parts);
+            hipLaunchKernelGGL(totals_pass2<4>, dim3(1), dim3(256), 0, s, nb, parts, ctrl);
+            break;
+        case 5:
+            hipLaunchKernelGGL(totals_pass1<5>, dim3(nb), dim3(256), 0, s, g.ncells, U, parts);
+            hipLaunchKernelGGL(totals_pass2<5>, dim3(1), dim3(256), 0, s, nb, parts, ctrl);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_prim_to_cons(const Geo& g, const double* W, double* U, hipStream_t s) {
+    const int nb = grid_for(g.ncells, 256, 4096);
+    switch (g.ndim) {
+        case 1: hipLaunchKernelGGL(prim_to_cons_kernel<1>, dim3(nb), dim3(256), 0, s, g, W, U); break;
+        case 2: hipLaunchKernelGGL(prim_to_cons_kernel<2>, dim3(nb), dim3(256), 0, s, g, W, U); break;
+        case 3: hipLaunchKernelGGL(prim_to_cons_kernel<3>, dim3(nb), dim3(256), 0, s, g, W, U); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_padded_prim(const Geo& g, int precision, const double* U, double* Wp, Ctrl* ctrl,
+                              hipStream_t s) {
+    const int nb = grid_for(g.ncells * 2 + 4096, 256, 4096);
+#define PP(ND, RT) hipLaunchKernelGGL((padded_prim_kernel<ND, RT>), dim3(nb), dim3(256), 0, s, g, U, Wp, ctrl)
+    if (precision == 0) {
+        switch (g.ndim) {
+            case 1: PP(1, double); break;
+            case 2: PP(2, double); break;
+            case 3: PP(3, double); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (g.ndim) {
+            case 1: PP(1, float); break;
+            case 2: PP(2, float); break;
+            case 3: PP(3, float); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+#undef PP
+    return hipGetLastError();
+}
+
+hipError_t launch_riemann(int precision, int ntan, double gamma, long long n, const double* WL,
+                          const double* WR, double* F, hipStream_t s) {
+    const int nb = grid_for(n, 256, 4096);
+#define RK(RT, NTAN) \
+    hipLaunchKernelGGL((riemann_kernel<RT, NTAN>), dim3(nb), dim3(256), 0, s, gamma, n, WL, WR, F)
+    if (precision == 0) {
+        switch (ntan) {
+            case 0: RK(double, 0); break;
+            case 1: RK(double, 1); break;
+            case 2: RK(double, 2); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (ntan) {
+            case 0: RK(float, 0); break;
+            case 1: RK(float, 1); break;
+            case 2: RK(float, 2); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+#undef RK
+    return hipGetLastError();
+}
+
+}  // namespace hydro

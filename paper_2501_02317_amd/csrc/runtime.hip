@@ -1,0 +1,462 @@
+// Host runtime behind include/hydro.h: configuration checks, workspace
+// carving, stream-ordered launches and the device-resident time step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "hydro.h"
+#include "hydro_internal.h"
+
+using namespace hydro;
+
+struct hydro_ctx {
+    hydro_config cfg;
+    Geo geo;
+    Tile tile;
+    hipStream_t stream;
+    int ncomp;
+    double dV;
+    double* U;      // current state U^n
+    double* U1;     // predictor U1 / scratch
+    double* parts;  // totals partials
+    Ctrl* ctrl;
+    Ctrl* host_ctrl;  // pinned mirror for reads
+    bool broken;
+    // optional event timing of the stage launches
+    int prof_cap;
+    int prof_n[2];
+    hipEvent_t* prof_ev[2];  // [stage][2 * launch + {0: start, 1: stop}]
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool config_ok(const hydro_config* c) {
+    if (!c) return false;
+    if (c->ndim < 1 || c->ndim > 3) return false;
+    if (!(c->gamma > 1.0) || !std::isfinite(c->gamma)) return false;
+    if (!(c->cfl > 0.0) || !(c->cfl <= 1.0)) return false;
+    if (c->precision != HYDRO_FP64 && c->precision != HYDRO_MIXED) return false;
+    long long cells = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (d < c->ndim) {
+            if (c->n[d] < 1) return false;
+            if (!(c->hi[d] > c->lo[d]) || !std::isfinite(c->hi[d] - c->lo[d])) return false;
+            for (int s = 0; s < 2; ++s)
+                if (c->bc[d][s] < HYDRO_BC_PERIODIC || c->bc[d][s] > HYDRO_BC_REFLECT) return false;
+            const bool p0 = c->bc[d][0] == HYDRO_BC_PERIODIC, p1 = c->bc[d][1] == HYDRO_BC_PERIODIC;
+            if (p0 != p1) return false;
+            // periodic and reflecting ghosts read two distinct interior cells
+            if ((p0 || c->bc[d][0] == HYDRO_BC_REFLECT || c->bc[d][1] == HYDRO_BC_REFLECT) &&
+                c->n[d] < 2)
+                return false;
+        } else if (c->n[d] != 1) {
+            return false;
+        }
+        cells *= c->n[d];
+        if (cells > (1ll << 40)) return false;
+    }
+    return true;
+}
+
+long long ncells_of(const hydro_config* c) { return (long long)c->n[0] * c->n[1] * c->n[2]; }
+
+size_t state_bytes(const hydro_config* c) {
+    return align_up((size_t)(c->ndim + 2) * (size_t)ncells_of(c) * sizeof(double));
+}
+
+// Kernel-axis geometry (see hydro_internal.h).
+Geo make_geo(const hydro_config* c) {
+    Geo g;
+    std::memset(&g, 0, sizeof(g));
+    g.ndim = c->ndim;
+    g.gamma = c->gamma;
+    g.cfl = c->cfl;
+    g.ncells = ncells_of(c);
+    double dx[3];
+    for (int d = 0; d < 3; ++d) dx[d] = d < c->ndim ? (c->hi[d] - c->lo[d]) / c->n[d] : 1.0;
+    int map[3];  // kernel axis -> physical axis (-1: inactive)
+    if (c->ndim == 3) {
+        map[0] = 0; map[1] = 1; map[2] = 2;
+    } else if (c->ndim == 2) {
+        map[0] = 0; map[1] = -1; map[2] = 1;
+    } else {
+        map[0] = 0; map[1] = -1; map[2] = -1;
+    }
+    for (int k = 0; k < 3; ++k) {
+        if (map[k] >= 0) {
+            g.n[k] = c->n[map[k]];
+            g.dx[k] = dx[map[k]];
+            g.bc[k][0] = c->bc[map[k]][0];
+            g.bc[k][1] = c->bc[map[k]][1];
+        } else {
+            g.n[k] = 1;
+            g.dx[k] = 1.0;
+            g.bc[k][0] = g.bc[k][1] = HYDRO_BC_PERIODIC;
+        }
+    }
+    return g;
+}
+
+int fail(hydro_t h, hipError_t e) {
+    if (e == hipSuccess) return HYDRO_OK;
+    if (h) h->broken = true;
+    return HYDRO_E_DEVICE;
+}
+
+int read_ctrl(hydro_t h) {
+    hipError_t e = hipMemcpyAsync(h->host_ctrl, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(h, e);
+    if (h->host_ctrl->flags & FLAG_NONPHYSICAL) return HYDRO_E_NONPHYSICAL;
+    return HYDRO_OK;
+}
+
+int usable(hydro_t h) {
+    if (!h) return HYDRO_E_INVAL;
+    if (h->broken) return HYDRO_E_STATE;
+    return HYDRO_OK;
+}
+
+StageArgs stage_args(hydro_t h) {
+    StageArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.ctrl = h->ctrl;
+    a.geo = h->geo;
+    return a;
+}
+
+// Launch one stage, bracketed by events when profiling is on.
+hipError_t timed_stage(hydro_t h, int mode, const StageArgs& a) {
+    const int st = mode == MODE_STAGE2 ? 1 : 0;
+    const bool rec = h->prof_cap > 0 && h->prof_n[st] < h->prof_cap;
+    hipError_t e = hipSuccess;
+    if (rec) e = hipEventRecord(h->prof_ev[st][2 * h->prof_n[st]], h->stream);
+    if (e == hipSuccess) e = launch_stage(h->cfg.precision, mode, h->tile, a, h->stream);
+    if (rec && e == hipSuccess) {
+        e = hipEventRecord(h->prof_ev[st][2 * h->prof_n[st] + 1], h->stream);
+        h->prof_n[st] += 1;
+    }
+    return e;
+}
+
+// One Heun step: stage 1 then stage 2 in place, dt either from the host or
+// from the device control block.
+hipError_t enqueue_step(hydro_t h, bool device_dt, double dt, double t_end) {
+    StageArgs a = stage_args(h);
+    a.use_device_dt = device_dt ? 1 : 0;
+    a.dt_host = dt;
+    a.t_end = t_end;
+    a.in = h->U;
+    a.out = h->U1;
+    hipError_t e = timed_stage(h, MODE_STAGE1, a);
+    if (e != hipSuccess) return e;
+    a.in = h->U1;
+    a.base = h->U;
+    a.out = h->U;
+    a.want_dt = device_dt ? 1 : 0;
+    e = timed_stage(h, MODE_STAGE2, a);
+    if (e != hipSuccess) return e;
+    if (device_dt) return launch_ctrl(h->ctrl, CTRL_FINALIZE_STEP, 0.0, t_end, h->cfg.cfl, h->stream);
+    return launch_ctrl(h->ctrl, CTRL_ADVANCE_T, dt, 0.0, h->cfg.cfl, h->stream);
+}
+
+hipError_t enqueue_dt(hydro_t h) {
+    hipError_t e = launch_ctrl(h->ctrl, CTRL_RESET_MIN, 0.0, 0.0, h->cfg.cfl, h->stream);
+    if (e == hipSuccess) e = launch_dt(h->geo, h->U, h->ctrl, h->stream);
+    if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_FINALIZE_DT, 0.0, 0.0, h->cfg.cfl, h->stream);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hydro_workspace_bytes(const hydro_config* cfg) {
+    if (!config_ok(cfg)) return 0;
+    return 2 * state_bytes(cfg) + align_up(sizeof(Ctrl)) +
+           align_up((size_t)kTotalsParts * kMaxComp * 2 * sizeof(double));
+}
+
+int hydro_create(const hydro_config* cfg, void* d_workspace, size_t nbytes, void* hip_stream,
+                 hydro_t* out) {
+    if (!out || !config_ok(cfg) || !d_workspace) return HYDRO_E_INVAL;
+    if (((uintptr_t)d_workspace) % kAlign != 0) return HYDRO_E_INVAL;
+    if (nbytes < hydro_workspace_bytes(cfg)) return HYDRO_E_INVAL;
+    hydro_ctx* h = new (std::nothrow) hydro_ctx;
+    if (!h) return HYDRO_E_NOMEM;
+    std::memset(h, 0, sizeof(*h));
+    h->cfg = *cfg;
+    h->geo = make_geo(cfg);
+    h->tile = default_tile(h->geo, cfg->precision);
+    h->stream = (hipStream_t)hip_stream;
+    h->ncomp = cfg->ndim + 2;
+    h->dV = 1.0;
+    for (int d = 0; d < cfg->ndim; ++d) h->dV *= (cfg->hi[d] - cfg->lo[d]) / cfg->n[d];
+    char* p = (char*)d_workspace;
+    const size_t sb = state_bytes(cfg);
+    h->U = (double*)p;
+    p += sb;
+    h->U1 = (double*)p;
+    p += sb;
+    h->ctrl = (Ctrl*)p;
+    p += align_up(sizeof(Ctrl));
+    h->parts = (double*)p;
+    if (hipHostMalloc((void**)&h->host_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+        delete h;
+        return HYDRO_E_NOMEM;
+    }
+    hipError_t e = hipMemsetAsync(h->U, 0, 2 * sb, h->stream);
+    if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_INIT, 0.0, 0.0, cfg->cfl, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        (void)hipHostFree(h->host_ctrl);
+        delete h;
+        return HYDRO_E_DEVICE;
+    }
+    *out = h;
+    return HYDRO_OK;
+}
+
+int hydro_set_state(hydro_t h, const double* U_host) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!U_host) return HYDRO_E_INVAL;
+    const size_t bytes = (size_t)h->ncomp * h->geo.ncells * sizeof(double);
+    hipError_t e = hipMemcpyAsync(h->U, U_host, bytes, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_INIT, 0.0, 0.0, h->cfg.cfl, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return fail(h, e);
+}
+
+int hydro_set_primitive(hydro_t h, const double* W_host) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!W_host) return HYDRO_E_INVAL;
+    const size_t bytes = (size_t)h->ncomp * h->geo.ncells * sizeof(double);
+    hipError_t e = hipMemcpyAsync(h->U1, W_host, bytes, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = launch_prim_to_cons(h->geo, h->U1, h->U, h->stream);
+    if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_INIT, 0.0, 0.0, h->cfg.cfl, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return fail(h, e);
+}
+
+int hydro_get_state(hydro_t h, double* U_host) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!U_host) return HYDRO_E_INVAL;
+    const size_t bytes = (size_t)h->ncomp * h->geo.ncells * sizeof(double);
+    hipError_t e = hipMemcpyAsync(U_host, h->U, bytes, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return fail(h, e);
+}
+
+int hydro_state_device(hydro_t h, const double** d_U) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!d_U) return HYDRO_E_INVAL;
+    *d_U = h->U;
+    return HYDRO_OK;
+}
+
+int hydro_cfl_dt(hydro_t h, double* dt) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!dt) return HYDRO_E_INVAL;
+    hipError_t e = enqueue_dt(h);
+    if (e != hipSuccess) return fail(h, e);
+    rc = read_ctrl(h);
+    if (rc) return rc;
+    *dt = h->host_ctrl->dt_raw;
+    return HYDRO_OK;
+}
+
+int hydro_step(hydro_t h, double dt) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return HYDRO_E_INVAL;
+    return fail(h, enqueue_step(h, false, dt, 0.0));
+}
+
+int hydro_step_auto(hydro_t h, int nsteps, double t_end) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (nsteps < 0 || !(t_end >= 0.0) || !std::isfinite(t_end)) return HYDRO_E_INVAL;
+    if (nsteps == 0) return HYDRO_OK;
+    // The first dt of a run comes from a standalone reduction over the
+    // current state; every later dt from the previous step's epilogue.
+    hipError_t e = enqueue_dt(h);
+    for (int s = 0; s < nsteps && e == hipSuccess; ++s) e = enqueue_step(h, true, 0.0, t_end);
+    return fail(h, e);
+}
+
+int hydro_conserved_totals(hydro_t h, double* totals) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!totals) return HYDRO_E_INVAL;
+    hipError_t e = launch_totals(h->geo, h->U, h->parts, kTotalsParts, h->ctrl, h->stream);
+    if (e != hipSuccess) return fail(h, e);
+    rc = read_ctrl(h);
+    if (rc && rc != HYDRO_E_NONPHYSICAL) return rc;
+    for (int c = 0; c < h->ncomp; ++c)
+        totals[c] = h->dV * (h->host_ctrl->sums[2 * c] + h->host_ctrl->sums[2 * c + 1]);
+    return rc;
+}
+
+int hydro_time(hydro_t h, double* t) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!t) return HYDRO_E_INVAL;
+    rc = read_ctrl(h);
+    if (rc && rc != HYDRO_E_NONPHYSICAL) return rc;
+    *t = h->host_ctrl->t;
+    return rc;
+}
+
+int hydro_steps_done(hydro_t h, int64_t* steps) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!steps) return HYDRO_E_INVAL;
+    rc = read_ctrl(h);
+    if (rc && rc != HYDRO_E_NONPHYSICAL) return rc;
+    *steps = (int64_t)h->host_ctrl->steps;
+    return rc;
+}
+
+int hydro_stage_rhs(hydro_t h, double dt, double* dU_host) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!dU_host || !(dt > 0.0) || !std::isfinite(dt)) return HYDRO_E_INVAL;
+    StageArgs a = stage_args(h);
+    a.dt_host = dt;
+    a.in = h->U;
+    a.out = h->U1;
+    hipError_t e = launch_stage(h->cfg.precision, MODE_RHS, h->tile, a, h->stream);
+    const size_t bytes = (size_t)h->ncomp * h->geo.ncells * sizeof(double);
+    if (e == hipSuccess) e = hipMemcpyAsync(dU_host, h->U1, bytes, hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return fail(h, e);
+    return read_ctrl(h);
+}
+
+int hydro_padded_primitive(hydro_t h, double* Wpad_host) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!Wpad_host) return HYDRO_E_INVAL;
+    size_t total = (size_t)h->ncomp;
+    for (int d = 0; d < 3; ++d) total *= (size_t)(h->cfg.n[d] + (d < h->cfg.ndim ? 4 : 0));
+    double* d_buf = nullptr;
+    hipError_t e = hipMallocAsync((void**)&d_buf, total * sizeof(double), h->stream);
+    if (e == hipSuccess) e = launch_padded_prim(h->geo, h->cfg.precision, h->U, d_buf, h->ctrl, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(Wpad_host, d_buf, total * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (d_buf) {
+        hipError_t e2 = hipFreeAsync(d_buf, h->stream);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return fail(h, e);
+    return read_ctrl(h);
+}
+
+namespace {
+void profile_free(hydro_t h) {
+    for (int st = 0; st < 2; ++st) {
+        if (!h->prof_ev[st]) continue;
+        for (int i = 0; i < 2 * h->prof_cap; ++i) (void)hipEventDestroy(h->prof_ev[st][i]);
+        delete[] h->prof_ev[st];
+        h->prof_ev[st] = nullptr;
+    }
+    h->prof_cap = 0;
+    h->prof_n[0] = h->prof_n[1] = 0;
+}
+}  // namespace
+
+int hydro_profile(hydro_t h, int max_launches) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (max_launches < 0 || max_launches > (1 << 20)) return HYDRO_E_INVAL;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(h, e);
+    profile_free(h);
+    if (max_launches == 0) return HYDRO_OK;
+    for (int st = 0; st < 2; ++st) {
+        h->prof_ev[st] = new (std::nothrow) hipEvent_t[2 * max_launches];
+        if (!h->prof_ev[st]) {
+            profile_free(h);
+            return HYDRO_E_NOMEM;
+        }
+        for (int i = 0; i < 2 * max_launches; ++i) {
+            e = hipEventCreate(&h->prof_ev[st][i]);
+            if (e != hipSuccess) {
+                for (int j = 0; j < i; ++j) (void)hipEventDestroy(h->prof_ev[st][j]);
+                delete[] h->prof_ev[st];
+                h->prof_ev[st] = nullptr;
+                profile_free(h);
+                return fail(h, e);
+            }
+        }
+    }
+    h->prof_cap = max_launches;
+    return HYDRO_OK;
+}
+
+int hydro_profile_read(hydro_t h, double* ms_stage1, double* ms_stage2, int64_t* launches) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!ms_stage1 || !ms_stage2 || !launches) return HYDRO_E_INVAL;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(h, e);
+    double tot[2] = {0.0, 0.0};
+    for (int st = 0; st < 2; ++st)
+        for (int i = 0; i < h->prof_n[st]; ++i) {
+            float ms = 0.0f;
+            e = hipEventElapsedTime(&ms, h->prof_ev[st][2 * i], h->prof_ev[st][2 * i + 1]);
+            if (e != hipSuccess) return fail(h, e);
+            tot[st] += ms;
+        }
+    *ms_stage1 = tot[0];
+    *ms_stage2 = tot[1];
+    launches[0] = h->prof_n[0];
+    launches[1] = h->prof_n[1];
+    h->prof_n[0] = h->prof_n[1] = 0;
+    return HYDRO_OK;
+}
+
+int hydro_destroy(hydro_t h) {
+    if (!h) return HYDRO_E_INVAL;
+    if (!h->broken) (void)hipStreamSynchronize(h->stream);
+    profile_free(h);
+    (void)hipHostFree(h->host_ctrl);
+    delete h;
+    return HYDRO_OK;
+}
+
+const char* hydro_strerror(int status) {
+    switch (status) {
+        case HYDRO_OK: return "ok";
+        case HYDRO_E_INVAL: return "invalid argument";
+        case HYDRO_E_NOMEM: return "out of host memory";
+        case HYDRO_E_DEVICE: return "HIP runtime error";
+        case HYDRO_E_NONPHYSICAL: return "non-physical state (rho <= 0, p <= 0 or non-finite)";
+        case HYDRO_E_STATE: return "handle unusable after an earlier device error";
+        default: return "unknown status";
+    }
+}
+
+int hydro_riemann_fluxes(int precision, int ntan, double gamma, int64_t nfaces, const double* d_WL,
+                         const double* d_WR, double* d_F, void* hip_stream) {
+    if (precision != HYDRO_FP64 && precision != HYDRO_MIXED) return HYDRO_E_INVAL;
+    if (ntan < 0 || ntan > 2 || nfaces < 0 || !(gamma > 1.0)) return HYDRO_E_INVAL;
+    if (nfaces == 0) return HYDRO_OK;
+    if (!d_WL || !d_WR || !d_F) return HYDRO_E_INVAL;
+    hipError_t e = launch_riemann(precision, ntan, gamma, (long long)nfaces, d_WL, d_WR, d_F,
+                                  (hipStream_t)hip_stream);
+    return e == hipSuccess ? HYDRO_OK : HYDRO_E_DEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,243 @@
+"""ctypes binding of libhydro.so (C ABI in include/hydro.h).
+
+Argument marshalling only: every step of the solver runs in the HIP
+kernels.  PyTorch provides the device workspace and the HIP stream.
+Importing this module loads the library and raises ImportError when it has
+not been built (``python -m paper_2501_02317_amd.build``); there is no
+fallback implementation.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhydro.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2501_02317_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+FP64, MIXED = 0, 1
+BC_PERIODIC, BC_FREE, BC_OUTFLOW, BC_REFLECT = 0, 1, 2, 3
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONPHYSICAL, E_STATE = 0, -1, -2, -3, -4, -5
+
+
+class Config(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 3), ("lo", C.c_double * 3),
+                ("hi", C.c_double * 3), ("gamma", C.c_double), ("cfl", C.c_double),
+                ("precision", C.c_int32), ("bc", (C.c_int32 * 2) * 3)]
+
+
+_dp = C.POINTER(C.c_double)
+_vp = C.c_void_p
+_h = C.c_void_p
+_SIG = {
+    "hydro_workspace_bytes": (C.c_size_t, [C.POINTER(Config)]),
+    "hydro_create": (C.c_int, [C.POINTER(Config), _vp, C.c_size_t, _vp, C.POINTER(_h)]),
+    "hydro_set_state": (C.c_int, [_h, _dp]),
+    "hydro_set_primitive": (C.c_int, [_h, _dp]),
+    "hydro_get_state": (C.c_int, [_h, _dp]),
+    "hydro_state_device": (C.c_int, [_h, C.POINTER(_vp)]),
+    "hydro_cfl_dt": (C.c_int, [_h, _dp]),
+    "hydro_step": (C.c_int, [_h, C.c_double]),
+    "hydro_step_auto": (C.c_int, [_h, C.c_int, C.c_double]),
+    "hydro_conserved_totals": (C.c_int, [_h, _dp]),
+    "hydro_time": (C.c_int, [_h, _dp]),
+    "hydro_steps_done": (C.c_int, [_h, C.POINTER(C.c_int64)]),
+    "hydro_stage_rhs": (C.c_int, [_h, C.c_double, _dp]),
+    "hydro_padded_primitive": (C.c_int, [_h, _dp]),
+    "hydro_profile": (C.c_int, [_h, C.c_int]),
+    "hydro_profile_read": (C.c_int, [_h, _dp, _dp, C.POINTER(C.c_int64)]),
+    "hydro_destroy": (C.c_int, [_h]),
+    "hydro_strerror": (C.c_char_p, [C.c_int]),
+    "hydro_riemann_fluxes": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_int64, _vp, _vp, _vp, _vp]),
+}
+for _name, (_res, _args) in _SIG.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+class HydroError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        msg = _lib.hydro_strerror(status).decode()
+        super().__init__(f"{what}: {msg} ({status})" if what else f"{msg} ({status})")
+
+
+def _check(status, what):
+    if status != OK:
+        raise HydroError(status, what)
+
+
+def strerror(status):
+    return _lib.hydro_strerror(int(status)).decode()
+
+
+def make_config(n, gamma, cfl, precision=FP64, lo=None, hi=None, bc=None):
+    """Config for the active axes' cell counts n (x first)."""
+    nd = len(n)
+    cfg = Config()
+    cfg.ndim = nd
+    lo = lo or (0.0,) * nd
+    hi = hi or (1.0,) * nd
+    bc = bc or ((BC_PERIODIC, BC_PERIODIC),) * nd
+    for d in range(3):
+        act = d < nd
+        cfg.n[d] = int(n[d]) if act else 1
+        cfg.lo[d] = float(lo[d]) if act else 0.0
+        cfg.hi[d] = float(hi[d]) if act else 1.0
+        for s in range(2):
+            cfg.bc[d][s] = int(bc[d][s]) if act else BC_PERIODIC
+    cfg.gamma = float(gamma)
+    cfg.cfl = float(cfl)
+    cfg.precision = int(precision)
+    return cfg
+
+
+def workspace_bytes(cfg):
+    return int(_lib.hydro_workspace_bytes(C.byref(cfg)))
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+class Hydro:
+    """One mesh resident on the GPU.
+
+    Fields are float64 numpy arrays of shape (ncomp, nz, ny, nx).
+    """
+
+    def __init__(self, n, gamma, cfl, precision=FP64, lo=None, hi=None, bc=None, device=None,
+                 stream=None):
+        import torch
+
+        self.cfg = make_config(n, gamma, cfl, precision, lo, hi, bc)
+        self.ndim = len(n)
+        self.ncomp = self.ndim + 2
+        nn = list(n) + [1] * (3 - len(n))
+        self.shape = (self.ncomp, nn[2], nn[1], nn[0])
+        nbytes = workspace_bytes(self.cfg)
+        if nbytes == 0:
+            raise HydroError(E_INVAL, "invalid configuration")
+        self.device = torch.device(device if device is not None else "cuda")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = _h()
+        _check(_lib.hydro_create(C.byref(self.cfg), _vp(self.workspace.data_ptr()), nbytes,
+                                 _vp(stream.cuda_stream), C.byref(h)), "hydro_create")
+        self._h = h
+
+    # ---- state
+    def set_state(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.shape)
+        _check(_lib.hydro_set_state(self._h, _ptr(U)), "hydro_set_state")
+
+    def set_primitive(self, W):
+        W = np.ascontiguousarray(W, dtype=np.float64).reshape(self.shape)
+        _check(_lib.hydro_set_primitive(self._h, _ptr(W)), "hydro_set_primitive")
+
+    def get_state(self):
+        U = np.empty(self.shape)
+        _check(_lib.hydro_get_state(self._h, _ptr(U)), "hydro_get_state")
+        return U
+
+    def state_view(self):
+        """Zero-copy torch view of the device state (valid until the next step)."""
+        import torch
+        p = _vp()
+        _check(_lib.hydro_state_device(self._h, C.byref(p)), "hydro_state_device")
+        off = p.value - self.workspace.data_ptr()
+        n = int(np.prod(self.shape))
+        return self.workspace[off: off + 8 * n].view(torch.float64).view(self.shape)
+
+    # ---- stepping
+    def cfl_dt(self):
+        dt = C.c_double()
+        _check(_lib.hydro_cfl_dt(self._h, C.byref(dt)), "hydro_cfl_dt")
+        return dt.value
+
+    def step(self, dt):
+        _check(_lib.hydro_step(self._h, float(dt)), "hydro_step")
+
+    def step_auto(self, nsteps, t_end=0.0):
+        _check(_lib.hydro_step_auto(self._h, int(nsteps), float(t_end)), "hydro_step_auto")
+
+    def time(self):
+        t = C.c_double()
+        _check(_lib.hydro_time(self._h, C.byref(t)), "hydro_time")
+        return t.value
+
+    def steps_done(self):
+        s = C.c_int64()
+        _check(_lib.hydro_steps_done(self._h, C.byref(s)), "hydro_steps_done")
+        return s.value
+
+    def totals(self):
+        T = np.empty(self.ncomp)
+        _check(_lib.hydro_conserved_totals(self._h, _ptr(T)), "hydro_conserved_totals")
+        return T
+
+    # ---- single-row views for testing
+    def stage_rhs(self, dt):
+        dU = np.empty(self.shape)
+        _check(_lib.hydro_stage_rhs(self._h, float(dt), _ptr(dU)), "hydro_stage_rhs")
+        return dU
+
+    def padded_primitive(self):
+        shp = [self.ncomp] + [s + (4 if (2 - a) < self.ndim else 0)
+                              for a, s in enumerate(self.shape[1:])]
+        Wp = np.empty(shp)
+        _check(_lib.hydro_padded_primitive(self._h, _ptr(Wp)), "hydro_padded_primitive")
+        return Wp
+
+    # ---- measurement
+    def profile(self, cap):
+        """Bracket the next cap launches of each stage kernel with HIP events."""
+        _check(_lib.hydro_profile(self._h, int(cap)), "hydro_profile")
+
+    def profile_read(self):
+        """(ms of stage-1 launches, ms of stage-2 launches, (n1, n2))."""
+        a, b = C.c_double(), C.c_double()
+        n = (C.c_int64 * 2)()
+        _check(_lib.hydro_profile_read(self._h, C.byref(a), C.byref(b), n), "hydro_profile_read")
+        return a.value, b.value, (n[0], n[1])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hydro_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def riemann_fluxes(precision, gamma, WL, WR, stream=None):
+    """HLLC fluxes of face-normal state pairs on the GPU.
+
+    WL, WR: float64 arrays (ntan+3, nfaces); returns F as numpy (ntan+3, nfaces).
+    """
+    import torch
+    WL = np.ascontiguousarray(WL, dtype=np.float64)
+    WR = np.ascontiguousarray(WR, dtype=np.float64)
+    nc, nf = WL.shape
+    dL = torch.from_numpy(WL).cuda()
+    dR = torch.from_numpy(WR).cuda()
+    dF = torch.empty_like(dL)
+    s = stream or torch.cuda.current_stream()
+    _check(_lib.hydro_riemann_fluxes(int(precision), nc - 3, float(gamma), nf, _vp(dL.data_ptr()),
+                                     _vp(dR.data_ptr()), _vp(dF.data_ptr()), _vp(s.cuda_stream)),
+           "hydro_riemann_fluxes")
+    s.synchronize()
+    return dF.cpu().numpy()
+
+
+def exported_symbols():
+    """Names the library exports from the C ABI (for the ABI test)."""
+    return sorted(_SIG)

@@ -185,12 +185,15 @@ def _grf(rng, n, kmin, kmax, slope):
 
 def turbulence_3d(n=128, mach=1.0, seed=201, gamma=5.0 / 3.0, cfl=0.3, steps=200, kmax=16,
                   sigma=0.1, ndim=3):
-    """Log-normal density (flat spectrum over 1 <= |k| <= kmax, std sigma in
+    """n: cells per axis (int, with ndim axes) or a tuple of per-axis counts.
+
+    Log-normal density (flat spectrum over 1 <= |k| <= kmax, std sigma in
     log space, unit mean) and a zero-mean Gaussian random velocity with
     per-mode |v_k|^2 ~ k^-4 (shell spectrum k^-2, ndim = 3) over the same
     band, scaled to rms |v| = mach (c_s = 1 with p = 1/gamma, rho = 1)."""
     rng = np.random.default_rng(seed)
-    nn = (n,) * ndim
+    nn = tuple(int(v) for v in n) if isinstance(n, (tuple, list)) else (int(n),) * ndim
+    ndim = len(nn)
     grid = _shape(nn)[3 - ndim:]
     s = _grf(rng, grid, 1.0, kmax, 0.0)
     s *= sigma / s.std()
@@ -211,7 +214,8 @@ def turbulence_3d(n=128, mach=1.0, seed=201, gamma=5.0 / 3.0, cfl=0.3, steps=200
     W = _pack(nn, rho.reshape(full), [v.reshape(full) for v in vel], p.reshape(full))
     lo = (0.0,) * ndim
     hi = (1.0,) * ndim
-    return Case(f"turbulence_{ndim}d_{n}", nn, lo, hi, gamma, cfl, W, steps=steps,
+    name = f"turbulence_{ndim}d_" + "x".join(str(v) for v in nn)
+    return Case(name, nn, lo, hi, gamma, cfl, W, steps=steps,
                 meta={"seed": seed, "mach": mach, "kmax": kmax, "sigma": sigma})
 
 

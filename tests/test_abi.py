@@ -1,0 +1,70 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/hydro.h declares, and rejects invalid configurations on the host."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "hydro.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hydro_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_2501_02317_amd import build
+    build.build(force=False)
+    from paper_2501_02317_amd import hydro
+    return hydro
+
+
+def test_library_exports_every_declared_symbol(H):
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(H._lib, n), n
+    assert set(names) == set(H.exported_symbols())
+
+
+def test_workspace_bytes_validation(H):
+    ok = H.make_config((64, 32, 16), 5.0 / 3.0, 0.3)
+    nb = H.workspace_bytes(ok)
+    assert nb >= 2 * 5 * 64 * 32 * 16 * 8
+    bad = [
+        H.make_config((64,), 1.0, 0.3),                       # gamma <= 1
+        H.make_config((64,), 1.4, 0.0),                       # cfl <= 0
+        H.make_config((64,), 1.4, 1.5),                       # cfl > 1
+        H.make_config((64,), 1.4, 0.3, precision=7),          # unknown precision
+        H.make_config((0,), 1.4, 0.3),                        # empty axis
+        H.make_config((1,), 1.4, 0.3),                        # periodic needs two cells
+        H.make_config((8,), 1.4, 0.3, bc=((0, 1),)),          # periodic on one side only
+        H.make_config((8,), 1.4, 0.3, lo=(1.0,), hi=(0.0,)),  # inverted box
+    ]
+    for cfg in bad:
+        assert H.workspace_bytes(cfg) == 0
+    cfg = H.make_config((8,), 1.4, 0.3)
+    cfg.ndim = 4
+    assert H.workspace_bytes(cfg) == 0
+    cfg = H.make_config((8,), 1.4, 0.3)
+    cfg.n[1] = 2                                              # inactive axis must be 1
+    assert H.workspace_bytes(cfg) == 0
+
+
+def test_create_rejects_bad_arguments_without_device(H):
+    cfg = H.make_config((64,), 1.4, 0.4)
+    h = C.c_void_p()
+    assert H._lib.hydro_create(C.byref(cfg), None, 1 << 20, None, C.byref(h)) == H.E_INVAL
+    assert H._lib.hydro_create(C.byref(cfg), C.c_void_p(256), 16, None, C.byref(h)) == H.E_INVAL
+    assert H._lib.hydro_create(C.byref(cfg), C.c_void_p(100), 1 << 20, None, C.byref(h)) == H.E_INVAL
+    assert H._lib.hydro_create(None, C.c_void_p(256), 1 << 20, None, C.byref(h)) == H.E_INVAL
+    assert H._lib.hydro_step(None, 1.0) == H.E_INVAL
+    assert H._lib.hydro_step_auto(None, 1, 0.0) == H.E_INVAL
+    assert H._lib.hydro_destroy(None) == H.E_INVAL
+    assert H._lib.hydro_riemann_fluxes(3, 1, 1.4, 10, None, None, None, None) == H.E_INVAL
+    assert H._lib.hydro_riemann_fluxes(0, 1, 1.4, 0, None, None, None, None) == H.OK
+    assert "non-physical" in H.strerror(H.E_NONPHYSICAL)

@@ -1,0 +1,395 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+FP64 path: the kernels evaluate the oracle's formulas in the same order with
+IEEE division and square root and no contraction, so results are expected to
+be identical; the gate is the stated tolerance (relative L1 <= 1e-12 after a
+run, 1e-14 for single rows), and the tests also report exact equality.
+Mixed path (FP32 reconstruction and Riemann solve, FP64 update): relative L1
+<= 1e-5 against the FP64 oracle on smooth flows; per-face HLLC error within
+the paper's 1e-3 (Sec. 3.2.2).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2501_02317_amd import workloads as wl
+from gpu_util import bitwise_equal, gpu_mesh, max_rel, oracle_mesh, rel_l1, say
+
+pytestmark = pytest.mark.gpu
+
+CLAIMS = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_claims.json")))
+FP64_RUN_TOL = 1e-12
+FP64_ROW_TOL = 1e-14
+MIXED_SMOOTH_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2501_02317_amd import hydro
+    return hydro
+
+
+def random_prim(ndim, n, seed, mach=0.8):
+    c = wl.turbulence_3d(n=n, mach=mach, seed=seed, ndim=ndim) if ndim > 1 else None
+    if c is None:
+        c = wl.smooth_1d(N=n[0], seed=seed)
+    return c
+
+
+# ------------------------------------------------------------ A5: HLLC per face
+
+def random_faces(rng, nt, n, spread=2.0):
+    W = np.empty((nt + 3, n))
+    W[0] = np.exp(rng.uniform(-spread, spread, n))
+    W[1:nt + 2] = rng.uniform(-spread, spread, (nt + 1, n))
+    W[-1] = np.exp(rng.uniform(-spread, spread, n))
+    return W
+
+
+@pytest.mark.parametrize("nt", [0, 1, 2])
+def test_hllc_fp64_matches_oracle(H, nt):
+    rng = np.random.default_rng(100 + nt)
+    WL, WR = random_faces(rng, nt, 3000), random_faces(rng, nt, 3000)
+    say("hllc fp64 nt", nt)
+    F = H.riemann_fluxes(H.FP64, 1.4, WL, WR)
+    Fo = np.stack([O.hllc(1.4, WL[:, i], WR[:, i]) for i in range(WL.shape[1])], axis=1)
+    scale = np.abs(Fo).max(axis=0)
+    assert np.all(np.abs(F - Fo).max(axis=0) <= FP64_ROW_TOL * scale)
+    print("hllc fp64 identical:", bitwise_equal(F, Fo))
+
+
+@pytest.mark.parametrize("nt", [0, 1, 2])
+def test_hllc_mixed_within_paper_bound(H, nt):
+    """Sec. 3.2.2: mixed-precision HLLC within 1e-3 relative of FP64."""
+    rng = np.random.default_rng(200 + nt)
+    WL, WR = random_faces(rng, nt, 3000, 3.0), random_faces(rng, nt, 3000, 3.0)
+    say("hllc mixed nt", nt)
+    F32 = H.riemann_fluxes(H.MIXED, 5.0 / 3.0, WL, WR)
+    Fo = np.stack([O.hllc(5.0 / 3.0, WL[:, i], WR[:, i]) for i in range(WL.shape[1])], axis=1)
+    err = np.abs(F32 - Fo).max(axis=0) / np.abs(Fo).max(axis=0)
+    print(f"mixed hllc rel err: median {np.median(err):.2e} p99 {np.quantile(err, 0.99):.2e} "
+          f"max {err.max():.2e}")
+    assert err.max() < CLAIMS["mixed_hllc_rel_error_max"]
+
+
+# ------------------------------------------------------------ A1 + A2: ghosts and primitives
+
+GHOST_CASES = [
+    (1, (37,), ((1, 1),)),
+    (1, (37,), ((3, 2),)),
+    (2, (70, 19), ((0, 0), (1, 3))),
+    (2, (70, 19), ((2, 3), (0, 0))),
+    (3, (37, 19, 11), None),
+    (3, (37, 19, 11), ((1, 2), (3, 3), (0, 0))),
+]
+
+
+@pytest.mark.parametrize("ndim,n,bc", GHOST_CASES)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ghost_fill_and_conversion(H, ndim, n, bc, precision):
+    c = random_prim(ndim, n, seed=7)
+    if bc is not None:
+        c.bc = bc
+    say("ghosts", ndim, n, bc, precision)
+    h = gpu_mesh(c, precision)
+    m = oracle_mesh(c)
+    U_o = O.prim_to_cons(m, c.W)
+    assert bitwise_equal(h.get_state(), U_o)              # device prim -> cons
+    Wp_o = O.padded_primitive(m, U_o)
+    Wp = h.padded_primitive()
+    if precision == 0:
+        assert bitwise_equal(Wp, Wp_o)
+    else:
+        assert bitwise_equal(Wp, Wp_o.astype(np.float32).astype(np.float64))
+    h.close()
+
+
+# ------------------------------------------------------------ A3: dt
+
+@pytest.mark.parametrize("ndim,n", [(1, (256,)), (2, (96, 80)), (3, (40, 36, 28))])
+def test_cfl_dt_matches_oracle(H, ndim, n):
+    c = random_prim(ndim, n, seed=8, mach=1.5)
+    say("dt", ndim, n)
+    h = gpu_mesh(c, 0)
+    m = oracle_mesh(c)
+    dt_o = O.cfl_dt(m, O.prim_to_cons(m, c.W), c.cfl)
+    dt = h.cfl_dt()
+    assert abs(dt - dt_o) <= 1e-15 * dt_o
+    h.close()
+
+
+# ------------------------------------------------------------ A4-A6: one stage
+
+STAGE_CASES = [
+    (1, (256,), None),
+    (1, (203,), ((1, 1),)),
+    (2, (96, 80), None),
+    (2, (150, 33), ((2, 2), (3, 3))),
+    (3, (40, 36, 28), None),
+    (3, (70, 19, 13), ((1, 1), (2, 3), (0, 0))),
+    (3, (33, 9, 40), ((3, 3), (0, 0), (2, 1))),
+]
+
+
+@pytest.mark.parametrize("ndim,n,bc", STAGE_CASES)
+def test_stage_rhs_fp64_matches_oracle(H, ndim, n, bc):
+    c = random_prim(ndim, n, seed=9, mach=1.2)
+    if bc is not None:
+        c.bc = bc
+    m = oracle_mesh(c)
+    U = O.prim_to_cons(m, c.W)
+    dt = O.cfl_dt(m, U, c.cfl)
+    say("stage rhs fp64", ndim, n, bc)
+    h = gpu_mesh(c, 0)
+    dU = h.stage_rhs(dt)
+    dU_o = O.rhs(m, U, dt)
+    err = max_rel(dU, dU_o)
+    print("stage rhs max rel", err, "identical:", bitwise_equal(dU, dU_o))
+    assert np.all(err <= FP64_ROW_TOL)
+    h.close()
+
+
+@pytest.mark.parametrize("ndim,n,bc", STAGE_CASES[::2])
+def test_stage_rhs_mixed_close_to_oracle(H, ndim, n, bc):
+    c = random_prim(ndim, n, seed=9, mach=1.2)
+    if bc is not None:
+        c.bc = bc
+    m = oracle_mesh(c)
+    U = O.prim_to_cons(m, c.W)
+    dt = O.cfl_dt(m, U, c.cfl)
+    say("stage rhs mixed", ndim, n, bc)
+    h = gpu_mesh(c, 1)
+    dU = h.stage_rhs(dt)
+    dU_o = O.rhs(m, U, dt)
+    # the increment relative to the state it updates
+    err = np.abs(dU - dU_o).reshape(m.ncomp, -1).sum(axis=1) / np.abs(U).reshape(m.ncomp, -1).sum(axis=1)
+    print("stage rhs mixed err / |U|", err)
+    assert np.all(err <= 1e-6)
+    h.close()
+
+
+# ------------------------------------------------------------ A7: whole runs
+
+def run_both(H, c, precision, steps=None, t_end=None):
+    m = oracle_mesh(c)
+    U0 = O.prim_to_cons(m, c.W)
+    steps = c.steps if steps is None else steps
+    t_end = c.t_end if t_end is None else t_end
+    U_o, t_o, s_o, _ = O.run(m, U0, c.cfl, max_steps=steps, t_end=t_end)
+    h = gpu_mesh(c, precision)
+    h.step_auto(s_o + (3 if t_end > 0 else 0), t_end)
+    U = h.get_state()
+    t, s = h.time(), h.steps_done()
+    T, T0 = h.totals(), O.totals(m, U0)
+    h.close()
+    return m, U0, U_o, t_o, s_o, U, t, s, T, T0
+
+
+RUN_CASES = [
+    ("smooth_1d", lambda: wl.smooth_1d(256)),
+    ("sod_1d", lambda: wl.sod_1d(256)),
+    ("shear_layer_96x80", lambda: wl.shear_layer_2d(96, 80, seed=4001, steps=40)),
+    ("turb2d_130x70_outflow", lambda: _with_bc(wl.turbulence_3d(n=(130, 70), mach=1.0, seed=3,
+                                                                   ndim=2, steps=30),
+                                                ((2, 2), (3, 3)))),
+    ("turb3d_40x36x28", lambda: wl.turbulence_3d(n=(40, 36, 28), mach=2.0, seed=4, steps=12)),
+    ("turb3d_33x20x17_mixedbc", lambda: _with_bc(wl.turbulence_3d(n=(33, 20, 17), mach=1.0, seed=5,
+                                                                     steps=10),
+                                                  ((1, 2), (3, 3), (0, 0)))),
+]
+
+
+def _with_bc(c, bc):
+    c.bc = bc
+    return c
+
+
+@pytest.mark.parametrize("name,make", RUN_CASES, ids=[r[0] for r in RUN_CASES])
+def test_run_fp64_matches_oracle(H, name, make):
+    c = make()
+    say("run fp64", name)
+    m, U0, U_o, t_o, s_o, U, t, s, T, T0 = run_both(H, c, 0)
+    assert s == s_o and t == t_o
+    err = rel_l1(U, U_o)
+    print(name, "relL1", err, "identical:", bitwise_equal(U, U_o))
+    assert np.all(err <= FP64_RUN_TOL)
+
+
+SMOOTH_CASES = [
+    RUN_CASES[0],
+    ("turb2d_128x96_mach0.5", lambda: wl.turbulence_3d(n=(128, 96), mach=0.5, seed=15, ndim=2,
+                                                          steps=40, kmax=8)),
+    ("shear_layer_256x256", lambda: wl.shear_layer_2d(256, 256, seed=4003, steps=40)),
+    RUN_CASES[4],
+]
+
+
+@pytest.mark.parametrize("name,make", SMOOTH_CASES, ids=[r[0] for r in SMOOTH_CASES])
+def test_run_mixed_smooth_within_gate(H, name, make):
+    """Smooth flows: mixed precision within relative L1 1e-5 of the FP64 oracle.
+    (A shear layer of tanh width 0.02 is smooth only where the mesh resolves
+    the width; at 256^2 it spans five cells.)"""
+    c = make()
+    say("run mixed", name)
+    m, U0, U_o, t_o, s_o, U, t, s, T, T0 = run_both(H, c, 1)
+    err = rel_l1(U, U_o)
+    print(name, "mixed relL1 vs FP64 oracle", err)
+    assert np.all(err <= MIXED_SMOOTH_TOL)
+
+
+@pytest.mark.parametrize("name,make", [RUN_CASES[1], RUN_CASES[2]], ids=["sod_1d", "shear_layer_96x80"])
+def test_run_mixed_nonsmooth_reported(H, name, make):
+    """Discontinuous or under-resolved flows: mixed vs FP64 reported, loose bound."""
+    c = make()
+    say("run mixed", name)
+    m, U0, U_o, t_o, s_o, U, t, s, T, T0 = run_both(H, c, 1)
+    err = rel_l1(U, U_o)
+    print(name, "mixed relL1 vs FP64 oracle", err)
+    assert np.all(err <= 1e-3)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_periodic_conservation_on_gpu(H, precision):
+    c = wl.turbulence_3d(n=48, mach=2.0, seed=6, steps=20)
+    say("conservation", precision)
+    m, U0, U_o, t_o, s_o, U, t, s, T, T0 = run_both(H, c, precision)
+    dV = np.prod(m.dx)
+    for comp in range(m.ncomp):
+        bound = CLAIMS["conservation_rel"] * dV * np.abs(U0[comp]).sum()
+        assert abs(T[comp] - T0[comp]) <= bound, (comp, T[comp] - T0[comp], bound)
+    # totals are the compensated sum of the returned state
+    Tst = O.totals(m, U)
+    assert np.all(np.abs(T - Tst) <= 1e-15 * dV * np.abs(U).reshape(m.ncomp, -1).sum(axis=1))
+
+
+# ------------------------------------------------------------ invariants on the GPU
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mirror_and_transpose_bitwise_on_gpu(H, precision):
+    c = wl.smooth_1d(N=200, seed=12)
+    cm = wl.smooth_1d(N=200, seed=12)
+    cm.W = c.W[:, :, :, ::-1].copy()
+    cm.W[1] = -cm.W[1]
+    say("mirror", precision)
+    h1, h2 = gpu_mesh(c, precision), gpu_mesh(cm, precision)
+    h1.step_auto(60)
+    h2.step_auto(60)
+    A, B = h1.get_state(), h2.get_state()
+    B = B[:, :, :, ::-1].copy()
+    B[1] = -B[1]
+    assert bitwise_equal(A, B)
+    h1.close(), h2.close()
+
+    c = wl.turbulence_3d(n=(72, 72), mach=1.0, seed=13, ndim=2)
+    ct = wl.turbulence_3d(n=(72, 72), mach=1.0, seed=13, ndim=2)
+    ct.W = np.swapaxes(c.W, 2, 3).copy()
+    ct.W[[1, 2]] = ct.W[[2, 1]]
+    say("transpose", precision)
+    h1, h2 = gpu_mesh(c, precision), gpu_mesh(ct, precision)
+    h1.step_auto(25)
+    h2.step_auto(25)
+    A, B = h1.get_state(), h2.get_state()
+    B = np.swapaxes(B, 2, 3).copy()
+    B[[1, 2]] = B[[2, 1]]
+    assert bitwise_equal(A, B)
+    h1.close(), h2.close()
+
+
+def test_deterministic_and_restart_bitwise(H):
+    c = wl.turbulence_3d(n=(40, 24, 20), mach=1.5, seed=14, steps=10)
+    say("determinism")
+    h = gpu_mesh(c, 0)
+    h.step_auto(10)
+    A = h.get_state()
+    h.set_primitive(c.W)
+    h.step_auto(10)
+    assert bitwise_equal(h.get_state(), A)
+    h.set_primitive(c.W)
+    h.step_auto(4)
+    mid = h.get_state()
+    h.close()
+    h2 = gpu_mesh(c, 0)
+    h2.set_state(mid)
+    h2.step_auto(6)
+    assert bitwise_equal(h2.get_state(), A)
+    h2.close()
+
+
+def test_host_dt_steps_match_oracle(H):
+    c = wl.shear_layer_2d(64, 64, seed=4002)
+    m = oracle_mesh(c)
+    U = O.prim_to_cons(m, c.W)
+    say("host dt")
+    h = gpu_mesh(c, 0)
+    for _ in range(5):
+        dt = O.cfl_dt(m, U, c.cfl)
+        assert h.cfl_dt() == dt
+        U = O.heun_step(m, U, dt)
+        h.step(dt)
+    assert np.all(rel_l1(h.get_state(), U) <= FP64_RUN_TOL)
+    h.close()
+
+
+def test_nonphysical_state_is_reported(H):
+    c = wl.smooth_1d(64)
+    c.W[-1, 0, 0, 10] = -1.0
+    say("nonphysical")
+    h = gpu_mesh(c, 0)
+    with pytest.raises(H.HydroError) as e:
+        h.cfl_dt()
+    assert e.value.status == H.E_NONPHYSICAL
+    h.step_auto(1)
+    with pytest.raises(H.HydroError) as e:
+        h.time()
+    assert e.value.status == H.E_NONPHYSICAL
+    with pytest.raises(H.HydroError) as e:
+        h.step(-1.0)
+    assert e.value.status == H.E_INVAL
+    with pytest.raises(H.HydroError):
+        h.step(float("nan"))
+    h.close()
+
+
+# ------------------------------------------------------------ full sizes, sampled
+
+def sample_cells(n, count, seed):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = (list(n) + [1, 1])[:3]
+    pts = [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (31, 7, 31), (32, 8, 32), (nx - 1, 0, nz // 2)]
+    idx = [(z * ny + y) * nx + x for x, y, z in pts]
+    idx += list(rng.integers(0, nx * ny * nz, count))
+    return np.unique(np.array(idx, dtype=np.int64))
+
+
+@pytest.mark.parametrize("n,mach,seed,precision", [(128, 1.0, 201, 0), (256, 2.0, 301, 0),
+                                                    (256, 2.0, 301, 1)])
+def test_full_size_one_step_sampled(H, n, mach, seed, precision):
+    """The benchmark's launch configuration at full size: one device-dt step
+    from the seeded initial state, checked at sampled cells (oracle per cell)."""
+    c = wl.turbulence_3d(n=n, mach=mach, seed=seed, steps=1)
+    m = oracle_mesh(c)
+    U0 = O.prim_to_cons(m, c.W)
+    dt = O.cfl_dt(m, U0, c.cfl)
+    cells = sample_cells(c.n, 400, seed)
+    ref = O.step_cells(m, U0, dt, cells)
+    say("full size sampled", n, precision)
+    h = gpu_mesh(c, precision)
+    h.step_auto(1)
+    got = h.get_state().reshape(m.ncomp, -1)[:, cells]
+    t = h.time()
+    h.close()
+    assert abs(t - dt) <= 1e-15 * dt
+    U0s = U0.reshape(m.ncomp, -1)[:, cells]
+    if precision == 0:
+        assert np.all(max_rel(got, ref) <= FP64_ROW_TOL)
+        print("full size fp64 identical:", bitwise_equal(got, ref))
+    else:
+        # one mixed step: increment error small against the state
+        err = np.abs(got - ref).sum(axis=1) / np.abs(U0s).sum(axis=1)
+        print("full size mixed one-step err", err)
+        assert np.all(err <= 1e-7)

@@ -12,9 +12,9 @@ constexpr int kMaxComp = 5;
 
 // Device control block, one per mesh, in the caller's workspace.
 struct Ctrl {
-    double dt_raw;                  // cfl * min CFL candidate of the current state
+    double dt_raw;                  // cfl / (max CFL rate) of the current state
     double t;                       // simulation time
-    unsigned long long dtmin_bits;  // min accumulator: positive doubles order as integers
+    unsigned long long rate_bits;   // max accumulator: non-negative doubles order as integers
     unsigned int flags;             // sticky error flags
     unsigned int dt_valid;          // dt_raw belongs to the current state
     unsigned long long steps;       // completed steps
@@ -27,9 +27,9 @@ enum : unsigned int { FLAG_NONPHYSICAL = 1u };
 
 enum CtrlOp : int {
     CTRL_INIT = 0,           // t = a0, steps = 0, flags = 0, dt invalid
-    CTRL_RESET_MIN = 1,      // dtmin = +inf
-    CTRL_FINALIZE_DT = 2,    // dt_raw = cfl * dtmin, dt valid
-    CTRL_FINALIZE_STEP = 3,  // t += clamped dt (t_end = a1), dt_raw = cfl * dtmin, reset min
+    CTRL_RESET_MIN = 1,      // rate accumulator = 0
+    CTRL_FINALIZE_DT = 2,    // dt_raw = cfl / rate, dt valid
+    CTRL_FINALIZE_STEP = 3,  // t += clamped dt (t_end = a1), dt_raw = cfl / rate, reset
     CTRL_ADVANCE_T = 4,      // t += a0 (host dt), dt invalid
 };
 
@@ -42,6 +42,7 @@ struct Geo {
     int ndim;
     int n[3];
     double dx[3];
+    double inv_dx[3];
     int bc[3][2];
     double gamma;
     double cfl;

@@ -32,12 +32,9 @@ namespace {
 enum { BC_PERIODIC = 0, BC_FREE = 1, BC_OUTFLOW = 2, BC_REFLECT = 3 };
 enum { VM_NONE = 0, VM_NEG = 1, VM_CLIP_LO = 2, VM_CLIP_HI = 3 };
 
-constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
 
 __device__ __forceinline__ double dabs(double x) { return __builtin_fabs(x); }
 __device__ __forceinline__ float dabs(float x) { return __builtin_fabsf(x); }
-__device__ __forceinline__ double dsqrt(double x) { return __builtin_sqrt(x); }
-__device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
 
 // Velocity component (index into W/U) along kernel axis ax.
 template <int NDIM>
@@ -45,30 +42,76 @@ __device__ __forceinline__ constexpr int vcomp(int ax) {
     return ax == 0 ? 1 : (ax == 1 ? 2 : NDIM);
 }
 
-// ----------------------------------------------------------------- physics
+// Arithmetic policy.  FP64: IEEE division and square root.  FP32 (the mixed
+// path's reconstruction and Riemann solve): the hardware reciprocal and
+// square root (1 ulp), which the FP32 tolerance of that path absorbs.
+template <typename R>
+struct Ops;
+
+template <>
+struct Ops<double> {
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double sqrt(double x) { return __builtin_sqrt(x); }
+    static __device__ __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+    static __device__ __forceinline__ double max0(double x) { return __builtin_fmax(x, 0.0); }
+    // median of (a, b, 0): the minmod of eq. minmod
+    static __device__ __forceinline__ double minmod(double a, double b) {
+        return __builtin_fmax(__builtin_fmin(a, b), __builtin_fmin(__builtin_fmax(a, b), 0.0));
+    }
+};
+
+template <>
+struct Ops<float> {
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+    static __device__ __forceinline__ float max0(float x) { return __builtin_fmaxf(x, 0.0f); }
+    static __device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
+};
+
+// Gas constants in the compute precision.
+template <typename R>
+struct Gas {
+    R g;        // gamma
+    R z;        // (gamma + 1) / (2 gamma)
+    R inv_gm1;  // 1 / (gamma - 1)
+};
 
 template <typename R>
-__device__ __forceinline__ R minmod(R a, R b) {
-    // eq. minmod; zero unless both slopes have the same strict sign
-    const bool same = (a > R(0) && b > R(0)) || (a < R(0) && b < R(0));
-    const R m = dabs(a) < dabs(b) ? a : b;
-    return same ? m : R(0);
+__device__ __forceinline__ Gas<R> make_gas(double g) {
+    Gas<R> o;
+    o.g = (R)g;
+    o.z = (R)((g + 1.0) / (2.0 * g));
+    o.inv_gm1 = (R)(1.0 / (g - 1.0));
+    return o;
 }
 
-// v_d = m_d / rho, p = (gamma - 1)(E - (1/2) sum_d m_d v_d); returns admissibility.
+// ----------------------------------------------------------------- physics
+
+// eq. minmod: the slope of smaller magnitude when both have the same strict
+// sign, else zero -- which is the median of (a, b, 0).
+template <typename R>
+__device__ __forceinline__ R minmod(R a, R b) {
+    return Ops<R>::minmod(a, b);
+}
+
+// Conserved -> primitive in FP64 (Sec. 3.1): r = 1/rho, v_d = m_d r,
+// p = (gamma - 1)(E - (1/2) r sum_d m_d^2); returns admissibility.  The
+// squares are rounded separately and summed in axis order, so interchanging
+// x and y leaves the result bitwise unchanged.
 template <int NDIM>
-__device__ __forceinline__ bool cons_to_prim(double g, const double (&u)[NDIM + 2],
+__device__ __forceinline__ bool cons_to_prim(double gm1, const double (&u)[NDIM + 2],
                                              double (&w)[NDIM + 2]) {
     const double rho = u[0];
-    double ke2 = 0.0;
-    w[0] = rho;
+    const double r = 1.0 / rho;
+    double msq = 0.0;
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) {
-        const double v = u[1 + d] / rho;
-        w[1 + d] = v;
-        ke2 = ke2 + u[1 + d] * v;
+        w[1 + d] = u[1 + d] * r;
+        msq = msq + u[1 + d] * u[1 + d];
     }
-    const double p = (g - 1.0) * (u[NDIM + 1] - 0.5 * ke2);
+    const double p = gm1 * __builtin_fma(-0.5 * r, msq, u[NDIM + 1]);
+    w[0] = rho;
     w[NDIM + 1] = p;
     bool fin = true;
 #pragma unroll
@@ -76,36 +119,39 @@ __device__ __forceinline__ bool cons_to_prim(double g, const double (&u)[NDIM + 
     return fin && rho > 0.0 && p > 0.0 && __builtin_isfinite(p);
 }
 
-// HLLC flux in the face-normal frame, W = (rho, u, t_1..t_NT, p).  Wave
-// speeds s_K = u_K + ds_K with ds_L = -c_L q_L, ds_R = c_R q_R and
-// q_K = sqrt(1 + (g+1)/(2g) (max(p*/p_K, 1) - 1)), p* the primitive-variable
-// pressure guess clipped at 0; contact speed from the bracketed form of
-// eq. hllc-contact-spd.  Only the side the selection picks is evaluated.
+// HLLC flux in the face-normal frame, W = (rho, u, t_1..t_NT, p).
+//   c_K = sqrt(g p_K / rho_K); p* = max(0, primitive-variable guess);
+//   ds_L = -c_L q_L, ds_R = c_R q_R with q_K = sqrt(1 + z (max(p*/p_K, 1) - 1))
+//   (eq. hllc-mixed-dvel), evaluated as c_K q_K = sqrt(g/rho_K (p_K + z max(p* - p_K, 0)))
+//   so ds_K = c_K exactly when p* <= p_K; s_* from the bracketed form of
+//   eq. hllc-contact-spd; star state and flux of the selected side only.
 template <typename R, int NT>
-__device__ __forceinline__ void hllc(const R g, const R (&WL)[NT + 3], const R (&WR)[NT + 3],
+__device__ __forceinline__ void hllc(const Gas<R>& gas, const R (&WL)[NT + 3], const R (&WR)[NT + 3],
                                      R (&F)[NT + 3]) {
+    using O = Ops<R>;
     constexpr int NC = NT + 3;
+    const R g = gas.g;
     const R rl = WL[0], ul = WL[1], pl = WL[NC - 1];
     const R rr = WR[0], ur = WR[1], pr = WR[NC - 1];
-    const R cl = dsqrt(g * pl / rl);
-    const R cr = dsqrt(g * pr / rr);
+    const R ril = O::rcp(rl), rir = O::rcp(rr);
+    const R gil = g * ril, gir = g * rir;
+    const R cl = O::sqrt(gil * pl);
+    const R cr = O::sqrt(gir * pr);
     const R ppv = R(0.5) * (pl + pr) - R(0.125) * (ur - ul) * (rl + rr) * (cl + cr);
-    const R ps = ppv > R(0) ? ppv : R(0);
-    const R z = (g + R(1)) / (R(2) * g);
-    const R ratl = ps / pl, ratr = ps / pr;
-    const R ql = dsqrt(R(1) + z * ((ratl > R(1) ? ratl : R(1)) - R(1)));
-    const R qr = dsqrt(R(1) + z * ((ratr > R(1) ? ratr : R(1)) - R(1)));
-    const R dsl = -cl * ql;
-    const R dsr = cr * qr;
+    const R ps = O::max0(ppv);
+    const R dsl = -O::sqrt(gil * O::fma(gas.z, O::max0(ps - pl), pl));
+    const R dsr = O::sqrt(gir * O::fma(gas.z, O::max0(ps - pr), pr));
     const R sl = ul + dsl;
     const R sr = ur + dsr;
-    const R ss = ((pr - rr * ur * dsr) - (pl - rl * ul * dsl)) / (rl * dsl - rr * dsr);
+    const R ml = rl * dsl, mr = rr * dsr;  // rho_K ds_K
+    const R ss = (O::fma(-mr, ur, pr) - O::fma(-ml, ul, pl)) * O::rcp(ml - mr);
 
     // s_L >= 0: F_L ; s_* >= 0: F*_L ; s_R > 0: F*_R ; else F_R
     const bool left = (sl >= R(0)) || (ss >= R(0));
     const bool star = left ? !(sl >= R(0)) : (sr > R(0));
     const R sK = left ? sl : sr;
-    const R dsK = left ? dsl : dsr;
+    const R mK = left ? ml : mr;
+    const R ri = left ? ril : rir;  // 1 / rho_K
     R W[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) W[c] = left ? WL[c] : WR[c];
@@ -120,28 +166,29 @@ __device__ __forceinline__ void hllc(const R g, const R (&WL)[NT + 3], const R (
     for (int k = 0; k < NT; ++k) {
         const R mt = rho * W[2 + k];
         Uk[2 + k] = mt;
-        ket = ket + mt * W[2 + k];
+        ket = O::fma(mt, W[2 + k], ket);
     }
-    const R ke2 = mu * u + ket;
-    const R E = p / (g - R(1)) + R(0.5) * ke2;
+    const R ke2 = O::fma(mu, u, ket);
+    const R E = O::fma(p, gas.inv_gm1, R(0.5) * ke2);
     Uk[NC - 1] = E;
     Fk[0] = mu;
-    Fk[1] = mu * u + p;
+    Fk[1] = O::fma(mu, u, p);
 #pragma unroll
     for (int k = 0; k < NT; ++k) Fk[2 + k] = mu * W[2 + k];
     Fk[NC - 1] = (E + p) * u;
 
     // star state chi (1, s_*, t, E/rho + (s_* - u)(s_* + p/(rho ds))), chi = rho ds / (s - s_*)
-    const R chi = rho * dsK / (sK - ss);
+    const R chi = mK * O::rcp(sK - ss);
+    const R e_rho = E * ri;
     R Us[NC];
     Us[0] = chi;
     Us[1] = chi * ss;
 #pragma unroll
     for (int k = 0; k < NT; ++k) Us[2 + k] = chi * W[2 + k];
-    Us[NC - 1] = chi * (E / rho + (ss - u) * (ss + p / (rho * dsK)));
+    Us[NC - 1] = chi * O::fma(ss - u, O::fma(p, O::rcp(mK), ss), e_rho);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        const R fs = Fk[c] + sK * (Us[c] - Uk[c]);
+        const R fs = O::fma(sK, Us[c] - Uk[c], Fk[c]);
         F[c] = star ? fs : Fk[c];
     }
 }
@@ -151,7 +198,7 @@ __device__ __forceinline__ void hllc(const R g, const R (&WL)[NT + 3], const R (
 // component, rotate the face normal to the first velocity slot, HLLC, rotate
 // back.  Tangential velocities keep increasing component order.
 template <int NDIM, int AX, typename R>
-__device__ __forceinline__ void face_flux(const R g, const R (&w0)[NDIM + 2], const R (&w1)[NDIM + 2],
+__device__ __forceinline__ void face_flux(const Gas<R>& g, const R (&w0)[NDIM + 2], const R (&w1)[NDIM + 2],
                                           const R (&w2)[NDIM + 2], const R (&w3)[NDIM + 2],
                                           R (&F)[NDIM + 2]) {
     constexpr int NC = NDIM + 2;
@@ -162,8 +209,8 @@ __device__ __forceinline__ void face_flux(const R g, const R (&w0)[NDIM + 2], co
     for (int c = 0; c < NC; ++c) {
         const R dj = minmod(w1[c] - w0[c], w2[c] - w1[c]);
         const R dj1 = minmod(w2[c] - w1[c], w3[c] - w2[c]);
-        wl[c] = w1[c] + R(0.5) * dj;
-        wr[c] = w2[c] - R(0.5) * dj1;
+        wl[c] = Ops<R>::fma(R(0.5), dj, w1[c]);
+        wr[c] = Ops<R>::fma(R(-0.5), dj1, w2[c]);
     }
     R L[NT + 3], Rs[NT + 3], Fn[NT + 3];
     L[0] = wl[0];
@@ -250,7 +297,7 @@ __device__ __forceinline__ void load_w(const Geo& g, const double* __restrict__ 
     double u[NC], w[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) u[c] = U[c * g.ncells + cell];
-    bad |= !cons_to_prim<NDIM>(g.gamma, u, w);
+    bad |= !cons_to_prim<NDIM>(g.gamma - 1.0, u, w);
     if (ax >= 0) {
         const int vc = ax == 0 ? 1 : (ax == 1 ? 2 : NDIM);
 #pragma unroll
@@ -261,18 +308,20 @@ __device__ __forceinline__ void load_w(const Geo& g, const double* __restrict__ 
     for (int c = 0; c < NC; ++c) W[c] = (R)w[c];
 }
 
-// CFL candidate of one cell: min over active kernel axes of dx/(|v| + c).
+// CFL rate of one cell, max over active kernel axes of (|v| + c)/dx; the
+// time step is cfl / (max over cells of the rate), the same quantity as
+// cfl * min over cells and axes of dx / (|v| + c) (Sec. 3.1).
 template <int NDIM>
-__device__ __forceinline__ double cfl_candidate(const Geo& g, const double (&w)[NDIM + 2]) {
-    const double cs = dsqrt(g.gamma * w[NDIM + 1] / w[0]);
-    double best = g.dx[0] / (dabs(w[1]) + cs);
+__device__ __forceinline__ double cfl_rate(const Geo& g, const double (&w)[NDIM + 2]) {
+    const double cs = __builtin_sqrt(g.gamma * w[NDIM + 1] / w[0]);
+    double best = (dabs(w[1]) + cs) * g.inv_dx[0];
     if (NDIM == 3) {
-        const double c1 = g.dx[1] / (dabs(w[2]) + cs);
-        best = c1 < best ? c1 : best;
+        const double c1 = (dabs(w[2]) + cs) * g.inv_dx[1];
+        best = c1 > best ? c1 : best;
     }
     if (NDIM >= 2) {
-        const double c2 = g.dx[2] / (dabs(w[NDIM]) + cs);
-        best = c2 < best ? c2 : best;
+        const double c2 = (dabs(w[NDIM]) + cs) * g.inv_dx[2];
+        best = c2 > best ? c2 : best;
     }
     return best;
 }
@@ -295,17 +344,51 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
     return x * q + (x < r ? x : r) + i;
 }
 
-__device__ __forceinline__ double wave_min(double v) {
+__device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         const double o = __shfl_xor(v, off, 64);
-        v = o < v ? o : v;
+        v = o > v ? o : v;
     }
     return v;
 }
 
 // ------------------------------------------------------------- stage kernel
 
+// Raw conserved values of one cell; cell = plane offset + column offset.
+template <int NC>
+__device__ __forceinline__ void load_u(const double* __restrict__ U, long long N, long long cell,
+                                       double (&u)[NC]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) u[c] = U[c * N + cell];
+}
+
+// Primitive state of raw values u; the velocity along kernel axis vax (if
+// any) takes the boundary treatment vm of the ghost it fills.
+template <int NDIM, typename R>
+__device__ __forceinline__ void to_prim(double gm1, const double (&u)[NDIM + 2], int vax, int vm,
+                                        R (&W)[NDIM + 2], bool& bad) {
+    constexpr int NC = NDIM + 2;
+    double w[NC];
+    bad |= !cons_to_prim<NDIM>(gm1, u, w);
+    if (vax >= 0) {
+        const int vc = vax == 0 ? 1 : (vax == 1 ? 2 : NDIM);
+#pragma unroll
+        for (int c = 1; c <= NDIM; ++c)
+            if (c == vc) w[c] = apply_vmode(w[c], vm);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) W[c] = (R)w[c];
+}
+
+// One stage over a TX x TY tile column and a chunk of kz planes.
+//
+// Software pipeline per plane k (kernel z): raw U of the interior plane k+3
+// and of the halo cells of plane k+1 are loaded one iteration before they are
+// converted, and U at plane k for the update is loaded at the top of the
+// iteration and used after the flux phase, so global loads stay in flight
+// across the two LDS barriers.  Each thread owns at most one halo cell of
+// the plane (4 TX + 4 TY <= TX TY).
 template <int NDIM, typename R, int MODE, int TX, int TY>
 __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
     constexpr int NC = NDIM + 2;
@@ -313,10 +396,14 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
     constexpr bool HZ = (NDIM >= 2);
     constexpr int NT = TX * TY;
     static_assert(HY || TY == 1, "tile rows need a second in-plane axis");
+    static_assert(4 * TX + (HY ? 4 * TY : 0) <= NT || !HY, "one halo cell per thread");
+    static_assert(HY || TX >= 4, "one halo cell per thread");
 
     const Geo& g = a.geo;
     const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
     const long long N = g.ncells;
+    const long long P = (long long)n0 * n1;  // plane stride
+    const double gm1 = g.gamma - 1.0;
 
     int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tix = b % a.tiles_x;
@@ -330,63 +417,110 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const bool act = lx < ax && ly < ay;
-    const int gx = x0 + lx, gy = y0 + ly;
+    const long long col = (long long)(y0 + ly) * n0 + (x0 + lx);
+
+    // this thread's halo cell (tile coordinates hx, hy), resolved once
+    bool hact = false;
+    int hx = 0, hy = 0, hvax = -1, hvm = VM_NONE;
+    long long hcol = 0;
+    {
+        const int nhx = 4 * ay;
+        const int nhy = HY ? 4 * ax : 0;
+        if (tid < nhx) {
+            const int q = tid & 3;
+            hy = tid >> 2;
+            hx = q < 2 ? q - 2 : ax + (q - 2);
+            hact = true;
+        } else if (tid < nhx + nhy) {
+            const int h2 = tid - nhx, q = h2 & 3;
+            hx = h2 >> 2;
+            hy = q < 2 ? q - 2 : ay + (q - 2);
+            hact = true;
+        }
+        if (hact) {
+            int X = x0 + hx, Y = y0 + hy;
+            if (X < 0 || X >= n0) {
+                X = resolve(g, 0, X, hvm);
+                hvax = 0;
+            } else if (Y < 0 || Y >= n1) {
+                Y = resolve(g, 1, Y, hvm);
+                hvax = 1;
+            }
+            hcol = (long long)Y * n0 + X;
+        }
+    }
 
     const double dt = a.use_device_dt ? device_dt(a.ctrl, a.t_end) : a.dt_host;
     const double lam0 = dt / g.dx[0];
     const double lam1 = dt / g.dx[1];
     const double lam2 = dt / g.dx[2];
-    const R gr = (R)g.gamma;
+    const Gas<R> gr = make_gas<R>(g.gamma);
 
     __shared__ R sW[NC][TY + 4][TX + 4];
     __shared__ R sFx[NC][TY][TX + 1];
     __shared__ R sFy[HY ? NC : 1][HY ? TY + 1 : 1][TX];
 
     bool bad = false;
-    double dtmin = __longlong_as_double((long long)kInfBits);
+    double rate = 0.0;
     R wq[5][NC];
     R fzl[NC];
+    double ui[NC];  // raw interior plane in flight (HZ)
+    double uh[NC];  // raw halo cell in flight
+
+    // interior plane z (any z: outside the mesh it is a ghost plane)
+    auto load_interior = [&](int z, double (&u)[NC], int& vm) {
+        vm = VM_NONE;
+        int zr = z;
+        if (z < 0 || z >= n2) zr = resolve(g, 2, z, vm);
+        load_u<NC>(a.in, N, (long long)zr * P + col, u);
+    };
+
     if (HZ && act) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) load_w<NDIM, R>(g, a.in, gx, gy, z0 - 2 + s, wq[s], bad);
+        for (int s = 0; s < 4; ++s) {
+            int vm;
+            double u[NC];
+            load_interior(z0 - 2 + s, u, vm);
+            to_prim<NDIM, R>(gm1, u, vm == VM_NONE ? -1 : 2, vm, wq[s], bad);
+        }
         face_flux<NDIM, 2, R>(gr, wq[0], wq[1], wq[2], wq[3], fzl);
     }
+    int vmi = VM_NONE;
+    if (HZ && act) load_interior(z0 + 2, ui, vmi);
+    if (hact) load_u<NC>(a.in, N, (long long)z0 * P + hcol, uh);
 
     for (int k = z0; k < z1; ++k) {
+        // loads for the update of plane k, consumed after the flux phase
+        double uin[NC], ubase[NC];
+        if (act && MODE != MODE_RHS) {
+            load_u<NC>(a.in, N, (long long)k * P + col, uin);
+            if (MODE == MODE_STAGE2) load_u<NC>(a.base, N, (long long)k * P + col, ubase);
+        }
+        // convert what arrived, then start the next plane's loads
         R wc[NC];
         if (act) {
             if (HZ) {
-                load_w<NDIM, R>(g, a.in, gx, gy, k + 2, wq[4], bad);
+                to_prim<NDIM, R>(gm1, ui, vmi == VM_NONE ? -1 : 2, vmi, wq[4], bad);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) wc[c] = wq[2][c];
             } else {
-                load_w<NDIM, R>(g, a.in, gx, gy, k, wc, bad);
+                double u[NC];
+                load_u<NC>(a.in, N, (long long)k * P + col, u);
+                to_prim<NDIM, R>(gm1, u, -1, VM_NONE, wc, bad);
             }
 #pragma unroll
             for (int c = 0; c < NC; ++c) sW[c][ly + 2][lx + 2] = wc[c];
         }
-        // halo of plane k: two columns left/right of each active row, two
-        // rows below/above each active column
-        {
-            const int nhx = 4 * ay;
-            const int nhy = HY ? 4 * ax : 0;
-            for (int h = tid; h < nhx + nhy; h += NT) {
-                int hx, hy;
-                if (h < nhx) {
-                    const int q = h & 3;
-                    hy = h >> 2;
-                    hx = q < 2 ? q - 2 : ax + (q - 2);
-                } else {
-                    const int h2 = h - nhx, q = h2 & 3;
-                    hx = h2 >> 2;
-                    hy = q < 2 ? q - 2 : ay + (q - 2);
-                }
-                R wh[NC];
-                load_w<NDIM, R>(g, a.in, x0 + hx, y0 + hy, k, wh, bad);
+        if (hact) {
+            R wh[NC];
+            to_prim<NDIM, R>(gm1, uh, hvax, hvm, wh, bad);
 #pragma unroll
-                for (int c = 0; c < NC; ++c) sW[c][hy + 2][hx + 2] = wh[c];
-            }
+            for (int c = 0; c < NC; ++c) sW[c][hy + 2][hx + 2] = wh[c];
+            if (k + 1 < z1) load_u<NC>(a.in, N, (long long)(k + 1) * P + hcol, uh);
         }
+        // plane k+3 is W(k'+2) of the next iteration k' = k+1; it lies at most
+        // two planes outside the mesh only while that iteration exists
+        if (HZ && act && k + 1 < z1) load_interior(k + 3, ui, vmi);
         __syncthreads();
 
         // x faces: face i separates tile columns i-1 and i; LDS columns i..i+3
@@ -434,17 +568,17 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
 #pragma unroll
                     for (int c = 0; c < NC; ++c) sFx[c][e][TX] = F[c];
                 } else if (HY) {
-                    const int col = e - ex;
+                    const int cl = e - ex;
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
-                        w0[c] = sW[c][TY][col + 2];
-                        w1[c] = sW[c][TY + 1][col + 2];
-                        w2[c] = sW[c][TY + 2][col + 2];
-                        w3[c] = sW[c][TY + 3][col + 2];
+                        w0[c] = sW[c][TY][cl + 2];
+                        w1[c] = sW[c][TY + 1][cl + 2];
+                        w2[c] = sW[c][TY + 2][cl + 2];
+                        w3[c] = sW[c][TY + 3][cl + 2];
                     }
                     face_flux<NDIM, 1, R>(gr, w0, w1, w2, w3, F);
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) sFy[HY ? c : 0][HY ? TY : 0][col] = F[c];
+                    for (int c = 0; c < NC; ++c) sFy[HY ? c : 0][HY ? TY : 0][cl] = F[c];
                 }
             }
         }
@@ -453,7 +587,7 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
         __syncthreads();
 
         if (act) {
-            const long long cell = ((long long)k * n1 + gy) * n0 + gx;
+            const long long cell = (long long)k * P + col;
             double unew[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
@@ -463,22 +597,21 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
                     acc = acc + lam1 * ((double)sFy[HY ? c : 0][HY ? ly : 0][lx] -
                                         (double)sFy[HY ? c : 0][HY ? ly + 1 : 0][lx]);
                 if (HZ) acc = acc + lam2 * ((double)fzl[c] - (double)fzh[c]);
-                const long long o = c * N + cell;
                 double r;
                 if (MODE == MODE_RHS)
                     r = acc;
                 else if (MODE == MODE_STAGE1)
-                    r = a.in[o] + acc;
+                    r = uin[c] + acc;
                 else
-                    r = 0.5 * a.base[o] + 0.5 * (a.in[o] + acc);
-                a.out[o] = r;
+                    r = 0.5 * ubase[c] + 0.5 * (uin[c] + acc);
+                a.out[c * N + cell] = r;
                 unew[c] = r;
             }
             if (MODE == MODE_STAGE2 && a.want_dt) {
                 double w[NC];
-                bad |= !cons_to_prim<NDIM>(g.gamma, unew, w);
-                const double cand = cfl_candidate<NDIM>(g, w);
-                dtmin = cand < dtmin ? cand : dtmin;
+                bad |= !cons_to_prim<NDIM>(gm1, unew, w);
+                const double cr = cfl_rate<NDIM>(g, w);
+                rate = cr > rate ? cr : rate;
             }
         }
         if (HZ) {
@@ -494,13 +627,13 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
     if (bad) atomicOr(&a.ctrl->flags, FLAG_NONPHYSICAL);
     if (MODE == MODE_STAGE2 && a.want_dt) {
         __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
-        dtmin = wave_min(dtmin);
-        if ((tid & 63) == 0) red[tid >> 6] = dtmin;
+        rate = wave_max(rate);
+        if ((tid & 63) == 0) red[tid >> 6] = rate;
         __syncthreads();
         if (tid == 0) {
             double m = red[0];
-            for (int i = 1; i < NT / 64; ++i) m = red[i] < m ? red[i] : m;
-            atomicMin(&a.ctrl->dtmin_bits, (unsigned long long)__double_as_longlong(m));
+            for (int i = 1; i < NT / 64; ++i) m = red[i] > m ? red[i] : m;
+            atomicMax(&a.ctrl->rate_bits, (unsigned long long)__double_as_longlong(m));
         }
     }
 }
@@ -510,26 +643,26 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
 template <int NDIM>
 __global__ __launch_bounds__(256) void dt_kernel(Geo g, const double* __restrict__ U, Ctrl* ctrl) {
     constexpr int NC = NDIM + 2;
-    double best = __longlong_as_double((long long)kInfBits);
+    double best = 0.0;
     bool bad = false;
     for (long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x; cell < g.ncells;
          cell += (long long)gridDim.x * blockDim.x) {
         double u[NC], w[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) u[c] = U[c * g.ncells + cell];
-        bad |= !cons_to_prim<NDIM>(g.gamma, u, w);
-        const double cand = cfl_candidate<NDIM>(g, w);
-        best = cand < best ? cand : best;
+        bad |= !cons_to_prim<NDIM>(g.gamma - 1.0, u, w);
+        const double cr = cfl_rate<NDIM>(g, w);
+        best = cr > best ? cr : best;
     }
     if (bad) atomicOr(&ctrl->flags, FLAG_NONPHYSICAL);
     __shared__ double red[4];
-    best = wave_min(best);
+    best = wave_max(best);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
     __syncthreads();
     if (threadIdx.x == 0) {
         double m = red[0];
-        for (int i = 1; i < 4; ++i) m = red[i] < m ? red[i] : m;
-        atomicMin(&ctrl->dtmin_bits, (unsigned long long)__double_as_longlong(m));
+        for (int i = 1; i < 4; ++i) m = red[i] > m ? red[i] : m;
+        atomicMax(&ctrl->rate_bits, (unsigned long long)__double_as_longlong(m));
     }
 }
 
@@ -542,15 +675,15 @@ __global__ void ctrl_kernel(Ctrl* c, int op, double a0, double a1, double cfl) {
             c->flags = 0;
             c->dt_valid = 0;
             c->dt_raw = 0.0;
-            c->dtmin_bits = kInfBits;
+            c->rate_bits = 0ull;
             break;
         case CTRL_RESET_MIN:
-            c->dtmin_bits = kInfBits;
+            c->rate_bits = 0ull;
             break;
         case CTRL_FINALIZE_DT:
-            c->dt_raw = cfl * __longlong_as_double((long long)c->dtmin_bits);
+            c->dt_raw = cfl / __longlong_as_double((long long)c->rate_bits);
             c->dt_valid = 1;
-            c->dtmin_bits = kInfBits;
+            c->rate_bits = 0ull;
             break;
         case CTRL_FINALIZE_STEP: {
             const double t_end = a1;
@@ -560,9 +693,9 @@ __global__ void ctrl_kernel(Ctrl* c, int op, double a0, double a1, double cfl) {
                 c->t = last ? t_end : c->t + dt;
                 c->steps += 1;
             }
-            c->dt_raw = cfl * __longlong_as_double((long long)c->dtmin_bits);
+            c->dt_raw = cfl / __longlong_as_double((long long)c->rate_bits);
             c->dt_valid = 1;
-            c->dtmin_bits = kInfBits;
+            c->rate_bits = 0ull;
             break;
         }
         case CTRL_ADVANCE_T:
@@ -739,7 +872,7 @@ __global__ __launch_bounds__(256) void riemann_kernel(double gamma, long long n,
             L[c] = (R)WL[c * n + i];
             Rr[c] = (R)WR[c * n + i];
         }
-        hllc<R, NT>((R)gamma, L, Rr, Fo);
+        hllc<R, NT>(make_gas<R>(gamma), L, Rr, Fo);
 #pragma unroll
         for (int c = 0; c < NC; ++c) F[c * n + i] = (double)Fo[c];
     }
@@ -762,7 +895,7 @@ template <int NDIM, typename R, int MODE>
 hipError_t launch_stage_tile(const Tile& t, StageArgs a, hipStream_t s) {
     if constexpr (NDIM == 3) {
         if (t.tx == 32 && t.ty == 8) return launch_stage_t<NDIM, R, MODE, 32, 8>(a, s);
-        if (t.tx == 64 && t.ty == 4) return launch_stage_t<NDIM, R, MODE, 64, 4>(a, s);
+        if (t.tx == 64 && t.ty == 8) return launch_stage_t<NDIM, R, MODE, 64, 8>(a, s);
         if (t.tx == 16 && t.ty == 16) return launch_stage_t<NDIM, R, MODE, 16, 16>(a, s);
         return hipErrorInvalidValue;
     } else {
@@ -798,16 +931,19 @@ Tile default_tile(const Geo& g, int precision) {
     if (g.ndim == 3) {
         t.tx = 32;
         t.ty = 8;
-        t.kz = 32;
     } else if (g.ndim == 2) {
         t.tx = g.n[0] >= 256 ? 256 : (g.n[0] >= 128 ? 128 : 64);
         t.ty = 1;
-        t.kz = 32;
     } else {
         t.tx = 64;
         t.ty = 1;
-        t.kz = 1;
     }
+    // chunk length along the marching axis: about 1024 work-groups, chunks of
+    // 16..64 planes (shorter chunks re-read more ghost planes)
+    const long long cols = (long long)((g.n[0] + t.tx - 1) / t.tx) * ((g.n[1] + t.ty - 1) / t.ty);
+    long long kz = (g.n[2] * cols + 1023) / 1024;
+    kz = kz < 16 ? 16 : (kz > 64 ? 64 : kz);
+    t.kz = g.ndim == 1 ? 1 : (int)kz;
     return t;
 }
 

@@ -93,11 +93,13 @@ Geo make_geo(const hydro_config* c) {
         if (map[k] >= 0) {
             g.n[k] = c->n[map[k]];
             g.dx[k] = dx[map[k]];
+            g.inv_dx[k] = 1.0 / dx[map[k]];
             g.bc[k][0] = c->bc[map[k]][0];
             g.bc[k][1] = c->bc[map[k]][1];
         } else {
             g.n[k] = 1;
             g.dx[k] = 1.0;
+            g.inv_dx[k] = 1.0;
             g.bc[k][0] = g.bc[k][1] = HYDRO_BC_PERIODIC;
         }
     }

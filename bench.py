@@ -39,7 +39,22 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many bytes five times "
+                         "(calibrates the HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(nbytes):
+    import torch
+    n = nbytes // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 8, "launches": 5}), flush=True)
 
 
 def bytes_per_update(ndim):
@@ -122,6 +137,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.copy_bytes:
+        copy_calibration(args.copy_bytes)
+        return
     from paper_2501_02317_amd import hydro as H
     from paper_2501_02317_amd import workloads as wl
 

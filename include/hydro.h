@@ -124,6 +124,15 @@ int hydro_step_auto(hydro_t h, int nsteps, double t_end);
  * FP64 sums in a fixed order (blocks). */
 int hydro_conserved_totals(hydro_t h, double* totals);
 
+/* Run limit kept on the device: device-dt steps (hydro_step_auto, batches)
+ * stop advancing this mesh once max_steps more steps are done (0: no step
+ * limit) or t reaches t_end (0: no time limit; the last step is shortened to
+ * land on it).  Async.  hydro_run_done blocks and reports whether the limit
+ * is reached.  hydro_step_auto replaces the time limit with its own and
+ * clears the step limit. */
+int hydro_set_run_limit(hydro_t h, int64_t max_steps, double t_end);
+int hydro_run_done(hydro_t h, int* done);
+
 /* Simulation time and completed step count (blocks). */
 int hydro_time(hydro_t h, double* t);
 int hydro_steps_done(hydro_t h, int64_t* steps);
@@ -139,6 +148,15 @@ int hydro_stage_rhs(hydro_t h, double dt, double* dU_host);
  * array with n_d + 4 cells on active axes; corner ghosts are set to 0. */
 int hydro_padded_primitive(hydro_t h, double* Wpad_host);
 
+/* Tile of the stage kernel: a work-group covers tx x ty cells of the
+ * (x, y) plane (3-D: 32x8, 64x8 or 16x16; 1-D and 2-D: 64, 128 or 256 by
+ * 1) and marches along the last active axis over chunks of kz >= 1 planes.
+ * Every face flux is the same function of the same inputs for any tile, so
+ * the results are bitwise independent of the tile; only speed changes.
+ * Unsupported shapes return HYDRO_E_INVAL.  hydro_create picks a default. */
+int hydro_set_tile(hydro_t h, int tx, int ty, int kz);
+int hydro_get_tile(hydro_t h, int* tx, int* ty, int* kz);
+
 /* Event timing of the stage kernels, for measurement: after
  * hydro_profile(h, cap) the next cap launches of each stage kernel are
  * bracketed by HIP events on the handle's stream (cap = 0 turns timing off
@@ -151,6 +169,30 @@ int hydro_profile_read(hydro_t h, double* ms_stage1, double* ms_stage2, int64_t*
 int hydro_destroy(hydro_t h);
 
 const char* hydro_strerror(int status);
+
+/*
+ * Batches: many independent meshes (any mix of ndim, sizes, precision and
+ * tiles) advanced together.  The members are existing handles that share one
+ * HIP stream; the batch keeps a descriptor table and a work-group table in a
+ * caller-owned device workspace of hydro_batch_workspace_bytes(n, members)
+ * bytes (0 when the members are invalid: NULL, repeated, broken, or on
+ * different streams).  A batched step is one launch per (ndim, precision,
+ * tile) group for each stage over all members' tiles, then one launch that
+ * advances every member's time and device dt; each member keeps its own dt
+ * and run limit (hydro_set_run_limit), and members that reached it are
+ * skipped.  With use_graph != 0 and a non-default stream, the nsteps-step
+ * sequence is captured once into a HIP graph and replayed (recaptured when
+ * nsteps changes).  hydro_batch_step is async; read results through the
+ * member handles after synchronising the stream.  Results equal those of
+ * stepping each member alone with hydro_step_auto.
+ */
+size_t hydro_batch_workspace_bytes(int n, const hydro_t* members);
+int hydro_batch_create(int n, const hydro_t* members, void* d_workspace, size_t nbytes, int use_graph,
+                       hydro_batch_t* out);
+int hydro_batch_step(hydro_batch_t b, int nsteps);
+/* Number of launch groups, total work-groups per stage, and whether steps run from a graph. */
+int hydro_batch_info(hydro_batch_t b, int* groups, int64_t* workgroups, int* graph);
+int hydro_batch_destroy(hydro_batch_t b);
 
 /* HLLC fluxes of nfaces face-normal state pairs on the device (async on
  * stream): WL, WR, F are device arrays [ntan+3][nfaces] of FP64 holding

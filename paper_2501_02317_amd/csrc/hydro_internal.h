@@ -19,18 +19,23 @@ struct Ctrl {
     unsigned int dt_valid;          // dt_raw belongs to the current state
     unsigned long long steps;       // completed steps
     double sums[2 * kMaxComp];      // totals: (sum, compensation) per component
-    double pad[9];
+    double t_end;                   // run limit in time (0: none)
+    unsigned long long max_steps;   // run limit in steps (0: none)
+    unsigned int done;              // a limit is reached: device-dt stages skip this mesh
+    unsigned int pad0;
+    double pad[6];
 };
 static_assert(sizeof(Ctrl) == 192, "control block layout");
 
 enum : unsigned int { FLAG_NONPHYSICAL = 1u };
 
 enum CtrlOp : int {
-    CTRL_INIT = 0,           // t = a0, steps = 0, flags = 0, dt invalid
+    CTRL_INIT = 0,           // t = a0, steps = 0, flags = 0, dt invalid, no limits
     CTRL_RESET_MIN = 1,      // rate accumulator = 0
     CTRL_FINALIZE_DT = 2,    // dt_raw = cfl / rate, dt valid
-    CTRL_FINALIZE_STEP = 3,  // t += clamped dt (t_end = a1), dt_raw = cfl / rate, reset
+    CTRL_FINALIZE_STEP = 3,  // t += clamped dt, steps += 1, dt_raw = cfl / rate, reset, done
     CTRL_ADVANCE_T = 4,      // t += a0 (host dt), dt invalid
+    CTRL_SET_LIMITS = 5,     // t_end = a0, max_steps = a1 (relative to the steps done), done
 };
 
 // Geometry in kernel axes.  Kernel axis 0 is x.  For 3-D, kernel axes
@@ -60,15 +65,31 @@ struct StageArgs {
     Ctrl* ctrl;
     Geo geo;
     double dt_host;      // dt when use_device_dt == 0
-    double t_end;        // clamp target for the device dt (0: none)
-    int use_device_dt;
+    int use_device_dt;   // dt from ctrl (clamped to its t_end); skip the mesh when done
     int want_dt;         // stage 2: accumulate the next CFL candidate
+    int tiles_x, tiles_y, chunks_z, kz;
+};
+
+// One member of a batch: the stage kernels build StageArgs from it.
+struct MeshDesc {
+    double* U;
+    double* U1;
+    Ctrl* ctrl;
+    Geo geo;
     int tiles_x, tiles_y, chunks_z, kz;
 };
 
 enum StageMode : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2 };
 
 hipError_t launch_stage(int precision, int mode, const Tile& tile, StageArgs a, hipStream_t s);
+// Fill the tiling fields of a descriptor for a tile.
+void plan_tiles(const Geo& g, const Tile& t, int& tiles_x, int& tiles_y, int& chunks_z, int& kz);
+// One stage over every mesh of a group sharing ndim, precision and tile:
+// blk[i] = (member, work-group within the member), nblk entries.
+hipError_t launch_stage_batch(int ndim, int precision, int mode, const Tile& tile, const MeshDesc* d,
+                              const int2* blk, int nblk, hipStream_t s);
+// CTRL_FINALIZE_STEP for members [0, n) of a descriptor table.
+hipError_t launch_ctrl_batch(const MeshDesc* d, int n, hipStream_t s);
 hipError_t launch_dt(const Geo& g, const double* U, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_ctrl(Ctrl* c, int op, double a0, double a1, double cfl, hipStream_t s);
 hipError_t launch_totals(const Geo& g, const double* U, double* partials, int nparts, Ctrl* ctrl,
@@ -81,6 +102,8 @@ hipError_t launch_riemann(int precision, int ntan, double gamma, long long n, co
 
 // Default tile for a mesh (kernel axes) and precision.
 Tile default_tile(const Geo& g, int precision);
+// Whether the stage kernel is compiled for this tile shape.
+bool tile_supported(int ndim, const Tile& t);
 // Number of totals partials the runtime reserves.
 constexpr int kTotalsParts = 1024;
 

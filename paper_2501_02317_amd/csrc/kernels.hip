@@ -42,17 +42,31 @@ __device__ __forceinline__ constexpr int vcomp(int ax) {
     return ax == 0 ? 1 : (ax == 1 ? 2 : NDIM);
 }
 
-// Arithmetic policy.  FP64: IEEE division and square root.  FP32 (the mixed
-// path's reconstruction and Riemann solve): the hardware reciprocal and
-// square root (1 ulp), which the FP32 tolerance of that path absorbs.
+// Arithmetic policy.  FP32 (the mixed path's reconstruction and Riemann
+// solve): the hardware reciprocal and reciprocal square root (1 ulp), which
+// the FP32 tolerance of that path absorbs.  FP64: the hardware estimates
+// refined by two Newton steps each (about 1 ulp), instead of the longer
+// correctly rounded division and square-root sequences.
 template <typename R>
 struct Ops;
 
 template <>
 struct Ops<double> {
-    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-    static __device__ __forceinline__ double sqrt(double x) { return __builtin_sqrt(x); }
     static __device__ __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+    static __device__ __forceinline__ double rcp(double x) {
+        double r = __builtin_amdgcn_rcp(x);
+        double e = __builtin_fma(-x, r, 1.0);
+        r = __builtin_fma(r, e, r);
+        e = __builtin_fma(-x, r, 1.0);
+        return __builtin_fma(r, e, r);
+    }
+    static __device__ __forceinline__ double rsq(double x) {
+        double y = __builtin_amdgcn_rsq(x);
+        double e = __builtin_fma(-x * y, y, 1.0);
+        y = __builtin_fma(0.5 * y, e, y);
+        e = __builtin_fma(-x * y, y, 1.0);
+        return __builtin_fma(0.5 * y, e, y);
+    }
     static __device__ __forceinline__ double max0(double x) { return __builtin_fmax(x, 0.0); }
     // median of (a, b, 0): the minmod of eq. minmod
     static __device__ __forceinline__ double minmod(double a, double b) {
@@ -62,9 +76,9 @@ struct Ops<double> {
 
 template <>
 struct Ops<float> {
-    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
     static __device__ __forceinline__ float max0(float x) { return __builtin_fmaxf(x, 0.0f); }
     static __device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
 };
@@ -72,9 +86,10 @@ struct Ops<float> {
 // Gas constants in the compute precision.
 template <typename R>
 struct Gas {
-    R g;        // gamma
-    R z;        // (gamma + 1) / (2 gamma)
-    R inv_gm1;  // 1 / (gamma - 1)
+    R g;          // gamma
+    R z;          // (gamma + 1) / (2 gamma)
+    R inv_gm1;    // 1 / (gamma - 1)
+    R inv_g_gm1;  // 1 / (gamma (gamma - 1))
 };
 
 template <typename R>
@@ -83,6 +98,7 @@ __device__ __forceinline__ Gas<R> make_gas(double g) {
     o.g = (R)g;
     o.z = (R)((g + 1.0) / (2.0 * g));
     o.inv_gm1 = (R)(1.0 / (g - 1.0));
+    o.inv_g_gm1 = (R)(1.0 / (g * (g - 1.0)));
     return o;
 }
 
@@ -103,7 +119,7 @@ template <int NDIM>
 __device__ __forceinline__ bool cons_to_prim(double gm1, const double (&u)[NDIM + 2],
                                              double (&w)[NDIM + 2]) {
     const double rho = u[0];
-    const double r = 1.0 / rho;
+    const double r = Ops<double>::rcp(rho);
     double msq = 0.0;
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) {
@@ -120,11 +136,15 @@ __device__ __forceinline__ bool cons_to_prim(double gm1, const double (&u)[NDIM 
 }
 
 // HLLC flux in the face-normal frame, W = (rho, u, t_1..t_NT, p).
-//   c_K = sqrt(g p_K / rho_K); p* = max(0, primitive-variable guess);
+//   c_K = sqrt(g p_K / rho_K), evaluated as (g p_K) / sqrt(g p_K rho_K);
+//   p* = max(0, primitive-variable guess);
 //   ds_L = -c_L q_L, ds_R = c_R q_R with q_K = sqrt(1 + z (max(p*/p_K, 1) - 1))
-//   (eq. hllc-mixed-dvel), evaluated as c_K q_K = sqrt(g/rho_K (p_K + z max(p* - p_K, 0)))
-//   so ds_K = c_K exactly when p* <= p_K; s_* from the bracketed form of
-//   eq. hllc-contact-spd; star state and flux of the selected side only.
+//   (eq. hllc-mixed-dvel), evaluated as c_K q_K = a_K / sqrt(a_K rho_K) with
+//   a_K = g (p_K + z max(p* - p_K, 0)), so ds_K = c_K exactly when p* <= p_K;
+//   s_* from the bracketed form of eq. hllc-contact-spd.  Only the selected
+//   side's star state and flux are evaluated; E_K/rho_K = c_K^2/(g (g-1)) +
+//   |v_K|^2 / 2 and one reciprocal of (s_K - s_*) rho_K ds_K serve the star
+//   state, so a face costs six reciprocal(-square-root) evaluations.
 template <typename R, int NT>
 __device__ __forceinline__ void hllc(const Gas<R>& gas, const R (&WL)[NT + 3], const R (&WR)[NT + 3],
                                      R (&F)[NT + 3]) {
@@ -133,14 +153,15 @@ __device__ __forceinline__ void hllc(const Gas<R>& gas, const R (&WL)[NT + 3], c
     const R g = gas.g;
     const R rl = WL[0], ul = WL[1], pl = WL[NC - 1];
     const R rr = WR[0], ur = WR[1], pr = WR[NC - 1];
-    const R ril = O::rcp(rl), rir = O::rcp(rr);
-    const R gil = g * ril, gir = g * rir;
-    const R cl = O::sqrt(gil * pl);
-    const R cr = O::sqrt(gir * pr);
+    const R gpl = g * pl, gpr = g * pr;
+    const R cl = gpl * O::rsq(gpl * rl);
+    const R cr = gpr * O::rsq(gpr * rr);
     const R ppv = R(0.5) * (pl + pr) - R(0.125) * (ur - ul) * (rl + rr) * (cl + cr);
     const R ps = O::max0(ppv);
-    const R dsl = -O::sqrt(gil * O::fma(gas.z, O::max0(ps - pl), pl));
-    const R dsr = O::sqrt(gir * O::fma(gas.z, O::max0(ps - pr), pr));
+    const R al = g * O::fma(gas.z, O::max0(ps - pl), pl);
+    const R ar = g * O::fma(gas.z, O::max0(ps - pr), pr);
+    const R dsl = -(al * O::rsq(al * rl));
+    const R dsr = ar * O::rsq(ar * rr);
     const R sl = ul + dsl;
     const R sr = ur + dsr;
     const R ml = rl * dsl, mr = rr * dsr;  // rho_K ds_K
@@ -151,25 +172,24 @@ __device__ __forceinline__ void hllc(const Gas<R>& gas, const R (&WL)[NT + 3], c
     const bool star = left ? !(sl >= R(0)) : (sr > R(0));
     const R sK = left ? sl : sr;
     const R mK = left ? ml : mr;
-    const R ri = left ? ril : rir;  // 1 / rho_K
+    const R cK = left ? cl : cr;
     R W[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) W[c] = left ? WL[c] : WR[c];
 
     const R rho = W[0], u = W[1], p = W[NC - 1];
     const R mu = rho * u;
-    R ket = R(0);
+    R tsq = R(0);
     R Uk[NC], Fk[NC];
     Uk[0] = rho;
     Uk[1] = mu;
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
-        const R mt = rho * W[2 + k];
-        Uk[2 + k] = mt;
-        ket = O::fma(mt, W[2 + k], ket);
+        Uk[2 + k] = rho * W[2 + k];
+        tsq = O::fma(W[2 + k], W[2 + k], tsq);
     }
-    const R ke2 = O::fma(mu, u, ket);
-    const R E = O::fma(p, gas.inv_gm1, R(0.5) * ke2);
+    const R vsq = O::fma(u, u, tsq);
+    const R E = O::fma(p, gas.inv_gm1, R(0.5) * rho * vsq);
     Uk[NC - 1] = E;
     Fk[0] = mu;
     Fk[1] = O::fma(mu, u, p);
@@ -177,15 +197,19 @@ __device__ __forceinline__ void hllc(const Gas<R>& gas, const R (&WL)[NT + 3], c
     for (int k = 0; k < NT; ++k) Fk[2 + k] = mu * W[2 + k];
     Fk[NC - 1] = (E + p) * u;
 
-    // star state chi (1, s_*, t, E/rho + (s_* - u)(s_* + p/(rho ds))), chi = rho ds / (s - s_*)
-    const R chi = mK * O::rcp(sK - ss);
-    const R e_rho = E * ri;
+    // star state chi (1, s_*, t, E/rho + (s_* - u)(s_* + p/(rho ds))),
+    // chi = rho ds / (s - s_*), with 1/(s - s_*) and 1/(rho ds) from one reciprocal
+    const R t1 = sK - ss;
+    const R q = O::rcp(t1 * mK);
+    const R chi = mK * (mK * q);
+    const R p_m = p * (t1 * q);
+    const R e_rho = O::fma(cK * cK, gas.inv_g_gm1, R(0.5) * vsq);
     R Us[NC];
     Us[0] = chi;
     Us[1] = chi * ss;
 #pragma unroll
     for (int k = 0; k < NT; ++k) Us[2 + k] = chi * W[2 + k];
-    Us[NC - 1] = chi * O::fma(ss - u, O::fma(p, O::rcp(mK), ss), e_rho);
+    Us[NC - 1] = chi * O::fma(ss - u, ss + p_m, e_rho);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const R fs = O::fma(sK, Us[c] - Uk[c], Fk[c]);
@@ -212,6 +236,45 @@ __device__ __forceinline__ void face_flux(const Gas<R>& g, const R (&w0)[NDIM + 
         wl[c] = Ops<R>::fma(R(0.5), dj, w1[c]);
         wr[c] = Ops<R>::fma(R(-0.5), dj1, w2[c]);
     }
+    R L[NT + 3], Rs[NT + 3], Fn[NT + 3];
+    L[0] = wl[0];
+    Rs[0] = wr[0];
+    L[1] = wl[VN];
+    Rs[1] = wr[VN];
+    {
+        int k = 2;
+#pragma unroll
+        for (int e = 1; e <= NDIM; ++e) {
+            if (e == VN) continue;
+            L[k] = wl[e];
+            Rs[k] = wr[e];
+            ++k;
+        }
+    }
+    L[NT + 2] = wl[NC - 1];
+    Rs[NT + 2] = wr[NC - 1];
+    hllc<R, NT>(g, L, Rs, Fn);
+    F[0] = Fn[0];
+    F[VN] = Fn[1];
+    {
+        int k = 2;
+#pragma unroll
+        for (int e = 1; e <= NDIM; ++e) {
+            if (e == VN) continue;
+            F[e] = Fn[k++];
+        }
+    }
+    F[NC - 1] = Fn[NT + 2];
+}
+
+// Flux from already reconstructed face states (global frame) along kernel
+// axis AX: the rotation and HLLC of face_flux without the PLM step.
+template <int NDIM, int AX, typename R>
+__device__ __forceinline__ void face_flux_states(const Gas<R>& g, const R (&wl)[NDIM + 2],
+                                                 const R (&wr)[NDIM + 2], R (&F)[NDIM + 2]) {
+    constexpr int NC = NDIM + 2;
+    constexpr int NT = NDIM - 1;
+    constexpr int VN = vcomp<NDIM>(AX);
     R L[NT + 3], Rs[NT + 3], Fn[NT + 3];
     L[0] = wl[0];
     Rs[0] = wr[0];
@@ -326,13 +389,34 @@ __device__ __forceinline__ double cfl_rate(const Geo& g, const double (&w)[NDIM 
     return best;
 }
 
-__device__ __forceinline__ double device_dt(const Ctrl* c, double t_end) {
+// dt of the next step from the control block: the CFL step, shortened to
+// land on t_end when one is set.
+__device__ __forceinline__ double device_dt(const Ctrl* c) {
     double dt = c->dt_raw;
-    if (t_end > 0.0) {
-        const double rem = t_end - c->t;
+    if (c->t_end > 0.0) {
+        const double rem = c->t_end - c->t;
         if (dt >= rem) dt = rem;
     }
     return dt > 0.0 ? dt : 0.0;
+}
+
+__device__ __forceinline__ void update_done(Ctrl* c) {
+    c->done = (c->t_end > 0.0 && !(c->t < c->t_end)) || (c->max_steps > 0 && c->steps >= c->max_steps);
+}
+
+// Advance time by the step just taken and take the next dt from the rate.
+__device__ __forceinline__ void finalize_step(Ctrl* c, double cfl) {
+    if (c->done) return;
+    const double dt = device_dt(c);
+    const bool last = c->t_end > 0.0 && c->dt_raw >= c->t_end - c->t;
+    if (dt > 0.0) {
+        c->t = last ? c->t_end : c->t + dt;
+        c->steps += 1;
+    }
+    c->dt_raw = cfl / __longlong_as_double((long long)c->rate_bits);
+    c->dt_valid = 1;
+    c->rate_bits = 0ull;
+    update_done(c);
 }
 
 // Work-groups are dispatched round-robin over the 8 XCDs; hand each XCD a
@@ -389,8 +473,15 @@ __device__ __forceinline__ void to_prim(double gm1, const double (&u)[NDIM + 2],
 // iteration and used after the flux phase, so global loads stay in flight
 // across the two LDS barriers.  Each thread owns at most one halo cell of
 // the plane (4 TX + 4 TY <= TX TY).
+// Work-groups per CU the compiler is asked to fit: the FP32 path keeps four
+// 256-thread groups per CU (16 waves); FP64 needs more registers per thread.
+template <typename R, int MODE>
+struct StageOccupancy {
+    static constexpr int kBlocks = sizeof(R) == 4 ? 4 : 2;
+};
+
 template <int NDIM, typename R, int MODE, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
+__device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
     constexpr int NC = NDIM + 2;
     constexpr bool HY = (NDIM == 3);
     constexpr bool HZ = (NDIM >= 2);
@@ -405,7 +496,6 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
     const long long P = (long long)n0 * n1;  // plane stride
     const double gm1 = g.gamma - 1.0;
 
-    int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tix = b % a.tiles_x;
     b /= a.tiles_x;
     const int tiy = b % a.tiles_y;
@@ -450,7 +540,7 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
         }
     }
 
-    const double dt = a.use_device_dt ? device_dt(a.ctrl, a.t_end) : a.dt_host;
+    const double dt = a.use_device_dt ? device_dt(a.ctrl) : a.dt_host;
     const double lam0 = dt / g.dx[0];
     const double lam1 = dt / g.dx[1];
     const double lam2 = dt / g.dx[2];
@@ -462,10 +552,11 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
 
     bool bad = false;
     double rate = 0.0;
-    R wq[5][NC];
-    R fzl[NC];
-    double ui[NC];  // raw interior plane in flight (HZ)
-    double uh[NC];  // raw halo cell in flight
+    // z pipeline entering iteration k: W_k, W_{k+1}, d = W_{k+1} - W_k, the
+    // left state of face k+1/2 (W_k + delta_k / 2) and the flux of face k-1/2
+    R wk[NC], wk1[NC], dk[NC], lz[NC], fzl[NC];
+    double ui[NC];  // raw interior plane k+2 in flight (HZ)
+    int vmi = VM_NONE;
 
     // interior plane z (any z: outside the mesh it is a ghost plane)
     auto load_interior = [&](int z, double (&u)[NC], int& vm) {
@@ -476,33 +567,58 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
     };
 
     if (HZ && act) {
+        R w[4][NC];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             int vm;
             double u[NC];
             load_interior(z0 - 2 + s, u, vm);
-            to_prim<NDIM, R>(gm1, u, vm == VM_NONE ? -1 : 2, vm, wq[s], bad);
+            to_prim<NDIM, R>(gm1, u, vm == VM_NONE ? -1 : 2, vm, w[s], bad);
         }
-        face_flux<NDIM, 2, R>(gr, wq[0], wq[1], wq[2], wq[3], fzl);
+        // planes z0-2 .. z0+1: face z0-1/2 and the left state of face z0+1/2,
+        // in the operations face_flux uses
+        R wl[NC], wr[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const R d0 = w[1][c] - w[0][c], d1 = w[2][c] - w[1][c], d2 = w[3][c] - w[2][c];
+            const R s1 = minmod(d0, d1), s2 = minmod(d1, d2);
+            wl[c] = Ops<R>::fma(R(0.5), s1, w[1][c]);
+            wr[c] = Ops<R>::fma(R(-0.5), s2, w[2][c]);
+            lz[c] = Ops<R>::fma(R(0.5), s2, w[2][c]);
+            wk[c] = w[2][c];
+            wk1[c] = w[3][c];
+            dk[c] = d2;
+        }
+        face_flux_states<NDIM, 2, R>(gr, wl, wr, fzl);
+        load_interior(z0 + 2, ui, vmi);
     }
-    int vmi = VM_NONE;
-    if (HZ && act) load_interior(z0 + 2, ui, vmi);
-    if (hact) load_u<NC>(a.in, N, (long long)z0 * P + hcol, uh);
 
     for (int k = z0; k < z1; ++k) {
-        // loads for the update of plane k, consumed after the flux phase
-        double uin[NC], ubase[NC];
-        if (act && MODE != MODE_RHS) {
-            load_u<NC>(a.in, N, (long long)k * P + col, uin);
-            if (MODE == MODE_STAGE2) load_u<NC>(a.base, N, (long long)k * P + col, ubase);
-        }
-        // convert what arrived, then start the next plane's loads
         R wc[NC];
+        R fzh[NC];
         if (act) {
             if (HZ) {
-                to_prim<NDIM, R>(gm1, ui, vmi == VM_NONE ? -1 : 2, vmi, wq[4], bad);
+                // W_{k+2} arrived: z face k+1/2 from (W_k, W_{k+1}, W_{k+2})
+                R w2[NC], wr[NC];
+                to_prim<NDIM, R>(gm1, ui, vmi == VM_NONE ? -1 : 2, vmi, w2, bad);
+                // plane k+3 is W_{k'+2} of the next iteration k' = k+1; it lies at
+                // most two planes outside the mesh only while that iteration exists
+                if (k + 1 < z1) load_interior(k + 3, ui, vmi);
 #pragma unroll
-                for (int c = 0; c < NC; ++c) wc[c] = wq[2][c];
+                for (int c = 0; c < NC; ++c) {
+                    const R d2 = w2[c] - wk1[c];
+                    const R s1 = minmod(dk[c], d2);
+                    wr[c] = Ops<R>::fma(R(-0.5), s1, wk1[c]);
+                    const R lnext = Ops<R>::fma(R(0.5), s1, wk1[c]);
+                    wc[c] = wk[c];
+                    dk[c] = d2;
+                    wk[c] = wk1[c];
+                    wk1[c] = w2[c];
+                    w2[c] = lnext;  // reuse: left state of face k+3/2
+                }
+                face_flux_states<NDIM, 2, R>(gr, lz, wr, fzh);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) lz[c] = w2[c];
             } else {
                 double u[NC];
                 load_u<NC>(a.in, N, (long long)k * P + col, u);
@@ -512,15 +628,13 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
             for (int c = 0; c < NC; ++c) sW[c][ly + 2][lx + 2] = wc[c];
         }
         if (hact) {
+            double uh[NC];
             R wh[NC];
+            load_u<NC>(a.in, N, (long long)k * P + hcol, uh);
             to_prim<NDIM, R>(gm1, uh, hvax, hvm, wh, bad);
 #pragma unroll
             for (int c = 0; c < NC; ++c) sW[c][hy + 2][hx + 2] = wh[c];
-            if (k + 1 < z1) load_u<NC>(a.in, N, (long long)(k + 1) * P + hcol, uh);
         }
-        // plane k+3 is W(k'+2) of the next iteration k' = k+1; it lies at most
-        // two planes outside the mesh only while that iteration exists
-        if (HZ && act && k + 1 < z1) load_interior(k + 3, ui, vmi);
         __syncthreads();
 
         // x faces: face i separates tile columns i-1 and i; LDS columns i..i+3
@@ -582,12 +696,13 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
                 }
             }
         }
-        R fzh[NC];
-        if (HZ && act) face_flux<NDIM, 2, R>(gr, wq[1], wq[2], wq[3], wq[4], fzh);
         __syncthreads();
 
         if (act) {
             const long long cell = (long long)k * P + col;
+            double uin[NC], ubase[NC];
+            if (MODE != MODE_RHS) load_u<NC>(a.in, N, cell, uin);
+            if (MODE == MODE_STAGE2) load_u<NC>(a.base, N, cell, ubase);
             double unew[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
@@ -613,14 +728,10 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
                 const double cr = cfl_rate<NDIM>(g, w);
                 rate = cr > rate ? cr : rate;
             }
-        }
-        if (HZ) {
+            if (HZ) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) fzl[c] = fzh[c];
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < NC; ++c) wq[s][c] = wq[s + 1][c];
+                for (int c = 0; c < NC; ++c) fzl[c] = fzh[c];
+            }
         }
     }
 
@@ -636,6 +747,43 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
             atomicMax(&a.ctrl->rate_bits, (unsigned long long)__double_as_longlong(m));
         }
     }
+}
+
+template <int NDIM, typename R, int MODE, int TX, int TY>
+__global__ __launch_bounds__(TX * TY, (StageOccupancy<R, MODE>::kBlocks)) void stage_kernel(StageArgs a) {
+    if (a.use_device_dt && a.ctrl->done) return;  // uniform over the grid
+    stage_body<NDIM, R, MODE, TX, TY>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Batched stage: work-group -> (member, work-group of the member) from a
+// table; members that reached their run limit are skipped.
+template <int NDIM, typename R, int MODE, int TX, int TY>
+__global__ __launch_bounds__(TX * TY, (StageOccupancy<R, MODE>::kBlocks)) void stage_kernel_batch(
+    const MeshDesc* __restrict__ descs, const int2* __restrict__ blk) {
+    const int2 e = blk[xcd_remap(blockIdx.x, gridDim.x)];
+    const MeshDesc& d = descs[e.x];
+    if (d.ctrl->done) return;  // uniform over the work-group
+    StageArgs a;
+    a.ctrl = d.ctrl;
+    a.geo = d.geo;
+    a.dt_host = 0.0;
+    a.use_device_dt = 1;
+    a.tiles_x = d.tiles_x;
+    a.tiles_y = d.tiles_y;
+    a.chunks_z = d.chunks_z;
+    a.kz = d.kz;
+    if (MODE == MODE_STAGE1) {
+        a.in = d.U;
+        a.base = d.U;
+        a.out = d.U1;
+        a.want_dt = 0;
+    } else {
+        a.in = d.U1;
+        a.base = d.U;
+        a.out = d.U;
+        a.want_dt = 1;
+    }
+    stage_body<NDIM, R, MODE, TX, TY>(a, e.y);
 }
 
 // ------------------------------------------------------------- small kernels
@@ -676,6 +824,9 @@ __global__ void ctrl_kernel(Ctrl* c, int op, double a0, double a1, double cfl) {
             c->dt_valid = 0;
             c->dt_raw = 0.0;
             c->rate_bits = 0ull;
+            c->t_end = 0.0;
+            c->max_steps = 0ull;
+            c->done = 0;
             break;
         case CTRL_RESET_MIN:
             c->rate_bits = 0ull;
@@ -685,27 +836,27 @@ __global__ void ctrl_kernel(Ctrl* c, int op, double a0, double a1, double cfl) {
             c->dt_valid = 1;
             c->rate_bits = 0ull;
             break;
-        case CTRL_FINALIZE_STEP: {
-            const double t_end = a1;
-            const double dt = device_dt(c, t_end);
-            const bool last = t_end > 0.0 && c->dt_raw >= t_end - c->t;
-            if (dt > 0.0) {
-                c->t = last ? t_end : c->t + dt;
-                c->steps += 1;
-            }
-            c->dt_raw = cfl / __longlong_as_double((long long)c->rate_bits);
-            c->dt_valid = 1;
-            c->rate_bits = 0ull;
+        case CTRL_FINALIZE_STEP:
+            finalize_step(c, cfl);
             break;
-        }
         case CTRL_ADVANCE_T:
             c->t = c->t + a0;
             c->steps += 1;
             c->dt_valid = 0;
             break;
+        case CTRL_SET_LIMITS:
+            c->t_end = a0;
+            c->max_steps = a1 > 0.0 ? c->steps + (unsigned long long)a1 : 0ull;
+            update_done(c);
+            break;
         default:
             break;
     }
+}
+
+__global__ void ctrl_batch_kernel(const MeshDesc* __restrict__ d, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) finalize_step(d[i].ctrl, d[i].geo.cfl);
 }
 
 // Neumaier-compensated accumulator combined pairwise in a fixed tree.
@@ -884,43 +1035,70 @@ int grid_for(long long work, int block, int cap) {
     return (int)(gb < cap ? gb : cap);
 }
 
+// Launch context: a single mesh (args) or a batch group (descriptor table).
+struct LaunchCtx {
+    const StageArgs* a;
+    const MeshDesc* d;
+    const int2* blk;
+    int nblk;
+};
+
 template <int NDIM, typename R, int MODE, int TX, int TY>
-hipError_t launch_stage_t(StageArgs a, hipStream_t s) {
-    const int nb = a.tiles_x * a.tiles_y * a.chunks_z;
-    hipLaunchKernelGGL((stage_kernel<NDIM, R, MODE, TX, TY>), dim3(nb), dim3(TX * TY), 0, s, a);
+hipError_t launch_stage_t(const LaunchCtx& L, hipStream_t s) {
+    if (L.a) {
+        const StageArgs& a = *L.a;
+        const int nb = a.tiles_x * a.tiles_y * a.chunks_z;
+        hipLaunchKernelGGL((stage_kernel<NDIM, R, MODE, TX, TY>), dim3(nb), dim3(TX * TY), 0, s, a);
+    } else {
+        if (L.nblk <= 0) return hipSuccess;
+        hipLaunchKernelGGL((stage_kernel_batch<NDIM, R, MODE, TX, TY>), dim3(L.nblk), dim3(TX * TY), 0, s,
+                           L.d, L.blk);
+    }
     return hipGetLastError();
 }
 
 template <int NDIM, typename R, int MODE>
-hipError_t launch_stage_tile(const Tile& t, StageArgs a, hipStream_t s) {
+hipError_t launch_stage_tile(const Tile& t, const LaunchCtx& L, hipStream_t s) {
     if constexpr (NDIM == 3) {
-        if (t.tx == 32 && t.ty == 8) return launch_stage_t<NDIM, R, MODE, 32, 8>(a, s);
-        if (t.tx == 64 && t.ty == 8) return launch_stage_t<NDIM, R, MODE, 64, 8>(a, s);
-        if (t.tx == 16 && t.ty == 16) return launch_stage_t<NDIM, R, MODE, 16, 16>(a, s);
+        if (t.tx == 32 && t.ty == 8) return launch_stage_t<NDIM, R, MODE, 32, 8>(L, s);
+        if (t.tx == 64 && t.ty == 8) return launch_stage_t<NDIM, R, MODE, 64, 8>(L, s);
+        if (t.tx == 16 && t.ty == 16) return launch_stage_t<NDIM, R, MODE, 16, 16>(L, s);
         return hipErrorInvalidValue;
     } else {
         if (t.ty != 1) return hipErrorInvalidValue;
-        if (t.tx == 64) return launch_stage_t<NDIM, R, MODE, 64, 1>(a, s);
-        if (t.tx == 128) return launch_stage_t<NDIM, R, MODE, 128, 1>(a, s);
-        if (t.tx == 256) return launch_stage_t<NDIM, R, MODE, 256, 1>(a, s);
+        if (t.tx == 64) return launch_stage_t<NDIM, R, MODE, 64, 1>(L, s);
+        if (t.tx == 128) return launch_stage_t<NDIM, R, MODE, 128, 1>(L, s);
+        if (t.tx == 256) return launch_stage_t<NDIM, R, MODE, 256, 1>(L, s);
         return hipErrorInvalidValue;
     }
 }
 
 template <int NDIM, typename R>
-hipError_t launch_stage_mode(int mode, const Tile& t, StageArgs a, hipStream_t s) {
+hipError_t launch_stage_mode(int mode, const Tile& t, const LaunchCtx& L, hipStream_t s) {
     switch (mode) {
-        case MODE_RHS: return launch_stage_tile<NDIM, R, MODE_RHS>(t, a, s);
-        case MODE_STAGE1: return launch_stage_tile<NDIM, R, MODE_STAGE1>(t, a, s);
-        case MODE_STAGE2: return launch_stage_tile<NDIM, R, MODE_STAGE2>(t, a, s);
+        case MODE_RHS:
+            if (!L.a) return hipErrorInvalidValue;
+            return launch_stage_tile<NDIM, R, MODE_RHS>(t, L, s);
+        case MODE_STAGE1: return launch_stage_tile<NDIM, R, MODE_STAGE1>(t, L, s);
+        case MODE_STAGE2: return launch_stage_tile<NDIM, R, MODE_STAGE2>(t, L, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int NDIM>
-hipError_t launch_stage_prec(int precision, int mode, const Tile& t, StageArgs a, hipStream_t s) {
-    if (precision == 0) return launch_stage_mode<NDIM, double>(mode, t, a, s);
-    return launch_stage_mode<NDIM, float>(mode, t, a, s);
+hipError_t launch_stage_prec(int precision, int mode, const Tile& t, const LaunchCtx& L, hipStream_t s) {
+    if (precision == 0) return launch_stage_mode<NDIM, double>(mode, t, L, s);
+    return launch_stage_mode<NDIM, float>(mode, t, L, s);
+}
+
+hipError_t launch_any(int ndim, int precision, int mode, const Tile& t, const LaunchCtx& L,
+                      hipStream_t s) {
+    switch (ndim) {
+        case 1: return launch_stage_prec<1>(precision, mode, t, L, s);
+        case 2: return launch_stage_prec<2>(precision, mode, t, L, s);
+        case 3: return launch_stage_prec<3>(precision, mode, t, L, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -938,27 +1116,46 @@ Tile default_tile(const Geo& g, int precision) {
         t.tx = 64;
         t.ty = 1;
     }
-    // chunk length along the marching axis: about 1024 work-groups, chunks of
+    // chunk length along the marching axis: about 2048 work-groups, chunks of
     // 16..64 planes (shorter chunks re-read more ghost planes)
     const long long cols = (long long)((g.n[0] + t.tx - 1) / t.tx) * ((g.n[1] + t.ty - 1) / t.ty);
-    long long kz = (g.n[2] * cols + 1023) / 1024;
+    long long kz = (g.n[2] * cols + 2047) / 2048;
     kz = kz < 16 ? 16 : (kz > 64 ? 64 : kz);
     t.kz = g.ndim == 1 ? 1 : (int)kz;
     return t;
 }
 
+bool tile_supported(int ndim, const Tile& t) {
+    if (t.kz < 1) return false;
+    if (ndim == 3)
+        return (t.tx == 32 && t.ty == 8) || (t.tx == 64 && t.ty == 8) || (t.tx == 16 && t.ty == 16);
+    return t.ty == 1 && (t.tx == 64 || t.tx == 128 || t.tx == 256);
+}
+
+void plan_tiles(const Geo& g, const Tile& t, int& tiles_x, int& tiles_y, int& chunks_z, int& kz) {
+    tiles_x = (g.n[0] + t.tx - 1) / t.tx;
+    tiles_y = (g.n[1] + t.ty - 1) / t.ty;
+    kz = t.kz < 1 ? 1 : (t.kz > g.n[2] ? g.n[2] : t.kz);
+    chunks_z = (g.n[2] + kz - 1) / kz;
+}
+
 hipError_t launch_stage(int precision, int mode, const Tile& t, StageArgs a, hipStream_t s) {
-    const Geo& g = a.geo;
-    a.tiles_x = (g.n[0] + t.tx - 1) / t.tx;
-    a.tiles_y = (g.n[1] + t.ty - 1) / t.ty;
-    a.kz = t.kz < 1 ? 1 : (t.kz > g.n[2] ? g.n[2] : t.kz);
-    a.chunks_z = (g.n[2] + a.kz - 1) / a.kz;
-    switch (g.ndim) {
-        case 1: return launch_stage_prec<1>(precision, mode, t, a, s);
-        case 2: return launch_stage_prec<2>(precision, mode, t, a, s);
-        case 3: return launch_stage_prec<3>(precision, mode, t, a, s);
-        default: return hipErrorInvalidValue;
-    }
+    plan_tiles(a.geo, t, a.tiles_x, a.tiles_y, a.chunks_z, a.kz);
+    LaunchCtx L{&a, nullptr, nullptr, 0};
+    return launch_any(a.geo.ndim, precision, mode, t, L, s);
+}
+
+hipError_t launch_stage_batch(int ndim, int precision, int mode, const Tile& tile, const MeshDesc* d,
+                              const int2* blk, int nblk, hipStream_t s) {
+    if (mode != MODE_STAGE1 && mode != MODE_STAGE2) return hipErrorInvalidValue;
+    LaunchCtx L{nullptr, d, blk, nblk};
+    return launch_any(ndim, precision, mode, tile, L, s);
+}
+
+hipError_t launch_ctrl_batch(const MeshDesc* d, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ctrl_batch_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_dt(const Geo& g, const double* U, Ctrl* ctrl, hipStream_t s) {

@@ -2,10 +2,12 @@
 // carving, stream-ordered launches and the device-resident time step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "hydro.h"
 #include "hydro_internal.h"
@@ -25,6 +27,7 @@ struct hydro_ctx {
     Ctrl* ctrl;
     Ctrl* host_ctrl;  // pinned mirror for reads
     bool broken;
+    bool dt_valid;    // ctrl->dt_raw belongs to the current state (host-side knowledge)
     // optional event timing of the stage launches
     int prof_cap;
     int prof_n[2];
@@ -149,12 +152,11 @@ hipError_t timed_stage(hydro_t h, int mode, const StageArgs& a) {
 }
 
 // One Heun step: stage 1 then stage 2 in place, dt either from the host or
-// from the device control block.
-hipError_t enqueue_step(hydro_t h, bool device_dt, double dt, double t_end) {
+// from the device control block (clamped to the run limit kept there).
+hipError_t enqueue_step(hydro_t h, bool device_dt, double dt) {
     StageArgs a = stage_args(h);
     a.use_device_dt = device_dt ? 1 : 0;
     a.dt_host = dt;
-    a.t_end = t_end;
     a.in = h->U;
     a.out = h->U1;
     hipError_t e = timed_stage(h, MODE_STAGE1, a);
@@ -165,7 +167,7 @@ hipError_t enqueue_step(hydro_t h, bool device_dt, double dt, double t_end) {
     a.want_dt = device_dt ? 1 : 0;
     e = timed_stage(h, MODE_STAGE2, a);
     if (e != hipSuccess) return e;
-    if (device_dt) return launch_ctrl(h->ctrl, CTRL_FINALIZE_STEP, 0.0, t_end, h->cfg.cfl, h->stream);
+    if (device_dt) return launch_ctrl(h->ctrl, CTRL_FINALIZE_STEP, 0.0, 0.0, h->cfg.cfl, h->stream);
     return launch_ctrl(h->ctrl, CTRL_ADVANCE_T, dt, 0.0, h->cfg.cfl, h->stream);
 }
 
@@ -173,6 +175,7 @@ hipError_t enqueue_dt(hydro_t h) {
     hipError_t e = launch_ctrl(h->ctrl, CTRL_RESET_MIN, 0.0, 0.0, h->cfg.cfl, h->stream);
     if (e == hipSuccess) e = launch_dt(h->geo, h->U, h->ctrl, h->stream);
     if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_FINALIZE_DT, 0.0, 0.0, h->cfg.cfl, h->stream);
+    if (e == hipSuccess) h->dt_valid = true;
     return e;
 }
 
@@ -233,6 +236,7 @@ int hydro_set_state(hydro_t h, const double* U_host) {
     const size_t bytes = (size_t)h->ncomp * h->geo.ncells * sizeof(double);
     hipError_t e = hipMemcpyAsync(h->U, U_host, bytes, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_INIT, 0.0, 0.0, h->cfg.cfl, h->stream);
+    h->dt_valid = false;
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     return fail(h, e);
 }
@@ -245,6 +249,7 @@ int hydro_set_primitive(hydro_t h, const double* W_host) {
     hipError_t e = hipMemcpyAsync(h->U1, W_host, bytes, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = launch_prim_to_cons(h->geo, h->U1, h->U, h->stream);
     if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_INIT, 0.0, 0.0, h->cfg.cfl, h->stream);
+    h->dt_valid = false;
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     return fail(h, e);
 }
@@ -271,7 +276,7 @@ int hydro_cfl_dt(hydro_t h, double* dt) {
     int rc = usable(h);
     if (rc) return rc;
     if (!dt) return HYDRO_E_INVAL;
-    hipError_t e = enqueue_dt(h);
+    hipError_t e = h->dt_valid ? hipSuccess : enqueue_dt(h);
     if (e != hipSuccess) return fail(h, e);
     rc = read_ctrl(h);
     if (rc) return rc;
@@ -283,7 +288,8 @@ int hydro_step(hydro_t h, double dt) {
     int rc = usable(h);
     if (rc) return rc;
     if (!(dt > 0.0) || !std::isfinite(dt)) return HYDRO_E_INVAL;
-    return fail(h, enqueue_step(h, false, dt, 0.0));
+    h->dt_valid = false;
+    return fail(h, enqueue_step(h, false, dt));
 }
 
 int hydro_step_auto(hydro_t h, int nsteps, double t_end) {
@@ -291,11 +297,30 @@ int hydro_step_auto(hydro_t h, int nsteps, double t_end) {
     if (rc) return rc;
     if (nsteps < 0 || !(t_end >= 0.0) || !std::isfinite(t_end)) return HYDRO_E_INVAL;
     if (nsteps == 0) return HYDRO_OK;
-    // The first dt of a run comes from a standalone reduction over the
-    // current state; every later dt from the previous step's epilogue.
-    hipError_t e = enqueue_dt(h);
-    for (int s = 0; s < nsteps && e == hipSuccess; ++s) e = enqueue_step(h, true, 0.0, t_end);
+    // The dt of the first step comes from a standalone reduction when the
+    // state changed since the last device-dt step; every later dt from the
+    // previous step's epilogue.
+    hipError_t e = launch_ctrl(h->ctrl, CTRL_SET_LIMITS, t_end, 0.0, h->cfg.cfl, h->stream);
+    if (e == hipSuccess && !h->dt_valid) e = enqueue_dt(h);
+    for (int s = 0; s < nsteps && e == hipSuccess; ++s) e = enqueue_step(h, true, 0.0);
     return fail(h, e);
+}
+
+int hydro_set_run_limit(hydro_t h, int64_t max_steps, double t_end) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (max_steps < 0 || !(t_end >= 0.0) || !std::isfinite(t_end)) return HYDRO_E_INVAL;
+    return fail(h, launch_ctrl(h->ctrl, CTRL_SET_LIMITS, t_end, (double)max_steps, h->cfg.cfl, h->stream));
+}
+
+int hydro_run_done(hydro_t h, int* done) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!done) return HYDRO_E_INVAL;
+    rc = read_ctrl(h);
+    if (rc && rc != HYDRO_E_NONPHYSICAL) return rc;
+    *done = h->host_ctrl->done ? 1 : 0;
+    return rc;
 }
 
 int hydro_conserved_totals(hydro_t h, double* totals) {
@@ -363,6 +388,28 @@ int hydro_padded_primitive(hydro_t h, double* Wpad_host) {
     }
     if (e != hipSuccess) return fail(h, e);
     return read_ctrl(h);
+}
+
+int hydro_set_tile(hydro_t h, int tx, int ty, int kz) {
+    int rc = usable(h);
+    if (rc) return rc;
+    Tile t;
+    t.tx = tx;
+    t.ty = ty;
+    t.kz = kz;
+    if (!tile_supported(h->cfg.ndim, t)) return HYDRO_E_INVAL;
+    h->tile = t;
+    return HYDRO_OK;
+}
+
+int hydro_get_tile(hydro_t h, int* tx, int* ty, int* kz) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!tx || !ty || !kz) return HYDRO_E_INVAL;
+    *tx = h->tile.tx;
+    *ty = h->tile.ty;
+    *kz = h->tile.kz;
+    return HYDRO_OK;
 }
 
 namespace {
@@ -459,6 +506,217 @@ int hydro_riemann_fluxes(int precision, int ntan, double gamma, int64_t nfaces, 
     hipError_t e = launch_riemann(precision, ntan, gamma, (long long)nfaces, d_WL, d_WR, d_F,
                                   (hipStream_t)hip_stream);
     return e == hipSuccess ? HYDRO_OK : HYDRO_E_DEVICE;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+struct hydro_batch_ctx {
+    std::vector<hydro_t> members;
+    hipStream_t stream;
+    MeshDesc* d_desc;  // descriptor table in the caller's workspace
+    int2* d_blk;       // work-group table, grouped
+    struct Group {
+        int ndim, precision;
+        Tile tile;
+        int blk_off, nblk;
+    };
+    std::vector<Group> groups;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int graph_steps;
+    bool use_graph;
+    bool broken;
+};
+
+namespace {
+
+struct BatchPlan {
+    std::vector<MeshDesc> desc;
+    std::vector<int2> blk;
+    std::vector<hydro_batch_ctx::Group> groups;
+};
+
+// Members grouped by (ndim, precision, tile); each group's work-groups are
+// contiguous in the table, members in the caller's order within a group.
+bool plan_batch(int n, const hydro_t* members, BatchPlan& P) {
+    P.desc.resize(n);
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) {
+        const hydro_t h = members[i];
+        MeshDesc& d = P.desc[i];
+        d.U = h->U;
+        d.U1 = h->U1;
+        d.ctrl = h->ctrl;
+        d.geo = h->geo;
+        plan_tiles(h->geo, h->tile, d.tiles_x, d.tiles_y, d.chunks_z, d.kz);
+        order[i] = i;
+    }
+    auto key = [&](int i) {
+        const hydro_t h = members[i];
+        return std::make_tuple(h->cfg.ndim, h->cfg.precision, h->tile.tx, h->tile.ty);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
+    for (int idx = 0; idx < n; ++idx) {
+        const int i = order[idx];
+        const hydro_t h = members[i];
+        if (P.groups.empty() || key(order[idx - 1]) != key(i)) {
+            hydro_batch_ctx::Group g;
+            g.ndim = h->cfg.ndim;
+            g.precision = h->cfg.precision;
+            g.tile = h->tile;
+            g.blk_off = (int)P.blk.size();
+            g.nblk = 0;
+            P.groups.push_back(g);
+        }
+        const MeshDesc& d = P.desc[i];
+        const long long nb = (long long)d.tiles_x * d.tiles_y * d.chunks_z;
+        if (nb > (1ll << 28) || (long long)P.blk.size() + nb > (1ll << 30)) return false;
+        for (int b = 0; b < (int)nb; ++b) P.blk.push_back(make_int2(i, b));
+        P.groups.back().nblk += (int)nb;
+    }
+    return true;
+}
+
+size_t batch_bytes(const BatchPlan& P) {
+    return align_up(P.desc.size() * sizeof(MeshDesc)) + align_up(P.blk.size() * sizeof(int2));
+}
+
+bool members_ok(int n, const hydro_t* members) {
+    if (n < 1 || !members) return false;
+    for (int i = 0; i < n; ++i) {
+        if (!members[i] || members[i]->broken) return false;
+        if (members[i]->stream != members[0]->stream) return false;
+        for (int j = 0; j < i; ++j)
+            if (members[j] == members[i]) return false;
+    }
+    return true;
+}
+
+// One batched Heun step: every group's stage 1, every group's stage 2, then
+// each member's time / dt update.
+hipError_t enqueue_batch_step(hydro_batch_t b) {
+    hipError_t e = hipSuccess;
+    for (const auto& g : b->groups)
+        if (e == hipSuccess)
+            e = launch_stage_batch(g.ndim, g.precision, MODE_STAGE1, g.tile, b->d_desc, b->d_blk + g.blk_off,
+                                   g.nblk, b->stream);
+    for (const auto& g : b->groups)
+        if (e == hipSuccess)
+            e = launch_stage_batch(g.ndim, g.precision, MODE_STAGE2, g.tile, b->d_desc, b->d_blk + g.blk_off,
+                                   g.nblk, b->stream);
+    if (e == hipSuccess) e = launch_ctrl_batch(b->d_desc, (int)b->members.size(), b->stream);
+    return e;
+}
+
+void drop_graph(hydro_batch_t b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_steps = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hydro_batch_workspace_bytes(int n, const hydro_t* members) {
+    if (!members_ok(n, members)) return 0;
+    BatchPlan P;
+    if (!plan_batch(n, members, P)) return 0;
+    return batch_bytes(P);
+}
+
+int hydro_batch_create(int n, const hydro_t* members, void* d_workspace, size_t nbytes, int use_graph,
+                       hydro_batch_t* out) {
+    if (!out || !members_ok(n, members) || !d_workspace) return HYDRO_E_INVAL;
+    if (((uintptr_t)d_workspace) % kAlign != 0) return HYDRO_E_INVAL;
+    BatchPlan P;
+    if (!plan_batch(n, members, P)) return HYDRO_E_INVAL;
+    if (nbytes < batch_bytes(P)) return HYDRO_E_INVAL;
+    hydro_batch_ctx* b = new (std::nothrow) hydro_batch_ctx;
+    if (!b) return HYDRO_E_NOMEM;
+    b->members.assign(members, members + n);
+    b->stream = members[0]->stream;
+    b->d_desc = (MeshDesc*)d_workspace;
+    b->d_blk = (int2*)((char*)d_workspace + align_up(P.desc.size() * sizeof(MeshDesc)));
+    b->groups = P.groups;
+    b->graph = nullptr;
+    b->exec = nullptr;
+    b->graph_steps = 0;
+    // stream capture needs a stream other than the legacy default stream
+    b->use_graph = use_graph != 0 && b->stream != nullptr;
+    b->broken = false;
+    hipError_t e = hipMemcpyAsync(b->d_desc, P.desc.data(), P.desc.size() * sizeof(MeshDesc),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_blk, P.blk.data(), P.blk.size() * sizeof(int2), hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        delete b;
+        return HYDRO_E_DEVICE;
+    }
+    *out = b;
+    return HYDRO_OK;
+}
+
+int hydro_batch_step(hydro_batch_t b, int nsteps) {
+    if (!b) return HYDRO_E_INVAL;
+    if (b->broken) return HYDRO_E_STATE;
+    if (nsteps < 0) return HYDRO_E_INVAL;
+    if (nsteps == 0) return HYDRO_OK;
+    hipError_t e = hipSuccess;
+    for (hydro_t h : b->members) {
+        if (h->broken) return HYDRO_E_STATE;
+        if (!h->dt_valid && e == hipSuccess) e = enqueue_dt(h);
+    }
+    if (e == hipSuccess && b->use_graph) {
+        if (b->graph_steps != nsteps) {
+            drop_graph(b);
+            e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+            for (int s = 0; s < nsteps && e == hipSuccess; ++s) e = enqueue_batch_step(b);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+            if (e == hipSuccess) {
+                b->graph = g;
+                b->graph_steps = nsteps;
+            } else if (g) {
+                (void)hipGraphDestroy(g);
+            }
+        }
+        if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
+    } else {
+        for (int s = 0; s < nsteps && e == hipSuccess; ++s) e = enqueue_batch_step(b);
+    }
+    if (e != hipSuccess) {
+        b->broken = true;
+        return HYDRO_E_DEVICE;
+    }
+    for (hydro_t h : b->members) h->dt_valid = true;
+    return HYDRO_OK;
+}
+
+int hydro_batch_info(hydro_batch_t b, int* groups, int64_t* workgroups, int* graph) {
+    if (!b || !groups || !workgroups || !graph) return HYDRO_E_INVAL;
+    *groups = (int)b->groups.size();
+    int64_t nb = 0;
+    for (const auto& g : b->groups) nb += g.nblk;
+    *workgroups = nb;
+    *graph = b->use_graph ? 1 : 0;
+    return HYDRO_OK;
+}
+
+int hydro_batch_destroy(hydro_batch_t b) {
+    if (!b) return HYDRO_E_INVAL;
+    if (!b->broken) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    delete b;
+    return HYDRO_OK;
 }
 
 }  // extern "C"

@@ -46,9 +46,18 @@ _SIG = {
     "hydro_steps_done": (C.c_int, [_h, C.POINTER(C.c_int64)]),
     "hydro_stage_rhs": (C.c_int, [_h, C.c_double, _dp]),
     "hydro_padded_primitive": (C.c_int, [_h, _dp]),
+    "hydro_set_tile": (C.c_int, [_h, C.c_int, C.c_int, C.c_int]),
+    "hydro_get_tile": (C.c_int, [_h, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "hydro_profile": (C.c_int, [_h, C.c_int]),
     "hydro_profile_read": (C.c_int, [_h, _dp, _dp, C.POINTER(C.c_int64)]),
+    "hydro_set_run_limit": (C.c_int, [_h, C.c_int64, C.c_double]),
+    "hydro_run_done": (C.c_int, [_h, C.POINTER(C.c_int)]),
     "hydro_destroy": (C.c_int, [_h]),
+    "hydro_batch_workspace_bytes": (C.c_size_t, [C.c_int, C.POINTER(_h)]),
+    "hydro_batch_create": (C.c_int, [C.c_int, C.POINTER(_h), _vp, C.c_size_t, C.c_int, C.POINTER(_h)]),
+    "hydro_batch_step": (C.c_int, [_h, C.c_int]),
+    "hydro_batch_info": (C.c_int, [_h, C.POINTER(C.c_int), C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
+    "hydro_batch_destroy": (C.c_int, [_h]),
     "hydro_strerror": (C.c_char_p, [C.c_int]),
     "hydro_riemann_fluxes": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_int64, _vp, _vp, _vp, _vp]),
 }
@@ -166,6 +175,16 @@ class Hydro:
     def step_auto(self, nsteps, t_end=0.0):
         _check(_lib.hydro_step_auto(self._h, int(nsteps), float(t_end)), "hydro_step_auto")
 
+    def set_run_limit(self, max_steps=0, t_end=0.0):
+        """Device-dt steps stop advancing this mesh after max_steps more steps
+        or at t_end (0: no limit)."""
+        _check(_lib.hydro_set_run_limit(self._h, int(max_steps), float(t_end)), "hydro_set_run_limit")
+
+    def run_done(self):
+        d = C.c_int()
+        _check(_lib.hydro_run_done(self._h, C.byref(d)), "hydro_run_done")
+        return bool(d.value)
+
     def time(self):
         t = C.c_double()
         _check(_lib.hydro_time(self._h, C.byref(t)), "hydro_time")
@@ -194,6 +213,15 @@ class Hydro:
         _check(_lib.hydro_padded_primitive(self._h, _ptr(Wp)), "hydro_padded_primitive")
         return Wp
 
+    # ---- tiling
+    def set_tile(self, tx, ty, kz):
+        _check(_lib.hydro_set_tile(self._h, int(tx), int(ty), int(kz)), "hydro_set_tile")
+
+    def get_tile(self):
+        tx, ty, kz = C.c_int(), C.c_int(), C.c_int()
+        _check(_lib.hydro_get_tile(self._h, C.byref(tx), C.byref(ty), C.byref(kz)), "hydro_get_tile")
+        return tx.value, ty.value, kz.value
+
     # ---- measurement
     def profile(self, cap):
         """Bracket the next cap launches of each stage kernel with HIP events."""
@@ -210,6 +238,46 @@ class Hydro:
         if getattr(self, "_h", None):
             _lib.hydro_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent meshes stepped together (one launch per group and stage,
+    optionally replayed from a HIP graph).  All members share one stream."""
+
+    def __init__(self, members, use_graph=True):
+        import torch
+        self.members = list(members)
+        n = len(self.members)
+        arr = (_h * n)(*[m._h for m in self.members])
+        self._arr = arr
+        nbytes = int(_lib.hydro_batch_workspace_bytes(n, arr))
+        if nbytes == 0:
+            raise HydroError(E_INVAL, "batch members (NULL, repeated, broken or on different streams)")
+        dev = self.members[0].device
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        b = _h()
+        _check(_lib.hydro_batch_create(n, arr, _vp(self.workspace.data_ptr()), nbytes, 1 if use_graph else 0,
+                                       C.byref(b)), "hydro_batch_create")
+        self._b = b
+
+    def step(self, nsteps):
+        _check(_lib.hydro_batch_step(self._b, int(nsteps)), "hydro_batch_step")
+
+    def info(self):
+        g, w, gr = C.c_int(), C.c_int64(), C.c_int()
+        _check(_lib.hydro_batch_info(self._b, C.byref(g), C.byref(w), C.byref(gr)), "hydro_batch_info")
+        return {"groups": g.value, "workgroups": w.value, "graph": bool(gr.value)}
+
+    def close(self):
+        if getattr(self, "_b", None):
+            _lib.hydro_batch_destroy(self._b)
+            self._b = None
 
     def __del__(self):
         try:

@@ -68,3 +68,13 @@ def test_create_rejects_bad_arguments_without_device(H):
     assert H._lib.hydro_riemann_fluxes(3, 1, 1.4, 10, None, None, None, None) == H.E_INVAL
     assert H._lib.hydro_riemann_fluxes(0, 1, 1.4, 0, None, None, None, None) == H.OK
     assert "non-physical" in H.strerror(H.E_NONPHYSICAL)
+
+
+def test_batch_rejects_invalid_members_without_device(H):
+    arr = (C.c_void_p * 2)(None, None)
+    assert H._lib.hydro_batch_workspace_bytes(2, arr) == 0
+    assert H._lib.hydro_batch_workspace_bytes(0, arr) == 0
+    b = C.c_void_p()
+    assert H._lib.hydro_batch_create(2, arr, C.c_void_p(256), 1 << 20, 1, C.byref(b)) == H.E_INVAL
+    assert H._lib.hydro_batch_step(None, 1) == H.E_INVAL
+    assert H._lib.hydro_batch_destroy(None) == H.E_INVAL

@@ -39,6 +39,10 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 2-D workload")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--serve-count", type=int, default=300)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes five times "
                          "(calibrates the HBM byte counters) and exit")
@@ -97,6 +101,81 @@ def run_precision(H, case, precision, steps, warmup):
         "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS, "totals": T.tolist(),
         "step_frac": rate * bytes_per_update(case.ndim) / 1e9 / HBM_PEAK_GBS,
     }
+
+
+def run_batch(H, wl, count, steps, precision):
+    """Ragged 2-D shear-layer meshes: one batched, graph-replayed run against
+    the same meshes stepped one at a time (hydro_step_auto per mesh)."""
+    import torch
+    cases = wl.batch_cases(count=count, seed=401, steps=steps)
+    s = torch.cuda.Stream()
+    ms = [H.Hydro(c.n, c.gamma, c.cfl, precision=precision, lo=c.lo, hi=c.hi, bc=c.bc, stream=s)
+          for c in cases]
+
+    def reset():
+        for h, c in zip(ms, cases):
+            h.set_primitive(c.W)
+            h.set_run_limit(steps, 0.0)
+        s.synchronize()
+
+    cells = sum(c.ncells for c in cases)
+    b = H.Batch(ms, use_graph=True)
+    reset()
+    b.step(steps)                                 # warm-up: captures the graph
+    s.synchronize()
+    reset()
+    t0 = time.perf_counter()
+    b.step(steps)
+    s.synchronize()
+    t_batch = time.perf_counter() - t0
+    done, st, flags = b.status()
+    assert all(done) and not any(flags)
+    info = b.info()
+    b.close()
+    reset()
+    t0 = time.perf_counter()
+    for h in ms:
+        h.step_auto(steps)
+    s.synchronize()
+    t_one = time.perf_counter() - t0
+    for h in ms:
+        h.close()
+    return {"meshes": count, "cells": cells, "steps": steps,
+            "precision": "mixed" if precision == H.MIXED else "fp64",
+            "batched_cell_updates_per_s": cells * steps / t_batch,
+            "one_at_a_time_cell_updates_per_s": cells * steps / t_one,
+            "speedup": t_one / t_batch, "batched_s": t_batch, "one_at_a_time_s": t_one,
+            "launch_groups": info["groups"], "graph": info["graph"]}
+
+
+def run_serving(count):
+    """Served capacity at saturation (all requests at t = 0) against the same
+    requests served one at a time; then a Poisson stream offered at 0.8 x the
+    measured capacity, with p50/p99 completion latency."""
+    from paper_2501_02317_amd import serving as S
+    sat = S.request_stream(count, 1.0, seed=502)
+    for r in sat:
+        r.arrival = 0.0
+    work = sum(r.cells * r.steps for r in sat)
+    t_served = S.Server(96 << 30, steps_per_iter=16).run(sat, time_limit=300.0)
+    capacity = work / t_served
+    t0 = time.perf_counter()
+    for r in S.request_stream(count, 1.0, seed=502):
+        S.serve_alone(r)
+    t_one = time.perf_counter() - t0
+    rate = 0.8 * capacity / S.mean_work()
+    reqs = S.request_stream(count, rate, seed=501)
+    srv = S.Server(96 << 30, steps_per_iter=16)
+    srv.run(reqs, time_limit=300.0)
+    rep = S.latency_report(reqs)
+    rep["offered_rate_per_s"] = rate
+    rep["offered_load_frac"] = 0.8
+    rep["requests"] = count
+    rep["iterations"] = srv.iterations
+    rep["saturated_cell_updates_per_s"] = capacity
+    rep["one_at_a_time_cell_updates_per_s"] = work / t_one
+    rep["saturated_speedup"] = t_one / t_served
+    return rep
 
 
 def cpu_baseline(case):
@@ -189,6 +268,16 @@ def main():
     }
     if "mixed" in res and "fp64" in res:
         out["mixed_over_fp64"] = res["mixed"]["rate"] / res["fp64"]["rate"]
+    if not args.no_batch:
+        print("[bench] batched 2-D workload ...", file=sys.stderr, flush=True)
+        out["batch"] = run_batch(H, wl, args.batch_count, 300, H.MIXED)
+        print(f"[bench] batch: {out['batch']['batched_cell_updates_per_s']:.3e} vs one-at-a-time "
+              f"{out['batch']['one_at_a_time_cell_updates_per_s']:.3e}", file=sys.stderr, flush=True)
+    if not args.no_serve:
+        print("[bench] serving ...", file=sys.stderr, flush=True)
+        out["serving"] = run_serving(args.serve_count)
+        print(f"[bench] serving: p50 {out['serving']['p50_s']:.3f} s p99 {out['serving']['p99_s']:.3f} s",
+              file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("[bench] oracle cpu baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case)

@@ -99,8 +99,15 @@ int hydro_set_state(hydro_t h, const double* U_host);
  * the device (m = rho v, E = p/(gamma-1) + (1/2) sum m v); reset t to 0. */
 int hydro_set_primitive(hydro_t h, const double* W_host);
 
+/* As hydro_set_primitive from a device array of the same layout (async;
+ * the array must stay valid until the stream reaches this call). */
+int hydro_set_primitive_device(hydro_t h, const double* d_W);
+
 /* Copy the current conserved state out (blocks). */
 int hydro_get_state(hydro_t h, double* U_host);
+
+/* Copy the current conserved state to a device array (async). */
+int hydro_get_state_device(hydro_t h, double* d_U);
 
 /* Device address of the current conserved state (valid until the next step). */
 int hydro_state_device(hydro_t h, const double** d_U);
@@ -190,6 +197,10 @@ size_t hydro_batch_workspace_bytes(int n, const hydro_t* members);
 int hydro_batch_create(int n, const hydro_t* members, void* d_workspace, size_t nbytes, int use_graph,
                        hydro_batch_t* out);
 int hydro_batch_step(hydro_batch_t b, int nsteps);
+/* Per-member run-limit flag (done[i] = 1 once member i reached its limit),
+ * optional completed step counts and sticky error flags (bit 0:
+ * non-physical state); blocks on the batch stream. */
+int hydro_batch_status(hydro_batch_t b, int* done, int64_t* steps, int* flags);
 /* Number of launch groups, total work-groups per stage, and whether steps run from a graph. */
 int hydro_batch_info(hydro_batch_t b, int* groups, int64_t* workgroups, int* graph);
 int hydro_batch_destroy(hydro_batch_t b);

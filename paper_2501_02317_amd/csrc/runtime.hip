@@ -254,6 +254,24 @@ int hydro_set_primitive(hydro_t h, const double* W_host) {
     return fail(h, e);
 }
 
+int hydro_set_primitive_device(hydro_t h, const double* d_W) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!d_W) return HYDRO_E_INVAL;
+    hipError_t e = launch_prim_to_cons(h->geo, d_W, h->U, h->stream);
+    if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_INIT, 0.0, 0.0, h->cfg.cfl, h->stream);
+    h->dt_valid = false;
+    return fail(h, e);
+}
+
+int hydro_get_state_device(hydro_t h, double* d_U) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!d_U) return HYDRO_E_INVAL;
+    const size_t bytes = (size_t)h->ncomp * h->geo.ncells * sizeof(double);
+    return fail(h, hipMemcpyAsync(d_U, h->U, bytes, hipMemcpyDeviceToDevice, h->stream));
+}
+
 int hydro_get_state(hydro_t h, double* U_host) {
     int rc = usable(h);
     if (rc) return rc;
@@ -528,6 +546,7 @@ struct hydro_batch_ctx {
     int graph_steps;
     bool use_graph;
     bool broken;
+    Ctrl* h_ctrl;  // pinned staging for member status reads
 };
 
 namespace {
@@ -649,6 +668,11 @@ int hydro_batch_create(int n, const hydro_t* members, void* d_workspace, size_t 
     // stream capture needs a stream other than the legacy default stream
     b->use_graph = use_graph != 0 && b->stream != nullptr;
     b->broken = false;
+    b->h_ctrl = nullptr;
+    if (hipHostMalloc((void**)&b->h_ctrl, (size_t)n * sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+        delete b;
+        return HYDRO_E_NOMEM;
+    }
     hipError_t e = hipMemcpyAsync(b->d_desc, P.desc.data(), P.desc.size() * sizeof(MeshDesc),
                                   hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
@@ -656,6 +680,7 @@ int hydro_batch_create(int n, const hydro_t* members, void* d_workspace, size_t 
                            b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
+        (void)hipHostFree(b->h_ctrl);
         delete b;
         return HYDRO_E_DEVICE;
     }
@@ -701,6 +726,27 @@ int hydro_batch_step(hydro_batch_t b, int nsteps) {
     return HYDRO_OK;
 }
 
+int hydro_batch_status(hydro_batch_t b, int* done, int64_t* steps, int* flags) {
+    if (!b || !done) return HYDRO_E_INVAL;
+    if (b->broken) return HYDRO_E_STATE;
+    const int n = (int)b->members.size();
+    // one asynchronous 192-byte copy per member into pinned staging, one sync
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(b->h_ctrl + i, b->members[i]->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        b->broken = true;
+        return HYDRO_E_DEVICE;
+    }
+    for (int i = 0; i < n; ++i) {
+        done[i] = b->h_ctrl[i].done ? 1 : 0;
+        if (steps) steps[i] = (int64_t)b->h_ctrl[i].steps;
+        if (flags) flags[i] = (int)b->h_ctrl[i].flags;
+    }
+    return HYDRO_OK;
+}
+
 int hydro_batch_info(hydro_batch_t b, int* groups, int64_t* workgroups, int* graph) {
     if (!b || !groups || !workgroups || !graph) return HYDRO_E_INVAL;
     *groups = (int)b->groups.size();
@@ -715,6 +761,7 @@ int hydro_batch_destroy(hydro_batch_t b) {
     if (!b) return HYDRO_E_INVAL;
     if (!b->broken) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
+    (void)hipHostFree(b->h_ctrl);
     delete b;
     return HYDRO_OK;
 }

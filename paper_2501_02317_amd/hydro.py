@@ -37,6 +37,8 @@ _SIG = {
     "hydro_set_state": (C.c_int, [_h, _dp]),
     "hydro_set_primitive": (C.c_int, [_h, _dp]),
     "hydro_get_state": (C.c_int, [_h, _dp]),
+    "hydro_set_primitive_device": (C.c_int, [_h, _vp]),
+    "hydro_get_state_device": (C.c_int, [_h, _vp]),
     "hydro_state_device": (C.c_int, [_h, C.POINTER(_vp)]),
     "hydro_cfl_dt": (C.c_int, [_h, _dp]),
     "hydro_step": (C.c_int, [_h, C.c_double]),
@@ -57,6 +59,7 @@ _SIG = {
     "hydro_batch_create": (C.c_int, [C.c_int, C.POINTER(_h), _vp, C.c_size_t, C.c_int, C.POINTER(_h)]),
     "hydro_batch_step": (C.c_int, [_h, C.c_int]),
     "hydro_batch_info": (C.c_int, [_h, C.POINTER(C.c_int), C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
+    "hydro_batch_status": (C.c_int, [_h, C.POINTER(C.c_int), C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
     "hydro_batch_destroy": (C.c_int, [_h]),
     "hydro_strerror": (C.c_char_p, [C.c_int]),
     "hydro_riemann_fluxes": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_int64, _vp, _vp, _vp, _vp]),
@@ -119,7 +122,7 @@ class Hydro:
     """
 
     def __init__(self, n, gamma, cfl, precision=FP64, lo=None, hi=None, bc=None, device=None,
-                 stream=None):
+                 stream=None, workspace=None):
         import torch
 
         self.cfg = make_config(n, gamma, cfl, precision, lo, hi, bc)
@@ -130,8 +133,15 @@ class Hydro:
         nbytes = workspace_bytes(self.cfg)
         if nbytes == 0:
             raise HydroError(E_INVAL, "invalid configuration")
-        self.device = torch.device(device if device is not None else "cuda")
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if workspace is not None:
+            # caller-provided device memory (uint8 CUDA tensor, >= nbytes, 256-byte aligned)
+            if workspace.numel() < nbytes or workspace.data_ptr() % 256:
+                raise HydroError(E_INVAL, "workspace too small or misaligned")
+            self.device = workspace.device
+            self.workspace = workspace
+        else:
+            self.device = torch.device(device if device is not None else "cuda")
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
@@ -148,6 +158,18 @@ class Hydro:
     def set_primitive(self, W):
         W = np.ascontiguousarray(W, dtype=np.float64).reshape(self.shape)
         _check(_lib.hydro_set_primitive(self._h, _ptr(W)), "hydro_set_primitive")
+
+    def set_primitive_device(self, W):
+        """W: float64 CUDA tensor of shape (ncomp, nz, ny, nx), contiguous.
+        The tensor must stay alive until the stream passes this call."""
+        assert W.is_cuda and W.dtype.is_floating_point and W.is_contiguous()
+        assert tuple(W.shape) == tuple(self.shape)
+        _check(_lib.hydro_set_primitive_device(self._h, _vp(W.data_ptr())), "hydro_set_primitive_device")
+
+    def get_state_device(self, out):
+        """Copy the state into a float64 CUDA tensor (async on the mesh's stream)."""
+        assert out.is_cuda and out.is_contiguous() and tuple(out.shape) == tuple(self.shape)
+        _check(_lib.hydro_get_state_device(self._h, _vp(out.data_ptr())), "hydro_get_state_device")
 
     def get_state(self):
         U = np.empty(self.shape)
@@ -268,6 +290,15 @@ class Batch:
 
     def step(self, nsteps):
         _check(_lib.hydro_batch_step(self._b, int(nsteps)), "hydro_batch_step")
+
+    def status(self):
+        """(done flags, completed steps, error flags) per member; blocks."""
+        n = len(self.members)
+        d = (C.c_int * n)()
+        st = (C.c_int64 * n)()
+        fl = (C.c_int * n)()
+        _check(_lib.hydro_batch_status(self._b, d, st, fl), "hydro_batch_status")
+        return list(d), list(st), list(fl)
 
     def info(self):
         g, w, gr = C.c_int(), C.c_int64(), C.c_int()

@@ -259,3 +259,59 @@ def batch_sizes(count=512, seed=401):
 def batch_cases(count=512, seed=401, steps=300):
     return [shear_layer_2d(nx, ny, seed=4000 + m, steps=steps)
             for m, (nx, ny) in enumerate(batch_sizes(count, seed))]
+
+
+def random_field_device(ndim, n, mach, gamma, seed, kmax=16, sigma=0.1, modes=48, device="cuda"):
+    """Primitive state of a random-field request, generated on the GPU as a
+    sum of seeded random Fourier modes (no FFT plans, so any mesh size costs
+    the same to set up).  Each field is sum_i a_i cos(2 pi k_i . x + phi_i)
+    over `modes` integer wavevectors with 1 <= |k_i| <= kmax, a_i ~ |k_i|^s
+    with s = 0 for the log-density and a shell spectrum k^-2 for each
+    velocity component; log-density std sigma, unit-mean density, zero-mean
+    velocity with rms |v| = mach, p = 1/gamma.  Mode parameters come from a
+    numpy generator seeded with `seed`.  Returns a contiguous float64 CUDA
+    tensor of shape (ndim + 2, nz, ny, nx)."""
+    import torch
+
+    rng = np.random.default_rng(int(seed))
+    kmax = max(1, int(kmax))
+    cand = np.stack(np.meshgrid(*[np.arange(-kmax, kmax + 1)] * ndim, indexing="ij"), -1).reshape(-1, ndim)
+    kn = np.sqrt((cand ** 2).sum(1))
+    cand, kn = cand[(kn >= 1) & (kn <= kmax)], kn[(kn >= 1) & (kn <= kmax)]
+    x = (torch.arange(n, device=device, dtype=torch.float64) + 0.5) / n
+    slope = -2.0 if ndim == 3 else -1.5
+
+    def field(s):
+        pick = rng.integers(0, len(cand), modes)
+        k = cand[pick]
+        a = kn[pick] ** s * rng.standard_normal(modes)
+        ph = rng.uniform(0.0, 2 * np.pi, modes)
+        out = torch.zeros((n,) * ndim, device=device, dtype=torch.float64)
+        for c0 in range(0, modes, 8):
+            kk = torch.as_tensor(k[c0:c0 + 8], dtype=torch.float64, device=device)
+            m = kk.shape[0]
+            arg = torch.as_tensor(ph[c0:c0 + 8], dtype=torch.float64, device=device).view(m, *[1] * ndim)
+            for d in range(ndim):
+                shp = [m] + [1] * ndim
+                shp[1 + d] = n
+                arg = arg + (2 * np.pi) * (kk[:, d].view(m, 1) * x.view(1, n)).view(shp)
+            amp = torch.as_tensor(a[c0:c0 + 8], dtype=torch.float64, device=device).view(m, *[1] * ndim)
+            out += (amp * torch.cos(arg)).sum(0)
+        return out
+
+    s = field(0.0)
+    s = s * (sigma / s.std())
+    rho = torch.exp(s)
+    rho = rho / rho.mean()
+    vel = []
+    for _ in range(ndim):
+        v = field(slope)
+        vel.append(v - v.mean())
+    vrms = torch.sqrt(torch.mean(sum(v * v for v in vel)))
+    vel = [v * (mach / vrms) for v in vel]
+    p = torch.full((n,) * ndim, 1.0 / gamma, device=device, dtype=torch.float64)
+    # fields are indexed (x, y[, z]); the state layout is (z, y, x)
+    stack = torch.stack([rho] + vel + [p])
+    stack = stack.permute(0, *range(ndim, 0, -1))
+    full = (1,) * (3 - ndim) + (n,) * ndim
+    return stack.reshape((ndim + 2,) + full).contiguous()

@@ -1,0 +1,75 @@
+"""Whole-run parity at the benchmark sizes: 128^3 Mach-1 for 200 steps (FP64)
+and 256^3 Mach-2 for 100 steps (FP64 and mixed), GPU against the FP64
+oracle run on the host cores (several minutes of oracle time).
+
+Enabled with HYDRO_FULL_PARITY=1; the default GPU run checks the same
+launch configuration at these sizes on sampled cells after one step
+(test_gpu_parity.test_full_size_one_step_sampled).
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2501_02317_amd import workloads as wl
+from gpu_util import gpu_mesh, oracle_mesh, rel_l1, say
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow,
+              pytest.mark.skipif(os.environ.get("HYDRO_FULL_PARITY") != "1",
+                                 reason="full-size oracle runs take minutes; set HYDRO_FULL_PARITY=1")]
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2501_02317_amd import hydro
+    return hydro
+
+
+CASES = {
+    "c2_128_mach1_200": lambda: wl.turbulence_3d(n=128, mach=1.0, seed=201, steps=200, cfl=0.3),
+    "c3_256_mach2_100": lambda: wl.turbulence_3d(n=256, mach=2.0, seed=301, steps=100, cfl=0.3),
+}
+_oracle_cache = {}
+
+
+def oracle_result(name):
+    if name not in _oracle_cache:
+        c = CASES[name]()
+        m = oracle_mesh(c)
+        U0 = O.prim_to_cons(m, c.W)
+        t0 = time.perf_counter()
+        U, t, s, dts = O.run(m, U0, c.cfl, max_steps=c.steps)
+        el = time.perf_counter() - t0
+        print(f"[oracle] {name}: {s} steps to t={t:.6e} in {el:.1f} s "
+              f"({c.ncells * s / el:.3e} cell-updates/s, OMP_NUM_THREADS={os.environ.get('OMP_NUM_THREADS')})",
+              flush=True)
+        _oracle_cache[name] = (c, m, U0, U, t, s)
+    return _oracle_cache[name]
+
+
+@pytest.mark.parametrize("name,precision,tol", [("c2_128_mach1_200", 0, 1e-12),
+                                                ("c3_256_mach2_100", 0, 1e-12),
+                                                ("c3_256_mach2_100", 1, 1e-5)])
+def test_full_run_against_oracle(H, name, precision, tol):
+    c, m, U0, U_o, t_o, s_o = oracle_result(name)
+    say("full run", name, precision)
+    h = gpu_mesh(c, precision)
+    h.step_auto(c.steps)
+    U = h.get_state()
+    t, s = h.time(), h.steps_done()
+    T = h.totals()
+    h.close()
+    err = rel_l1(U, U_o)
+    T0 = O.totals(m, U0)
+    dV = np.prod(m.dx)
+    drift = np.abs(T - T0) / (dV * np.abs(U0).reshape(m.ncomp, -1).sum(axis=1))
+    print(f"[parity] {name} precision={precision}: relL1 per component {err}, "
+          f"t {t:.15e} vs oracle {t_o:.15e}, steps {s} vs {s_o}, totals drift / (dV sum|U|) {drift}",
+          flush=True)
+    assert s == s_o
+    assert np.all(err <= tol)
+    assert np.all(drift <= 1e-12)

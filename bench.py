@@ -69,6 +69,7 @@ def run_precision(H, case, precision, steps, warmup):
     import torch
     h = H.Hydro(case.n, case.gamma, case.cfl, precision=precision, lo=case.lo, hi=case.hi, bc=case.bc)
     h.set_primitive(case.W)
+    tile, _ = h.autotune(2)        # tuning steps are warm-up steps of the run
     h.step_auto(warmup)
     torch.cuda.synchronize()
     h.set_primitive(case.W)        # timed run starts from the seeded state
@@ -100,6 +101,7 @@ def run_precision(H, case, precision, steps, warmup):
         "stage_ms": [ms1 / max(n1, 1), ms2 / max(n2, 1)], "launches": [n1, n2],
         "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS, "totals": T.tolist(),
         "step_frac": rate * bytes_per_update(case.ndim) / 1e9 / HBM_PEAK_GBS,
+        "tile": list(tile),
     }
 
 
@@ -263,7 +265,8 @@ def main():
                      "stage_ms": head["stage_ms"]},
         "by_precision": {k: {"value": v["rate"], "ms_per_step": v["ms_per_step"],
                              "roofline_frac": v["frac"], "step_roofline_frac": v["step_frac"],
-                             "stage_ms": v["stage_ms"], "achieved_gbs": v["achieved_gbs"]}
+                             "stage_ms": v["stage_ms"], "achieved_gbs": v["achieved_gbs"],
+                             "tile": v["tile"]}
                          for k, v in res.items()},
     }
     if "mixed" in res and "fp64" in res:

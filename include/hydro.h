@@ -164,6 +164,22 @@ int hydro_padded_primitive(hydro_t h, double* Wpad_host);
 int hydro_set_tile(hydro_t h, int tx, int ty, int kz);
 int hydro_get_tile(hydro_t h, int* tx, int* ty, int* kz);
 
+/* The tiles the autotuner tries for a configuration: writes up to max
+ * (tx, ty, kz) triples to tiles[3 * i ...] and returns their total number
+ * (HYDRO_E_INVAL for an invalid configuration or max < 0). */
+int hydro_tile_candidates(const hydro_config* cfg, int* tiles, int max);
+
+/* Autotuner.  Advances the run by steps_per_tile real Heun steps per
+ * candidate tile (device-resident dt as in hydro_step_auto, t_end 0 = no
+ * clamp), each candidate timed with HIP events, then keeps the fastest tile
+ * and returns it with its time per step.  The steps are part of the run
+ * (results do not depend on the tile), so tuning can replace warm-up steps.
+ * Blocks until done.  If the run reached its limit while tuning (timings of
+ * skipped steps mean nothing) the tile is left as it was and the call returns
+ * HYDRO_E_STATE; the handle stays usable.  steps_per_tile in [1, 1000]. */
+int hydro_autotune(hydro_t h, int steps_per_tile, double t_end, int* tx, int* ty, int* kz,
+                   double* ms_per_step);
+
 /* Event timing of the stage kernels, for measurement: after
  * hydro_profile(h, cap) the next cap launches of each stage kernel are
  * bracketed by HIP events on the handle's stream (cap = 0 turns timing off

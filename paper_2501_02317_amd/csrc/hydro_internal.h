@@ -104,6 +104,9 @@ hipError_t launch_riemann(int precision, int ntan, double gamma, long long n, co
 Tile default_tile(const Geo& g, int precision);
 // Whether the stage kernel is compiled for this tile shape.
 bool tile_supported(int ndim, const Tile& t);
+// Tiles the autotuner tries for a mesh (at most max written); returns how
+// many there are.
+int tile_candidates(const Geo& g, Tile* out, int max);
 // Number of totals partials the runtime reserves.
 constexpr int kTotalsParts = 1024;
 

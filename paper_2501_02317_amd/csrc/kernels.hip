@@ -267,6 +267,32 @@ __device__ __forceinline__ void face_flux(const Gas<R>& g, const R (&w0)[NDIM + 
     F[NC - 1] = Fn[NT + 2];
 }
 
+// Flux through an in-plane face of a 3-D tile whose axis (0: x, 1: y) is a
+// run-time value: the same arithmetic as face_flux<3, 0 or 1>, with the
+// rotation done by selects so faces of both axes share one code path.
+template <typename R>
+__device__ __forceinline__ void face_flux_xy(const Gas<R>& g, bool yaxis, const R (&w0)[5], const R (&w1)[5],
+                                             const R (&w2)[5], const R (&w3)[5], R (&F)[5]) {
+    R wl[5], wr[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        const R dj = minmod(w1[c] - w0[c], w2[c] - w1[c]);
+        const R dj1 = minmod(w2[c] - w1[c], w3[c] - w2[c]);
+        wl[c] = Ops<R>::fma(R(0.5), dj, w1[c]);
+        wr[c] = Ops<R>::fma(R(-0.5), dj1, w2[c]);
+    }
+    // normal velocity first, then the other in-plane one, then z
+    R L[5] = {wl[0], yaxis ? wl[2] : wl[1], yaxis ? wl[1] : wl[2], wl[3], wl[4]};
+    R Rr[5] = {wr[0], yaxis ? wr[2] : wr[1], yaxis ? wr[1] : wr[2], wr[3], wr[4]};
+    R Fn[5];
+    hllc<R, 2>(g, L, Rr, Fn);
+    F[0] = Fn[0];
+    F[1] = yaxis ? Fn[2] : Fn[1];
+    F[2] = yaxis ? Fn[1] : Fn[2];
+    F[3] = Fn[3];
+    F[4] = Fn[4];
+}
+
 // Flux from already reconstructed face states (global frame) along kernel
 // axis AX: the rotation and HLLC of face_flux without the PLM step.
 template <int NDIM, int AX, typename R>
@@ -376,7 +402,8 @@ __device__ __forceinline__ void load_w(const Geo& g, const double* __restrict__ 
 // cfl * min over cells and axes of dx / (|v| + c) (Sec. 3.1).
 template <int NDIM>
 __device__ __forceinline__ double cfl_rate(const Geo& g, const double (&w)[NDIM + 2]) {
-    const double cs = __builtin_sqrt(g.gamma * w[NDIM + 1] / w[0]);
+    const double gp = g.gamma * w[NDIM + 1];
+    const double cs = gp * Ops<double>::rsq(gp * w[0]);  // sqrt(gamma p / rho)
     double best = (dabs(w[1]) + cs) * g.inv_dx[0];
     if (NDIM == 3) {
         const double c1 = (dabs(w[2]) + cs) * g.inv_dx[1];
@@ -449,12 +476,13 @@ __device__ __forceinline__ void load_u(const double* __restrict__ U, long long N
 
 // Primitive state of raw values u; the velocity along kernel axis vax (if
 // any) takes the boundary treatment vm of the ghost it fills.
-template <int NDIM, typename R>
+template <int NDIM, typename R, bool CHECK = true>
 __device__ __forceinline__ void to_prim(double gm1, const double (&u)[NDIM + 2], int vax, int vm,
                                         R (&W)[NDIM + 2], bool& bad) {
     constexpr int NC = NDIM + 2;
     double w[NC];
-    bad |= !cons_to_prim<NDIM>(gm1, u, w);
+    const bool ok = cons_to_prim<NDIM>(gm1, u, w);
+    if (CHECK) bad |= !ok;
     if (vax >= 0) {
         const int vc = vax == 0 ? 1 : (vax == 1 ? 2 : NDIM);
 #pragma unroll
@@ -631,7 +659,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
             double uh[NC];
             R wh[NC];
             load_u<NC>(a.in, N, (long long)k * P + hcol, uh);
-            to_prim<NDIM, R>(gm1, uh, hvax, hvm, wh, bad);
+            // not checked here: every cell is checked by the tile that owns it
+            to_prim<NDIM, R, false>(gm1, uh, hvax, hvm, wh, bad);
 #pragma unroll
             for (int c = 0; c < NC; ++c) sW[c][hy + 2][hx + 2] = wh[c];
         }
@@ -664,13 +693,34 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) sFy[HY ? c : 0][HY ? ly : 0][lx] = F[c];
         }
-        // faces past the last thread column / row of a full tile
+        // faces past the last thread column / row of a full tile; in 3-D the
+        // x and y ones share one code path (axis chosen per lane)
         {
             const int ex = (ax == TX) ? ay : 0;
             const int ey = (HY && ay == TY) ? ax : 0;
             for (int e = tid; e < ex + ey; e += NT) {
                 R w0[NC], w1[NC], w2[NC], w3[NC], F[NC];
-                if (e < ex) {
+                if constexpr (HY) {
+                    const bool yaxis = e >= ex;
+                    // x face (row e, column TX) or y face (row TY, column e - ex)
+                    const int r0 = yaxis ? TY : e + 2, c0 = yaxis ? e - ex + 2 : TX;
+                    const int dr = yaxis ? 1 : 0, dc = yaxis ? 0 : 1;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        w0[c] = sW[c][r0][c0];
+                        w1[c] = sW[c][r0 + dr][c0 + dc];
+                        w2[c] = sW[c][r0 + 2 * dr][c0 + 2 * dc];
+                        w3[c] = sW[c][r0 + 3 * dr][c0 + 3 * dc];
+                    }
+                    face_flux_xy<R>(gr, yaxis, w0, w1, w2, w3, F);
+                    if (yaxis) {
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) sFy[c][TY][e - ex] = F[c];
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) sFx[c][e][TX] = F[c];
+                    }
+                } else {
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
                         w0[c] = sW[c][e + 2][TX];
@@ -681,18 +731,6 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                     face_flux<NDIM, 0, R>(gr, w0, w1, w2, w3, F);
 #pragma unroll
                     for (int c = 0; c < NC; ++c) sFx[c][e][TX] = F[c];
-                } else if (HY) {
-                    const int cl = e - ex;
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) {
-                        w0[c] = sW[c][TY][cl + 2];
-                        w1[c] = sW[c][TY + 1][cl + 2];
-                        w2[c] = sW[c][TY + 2][cl + 2];
-                        w3[c] = sW[c][TY + 3][cl + 2];
-                    }
-                    face_flux<NDIM, 1, R>(gr, w0, w1, w2, w3, F);
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) sFy[HY ? c : 0][HY ? TY : 0][cl] = F[c];
                 }
             }
         }
@@ -1130,6 +1168,29 @@ bool tile_supported(int ndim, const Tile& t) {
     if (ndim == 3)
         return (t.tx == 32 && t.ty == 8) || (t.tx == 64 && t.ty == 8) || (t.tx == 16 && t.ty == 16);
     return t.ty == 1 && (t.tx == 64 || t.tx == 128 || t.tx == 256);
+}
+
+int tile_candidates(const Geo& g, Tile* out, int max) {
+    static const int shapes3[3][2] = {{32, 8}, {64, 8}, {16, 16}};
+    static const int shapes12[3][2] = {{64, 1}, {128, 1}, {256, 1}};
+    static const int kzs[4] = {8, 16, 32, 64};
+    const int(*shapes)[2] = g.ndim == 3 ? shapes3 : shapes12;
+    int n = 0;
+    for (int s = 0; s < 3; ++s) {
+        // in 1-D and 2-D a row wider than twice the mesh only idles threads
+        if (g.ndim < 3 && s > 0 && shapes[s][0] >= 2 * g.n[0]) continue;
+        for (int q = 0; q < (g.ndim == 1 ? 1 : 4); ++q) {
+            const int kz = g.ndim == 1 ? 1 : kzs[q];
+            if (q > 0 && kzs[q - 1] >= g.n[2]) break;  // same chunks as the previous kz
+            if (n < max) {
+                out[n].tx = shapes[s][0];
+                out[n].ty = shapes[s][1];
+                out[n].kz = kz;
+            }
+            ++n;
+        }
+    }
+    return n;
 }
 
 void plan_tiles(const Geo& g, const Tile& t, int& tiles_x, int& tiles_y, int& chunks_z, int& kz) {

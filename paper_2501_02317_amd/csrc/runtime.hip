@@ -430,6 +430,72 @@ int hydro_get_tile(hydro_t h, int* tx, int* ty, int* kz) {
     return HYDRO_OK;
 }
 
+int hydro_autotune(hydro_t h, int steps_per_tile, double t_end, int* tx, int* ty, int* kz,
+                   double* ms_per_step) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (steps_per_tile < 1 || steps_per_tile > 1000 || !(t_end >= 0.0) || !std::isfinite(t_end) || !tx ||
+        !ty || !kz || !ms_per_step)
+        return HYDRO_E_INVAL;
+    constexpr int kMaxCand = 32;
+    Tile cand[kMaxCand];
+    const int nc = std::min(tile_candidates(h->geo, cand, kMaxCand), kMaxCand);
+    hipEvent_t ev[kMaxCand + 1];
+    int made = 0;
+    hipError_t e = hipSuccess;
+    for (; made <= nc && e == hipSuccess; ++made) e = hipEventCreate(&ev[made]);
+    if (e != hipSuccess) --made;
+    const Tile keep = h->tile;
+    // The tuning steps are real steps of the run: each candidate advances the
+    // state, and the results do not depend on the tile.
+    if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_SET_LIMITS, t_end, 0.0, h->cfg.cfl, h->stream);
+    if (e == hipSuccess && !h->dt_valid) e = enqueue_dt(h);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], h->stream);
+    for (int c = 0; c < nc && e == hipSuccess; ++c) {
+        h->tile = cand[c];
+        for (int s = 0; s < steps_per_tile && e == hipSuccess; ++s) e = enqueue_step(h, true, 0.0);
+        if (e == hipSuccess) e = hipEventRecord(ev[c + 1], h->stream);
+    }
+    h->tile = keep;
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    int best = -1;
+    float best_ms = 0.0f;
+    for (int c = 0; c < nc && e == hipSuccess; ++c) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, ev[c], ev[c + 1]);
+        if (e == hipSuccess && (best < 0 || ms < best_ms)) {
+            best = c;
+            best_ms = ms;
+        }
+    }
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+    if (e != hipSuccess) return fail(h, e);
+    rc = read_ctrl(h);
+    if (rc) return rc;
+    // a run that reached its limit while tuning skipped steps: no valid timing
+    if (h->host_ctrl->done || best < 0) return HYDRO_E_STATE;
+    h->tile = cand[best];
+    *tx = cand[best].tx;
+    *ty = cand[best].ty;
+    *kz = cand[best].kz;
+    *ms_per_step = (double)best_ms / steps_per_tile;
+    return HYDRO_OK;
+}
+
+int hydro_tile_candidates(const hydro_config* cfg, int* tiles, int max) {
+    if (!config_ok(cfg) || max < 0 || (max > 0 && !tiles)) return HYDRO_E_INVAL;
+    const Geo g = make_geo(cfg);
+    constexpr int kMaxCand = 32;
+    Tile cand[kMaxCand];
+    const int nc = std::min(tile_candidates(g, cand, kMaxCand), kMaxCand);
+    for (int c = 0; c < nc && c < max; ++c) {
+        tiles[3 * c] = cand[c].tx;
+        tiles[3 * c + 1] = cand[c].ty;
+        tiles[3 * c + 2] = cand[c].kz;
+    }
+    return nc;
+}
+
 namespace {
 void profile_free(hydro_t h) {
     for (int st = 0; st < 2; ++st) {

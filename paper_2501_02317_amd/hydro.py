@@ -50,6 +50,9 @@ _SIG = {
     "hydro_padded_primitive": (C.c_int, [_h, _dp]),
     "hydro_set_tile": (C.c_int, [_h, C.c_int, C.c_int, C.c_int]),
     "hydro_get_tile": (C.c_int, [_h, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "hydro_tile_candidates": (C.c_int, [C.POINTER(Config), C.POINTER(C.c_int), C.c_int]),
+    "hydro_autotune": (C.c_int, [_h, C.c_int, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                 C.POINTER(C.c_int), _dp]),
     "hydro_profile": (C.c_int, [_h, C.c_int]),
     "hydro_profile_read": (C.c_int, [_h, _dp, _dp, C.POINTER(C.c_int64)]),
     "hydro_set_run_limit": (C.c_int, [_h, C.c_int64, C.c_double]),
@@ -127,6 +130,8 @@ class Hydro:
 
         self.cfg = make_config(n, gamma, cfl, precision, lo, hi, bc)
         self.ndim = len(n)
+        self.n = tuple(int(v) for v in n)
+        self.precision = int(precision)
         self.ncomp = self.ndim + 2
         nn = list(n) + [1] * (3 - len(n))
         self.shape = (self.ncomp, nn[2], nn[1], nn[0])
@@ -244,6 +249,27 @@ class Hydro:
         _check(_lib.hydro_get_tile(self._h, C.byref(tx), C.byref(ty), C.byref(kz)), "hydro_get_tile")
         return tx.value, ty.value, kz.value
 
+    def autotune(self, steps_per_tile=1, t_end=0.0, cache=None):
+        """Pick the fastest tile.  With a cache file (JSON) a tile stored for
+        the same device, dimensionality, size and precision is set directly;
+        otherwise hydro_autotune times every candidate over real steps of
+        this run and the winner is stored.  Returns (tile, steps advanced)."""
+        key = None
+        if cache:
+            key = _tile_key(self.ndim, self.n, self.precision)
+            entry = _cache_read(cache).get(key)
+            if entry:
+                self.set_tile(*entry["tile"])
+                return tuple(entry["tile"]), 0
+        s0 = self.steps_done()
+        tx, ty, kz, ms = C.c_int(), C.c_int(), C.c_int(), C.c_double()
+        _check(_lib.hydro_autotune(self._h, int(steps_per_tile), float(t_end), C.byref(tx), C.byref(ty),
+                                   C.byref(kz), C.byref(ms)), "hydro_autotune")
+        tile = (tx.value, ty.value, kz.value)
+        if cache:
+            _cache_store(cache, key, {"tile": list(tile), "ms_per_step": ms.value})
+        return tile, self.steps_done() - s0
+
     # ---- measurement
     def profile(self, cap):
         """Bracket the next cap launches of each stage kernel with HIP events."""
@@ -335,6 +361,41 @@ def riemann_fluxes(precision, gamma, WL, WR, stream=None):
            "hydro_riemann_fluxes")
     s.synchronize()
     return dF.cpu().numpy()
+
+
+def tile_candidates(ndim, n, precision=FP64):
+    """(tx, ty, kz) tiles the autotuner tries for a mesh of this shape."""
+    cfg = make_config(n, 1.4, 0.4, precision)
+    cnt = _lib.hydro_tile_candidates(C.byref(cfg), None, 0)
+    _check(min(cnt, 0), "hydro_tile_candidates")
+    buf = (C.c_int * (3 * cnt))()
+    _lib.hydro_tile_candidates(C.byref(cfg), buf, cnt)
+    return [tuple(buf[3 * i:3 * i + 3]) for i in range(cnt)]
+
+
+def _tile_key(ndim, n, precision):
+    import torch
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    return f"{arch}|{ndim}d|{'x'.join(str(v) for v in n)}|{'fp64' if precision == FP64 else 'mixed'}"
+
+
+def _cache_read(path):
+    import json
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (FileNotFoundError, ValueError):
+        return {}
+
+
+def _cache_store(path, key, entry):
+    import json
+    data = _cache_read(path)
+    data[key] = entry
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
 
 
 def exported_symbols():

@@ -103,3 +103,37 @@ def test_batch_members_track_oracle(H):
         err = rel_l1(U, U_o)
         print(c.name, prec, "relL1 vs oracle", err)
         assert np.all(err <= (1e-12 if prec == 0 else 1e-5))
+
+
+_subset_oracle = {}
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-3)])
+def test_batch_workload_subset_tracks_oracle(H, precision, tol):
+    """Sixteen meshes of the 512-mesh ragged 2-D workload (seeded choice,
+    the smallest and the largest included), 20 batched steps, each member
+    against the oracle.  FP64 to the 1e-12 gate; mixed to the loose bound of
+    marginally resolved layers (the tanh width spans 1 to 8 cells here)."""
+    full = wl.batch_sizes(512, seed=401)
+    cells = [nx * ny for nx, ny in full]
+    rng = np.random.default_rng(402)
+    pick = {int(np.argmin(cells)), int(np.argmax(cells))}
+    while len(pick) < 16:
+        pick.add(int(rng.integers(len(full))))
+    pick = sorted(pick)
+    cases = [(wl.shear_layer_2d(*full[m], seed=4000 + m, steps=20), precision, 20, 0.0) for m in pick]
+    say("batch workload subset", precision, [full[m] for m in pick])
+    outs, times, steps, info = run_batch(H, cases, 20, use_graph=True)
+    assert steps == [20] * 16
+    worst = np.zeros(4)
+    for (c, prec, ks, te), U, t in zip(cases, outs[0], times):
+        key = (c.name, c.meta["seed"])
+        if key not in _subset_oracle:
+            m = oracle_mesh(c)
+            _subset_oracle[key] = O.run(m, O.prim_to_cons(m, c.W), c.cfl, max_steps=ks)
+        U_o, t_o, s_o, _ = _subset_oracle[key]
+        err = rel_l1(U, U_o)
+        worst = np.maximum(worst, err)
+        assert np.all(err <= tol), (c.name, err)
+        assert abs(t - t_o) <= (1e-14 if prec == 0 else 1e-6) * t_o
+    print("worst relL1 per component", worst)

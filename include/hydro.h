@@ -157,10 +157,14 @@ int hydro_padded_primitive(hydro_t h, double* Wpad_host);
 
 /* Tile of the stage kernel: a work-group covers tx x ty cells of the
  * (x, y) plane (3-D: 32x8, 64x8 or 16x16; 1-D and 2-D: 64, 128 or 256 by
- * 1) and marches along the last active axis over chunks of kz >= 1 planes.
- * Every face flux is the same function of the same inputs for any tile, so
- * the results are bitwise independent of the tile; only speed changes.
- * Unsupported shapes return HYDRO_E_INVAL.  hydro_create picks a default. */
+ * 1) and marches along the last active axis over chunks of kz planes.
+ * kz = 0 (2-D and 3-D) picks the chunk length at each launch so that one
+ * round of the work-groups the device holds at once covers the mesh (at
+ * least 16 and at most 128 planes; in a batch, about 2048 work-groups per
+ * member).  Every face flux is the same function of the same inputs for any
+ * tile, so the results are bitwise independent of the tile; only speed
+ * changes.  Unsupported shapes return HYDRO_E_INVAL.  hydro_create picks a
+ * default (3-D 32 x 8, automatic kz). */
 int hydro_set_tile(hydro_t h, int tx, int ty, int kz);
 int hydro_get_tile(hydro_t h, int* tx, int* ty, int* kz);
 

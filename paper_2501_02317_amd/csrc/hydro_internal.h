@@ -103,6 +103,10 @@ hipError_t launch_riemann(int precision, int ntan, double gamma, long long n, co
 // Default tile for a mesh (kernel axes) and precision.
 Tile default_tile(const Geo& g, int precision);
 // Whether the stage kernel is compiled for this tile shape.
+// Bounds of the automatic chunk length (Tile::kz == 0).
+constexpr int kMinAutoKz = 16;
+constexpr int kMaxAutoKz = 128;
+
 bool tile_supported(int ndim, const Tile& t);
 // Tiles the autotuner tries for a mesh (at most max written); returns how
 // many there are.

@@ -505,7 +505,14 @@ __device__ __forceinline__ void to_prim(double gm1, const double (&u)[NDIM + 2],
 // 256-thread groups per CU (16 waves); FP64 needs more registers per thread.
 template <typename R, int MODE>
 struct StageOccupancy {
-    static constexpr int kBlocks = sizeof(R) == 4 ? 4 : 2;
+    // Input ring: the raw input values of a cell, read for its conversion
+    // when its plane enters the z stencil, are kept in a three-plane LDS ring
+    // until the update of that plane instead of being read again.  It pays
+    // in the mixed stage 2, whose update also reads U^n: there the ring's
+    // LDS sets the occupancy to three work-groups per CU, which the
+    // register use of that kernel allows without spills.
+    static constexpr bool kRing = sizeof(R) == 4 && MODE == MODE_STAGE2;
+    static constexpr int kBlocks = sizeof(R) == 4 ? (kRing ? 3 : 4) : 2;
 };
 
 template <int NDIM, typename R, int MODE, int TX, int TY>
@@ -574,6 +581,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
     const double lam2 = dt / g.dx[2];
     const Gas<R> gr = make_gas<R>(g.gamma);
 
+    constexpr bool RING = StageOccupancy<R, MODE>::kRing && HZ;
+    __shared__ double sRaw[RING ? 3 : 1][RING ? NC : 1][RING ? NT : 1];
     __shared__ R sW[NC][TY + 4][TX + 4];
     __shared__ R sFx[NC][TY][TX + 1];
     __shared__ R sFy[HY ? NC : 1][HY ? TY + 1 : 1][TX];
@@ -602,6 +611,10 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
             double u[NC];
             load_interior(z0 - 2 + s, u, vm);
             to_prim<NDIM, R>(gm1, u, vm == VM_NONE ? -1 : 2, vm, w[s], bad);
+            if (RING && s >= 2) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) sRaw[RING ? (z0 - 2 + s) % 3 : 0][RING ? c : 0][RING ? tid : 0] = u[c];
+            }
         }
         // planes z0-2 .. z0+1: face z0-1/2 and the left state of face z0+1/2,
         // in the operations face_flux uses
@@ -629,6 +642,11 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                 // W_{k+2} arrived: z face k+1/2 from (W_k, W_{k+1}, W_{k+2})
                 R w2[NC], wr[NC];
                 to_prim<NDIM, R>(gm1, ui, vmi == VM_NONE ? -1 : 2, vmi, w2, bad);
+                // plane k+2 is an interior plane whenever its update comes
+                if (RING) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) sRaw[RING ? (k + 2) % 3 : 0][RING ? c : 0][RING ? tid : 0] = ui[c];
+                }
                 // plane k+3 is W_{k'+2} of the next iteration k' = k+1; it lies at
                 // most two planes outside the mesh only while that iteration exists
                 if (k + 1 < z1) load_interior(k + 3, ui, vmi);
@@ -739,7 +757,12 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
         if (act) {
             const long long cell = (long long)k * P + col;
             double uin[NC], ubase[NC];
-            if (MODE != MODE_RHS) load_u<NC>(a.in, N, cell, uin);
+            if (RING) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) uin[c] = sRaw[RING ? k % 3 : 0][RING ? c : 0][RING ? tid : 0];
+            } else if (MODE != MODE_RHS) {
+                load_u<NC>(a.in, N, cell, uin);
+            }
             if (MODE == MODE_STAGE2) load_u<NC>(a.base, N, cell, ubase);
             double unew[NC];
 #pragma unroll
@@ -1081,10 +1104,38 @@ struct LaunchCtx {
     int nblk;
 };
 
+// Work-groups of this stage kernel resident on the whole device at once
+// (0 if the runtime cannot tell).
+template <int NDIM, typename R, int MODE, int TX, int TY>
+int stage_slots() {
+    static const int slots = [] {
+        int dev = 0, cus = 0, nb = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, reinterpret_cast<const void*>(&stage_kernel<NDIM, R, MODE, TX, TY>), TX * TY, 0) !=
+            hipSuccess)
+            return 0;
+        return cus * nb;
+    }();
+    return slots;
+}
+
 template <int NDIM, typename R, int MODE, int TX, int TY>
 hipError_t launch_stage_t(const LaunchCtx& L, hipStream_t s) {
     if (L.a) {
-        const StageArgs& a = *L.a;
+        StageArgs a = *L.a;
+        if (a.kz == 0) {
+            // automatic chunk length: one round of resident work-groups
+            // covers the mesh, so no work-group waits for a second round
+            const int slots = stage_slots<NDIM, R, MODE, TX, TY>();
+            const long long cols = (long long)a.tiles_x * a.tiles_y;
+            const int n2 = a.geo.n[2];
+            long long kz = slots > 0 ? (n2 * cols + slots - 1) / slots : 32;
+            kz = kz < kMinAutoKz ? kMinAutoKz : (kz > kMaxAutoKz ? kMaxAutoKz : kz);
+            a.kz = kz > n2 ? n2 : (int)kz;
+            a.chunks_z = (n2 + a.kz - 1) / a.kz;
+        }
         const int nb = a.tiles_x * a.tiles_y * a.chunks_z;
         hipLaunchKernelGGL((stage_kernel<NDIM, R, MODE, TX, TY>), dim3(nb), dim3(TX * TY), 0, s, a);
     } else {
@@ -1154,17 +1205,13 @@ Tile default_tile(const Geo& g, int precision) {
         t.tx = 64;
         t.ty = 1;
     }
-    // chunk length along the marching axis: about 2048 work-groups, chunks of
-    // 16..64 planes (shorter chunks re-read more ghost planes)
-    const long long cols = (long long)((g.n[0] + t.tx - 1) / t.tx) * ((g.n[1] + t.ty - 1) / t.ty);
-    long long kz = (g.n[2] * cols + 2047) / 2048;
-    kz = kz < 16 ? 16 : (kz > 64 ? 64 : kz);
-    t.kz = g.ndim == 1 ? 1 : (int)kz;
+    // chunk length chosen at launch (one round of resident work-groups)
+    t.kz = g.ndim == 1 ? 1 : 0;
     return t;
 }
 
 bool tile_supported(int ndim, const Tile& t) {
-    if (t.kz < 1) return false;
+    if (t.kz < 0 || (t.kz == 0 && ndim == 1)) return false;
     if (ndim == 3)
         return (t.tx == 32 && t.ty == 8) || (t.tx == 64 && t.ty == 8) || (t.tx == 16 && t.ty == 16);
     return t.ty == 1 && (t.tx == 64 || t.tx == 128 || t.tx == 256);
@@ -1173,15 +1220,15 @@ bool tile_supported(int ndim, const Tile& t) {
 int tile_candidates(const Geo& g, Tile* out, int max) {
     static const int shapes3[3][2] = {{32, 8}, {64, 8}, {16, 16}};
     static const int shapes12[3][2] = {{64, 1}, {128, 1}, {256, 1}};
-    static const int kzs[4] = {8, 16, 32, 64};
+    static const int kzs[5] = {0, 8, 16, 32, 64};  // 0: automatic
     const int(*shapes)[2] = g.ndim == 3 ? shapes3 : shapes12;
     int n = 0;
     for (int s = 0; s < 3; ++s) {
         // in 1-D and 2-D a row wider than twice the mesh only idles threads
         if (g.ndim < 3 && s > 0 && shapes[s][0] >= 2 * g.n[0]) continue;
-        for (int q = 0; q < (g.ndim == 1 ? 1 : 4); ++q) {
+        for (int q = 0; q < (g.ndim == 1 ? 1 : 5); ++q) {
             const int kz = g.ndim == 1 ? 1 : kzs[q];
-            if (q > 0 && kzs[q - 1] >= g.n[2]) break;  // same chunks as the previous kz
+            if (q > 1 && kzs[q - 1] >= g.n[2]) break;  // same chunks as the previous kz
             if (n < max) {
                 out[n].tx = shapes[s][0];
                 out[n].ty = shapes[s][1];
@@ -1193,15 +1240,27 @@ int tile_candidates(const Geo& g, Tile* out, int max) {
     return n;
 }
 
+// Chunk length for tile t: t.kz, or with t.kz == 0 about 2048 work-groups in
+// chunks of 16..64 planes (shorter chunks re-read more ghost planes).
+int batch_kz(const Geo& g, const Tile& t) {
+    if (t.kz > 0) return t.kz;
+    if (g.ndim == 1) return 1;
+    const long long cols = (long long)((g.n[0] + t.tx - 1) / t.tx) * ((g.n[1] + t.ty - 1) / t.ty);
+    long long kz = (g.n[2] * cols + 2047) / 2048;
+    return (int)(kz < 16 ? 16 : (kz > 64 ? 64 : kz));
+}
+
 void plan_tiles(const Geo& g, const Tile& t, int& tiles_x, int& tiles_y, int& chunks_z, int& kz) {
     tiles_x = (g.n[0] + t.tx - 1) / t.tx;
     tiles_y = (g.n[1] + t.ty - 1) / t.ty;
-    kz = t.kz < 1 ? 1 : (t.kz > g.n[2] ? g.n[2] : t.kz);
+    kz = batch_kz(g, t);
+    kz = kz > g.n[2] ? g.n[2] : kz;
     chunks_z = (g.n[2] + kz - 1) / kz;
 }
 
 hipError_t launch_stage(int precision, int mode, const Tile& t, StageArgs a, hipStream_t s) {
     plan_tiles(a.geo, t, a.tiles_x, a.tiles_y, a.chunks_z, a.kz);
+    if (t.kz == 0 && a.geo.ndim > 1) a.kz = 0;  // resolved per kernel at launch
     LaunchCtx L{&a, nullptr, nullptr, 0};
     return launch_any(a.geo.ndim, precision, mode, t, L, s);
 }

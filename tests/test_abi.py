@@ -84,13 +84,14 @@ def test_tile_candidates(H):
     """The autotuner's candidate tiles: every one supported, none repeated,
     kz values that differ in the chunks they give."""
     c3 = H.tile_candidates(3, (256, 256, 256))
-    assert len(c3) == 12 and len(set(c3)) == 12
+    assert len(c3) == 15 and len(set(c3)) == 15
     assert {(tx, ty) for tx, ty, _ in c3} == {(32, 8), (64, 8), (16, 16)}
-    assert {kz for *_, kz in c3} == {8, 16, 32, 64}
+    assert {kz for *_, kz in c3} == {0, 8, 16, 32, 64}        # 0: automatic
     # a short marching axis: kz beyond it gives the same single chunk
-    assert {kz for *_, kz in H.tile_candidates(3, (64, 64, 12))} == {8, 16}
+    assert {kz for *_, kz in H.tile_candidates(3, (64, 64, 12))} == {0, 8, 16}
     # 2-D: rows much wider than the mesh are not tried
-    assert H.tile_candidates(2, (64, 512)) == [(64, 1, 8), (64, 1, 16), (64, 1, 32), (64, 1, 64)]
+    assert H.tile_candidates(2, (64, 512)) == [(64, 1, 0), (64, 1, 8), (64, 1, 16), (64, 1, 32),
+                                               (64, 1, 64)]
     assert {tx for tx, *_ in H.tile_candidates(2, (96, 96))} == {64, 128}
     assert H.tile_candidates(1, (256,)) == [(64, 1, 1), (128, 1, 1), (256, 1, 1)]
     bad = H.make_config((0, 4), 1.4, 0.4)

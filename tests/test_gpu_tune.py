@@ -51,3 +51,23 @@ def test_autotune_reports_a_run_that_ended(H):
     h.step_auto(2)                            # still usable
     assert h.steps_done() >= 2
     h.close()
+
+
+@pytest.mark.parametrize("ndim,prec", [(3, 0), (3, 1), (2, 1)])
+def test_results_bitwise_independent_of_tile(H, ndim, prec):
+    """Every candidate tile (shapes, fixed and automatic chunk lengths) gives
+    the same bits after several steps on a ragged mesh."""
+    c = (wl.turbulence_3d(n=(72, 44, 40), mach=1.5, seed=25) if ndim == 3
+         else wl.shear_layer_2d(200, 136, seed=4031))
+    ref = None
+    for tile in H.tile_candidates(ndim, c.n, prec):
+        say("tile", ndim, prec, tile)
+        h = gpu_mesh(c, prec)
+        h.set_tile(*tile)
+        h.step_auto(4)
+        U = h.get_state()
+        h.close()
+        if ref is None:
+            ref = U
+        else:
+            assert bitwise_equal(U, ref), tile

@@ -18,6 +18,7 @@ FP64 oracle on the host cores for one Heun step of the same 256^3 state.
 import argparse
 import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -43,6 +44,11 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-count", type=int, default=300)
+    ap.add_argument("--tile", default="",
+                    help="fixed tile tx,ty,kz (kz 0: automatic) for both stages instead of autotuning")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the library's default stage tiles (no autotuning), e.g. for profiler "
+                         "runs that should see one kernel per stage")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes five times "
                          "(calibrates the HBM byte counters) and exit")
@@ -65,11 +71,16 @@ def bytes_per_update(ndim):
     return 5 * (ndim + 2) * 8
 
 
-def run_precision(H, case, precision, steps, warmup):
+def run_precision(H, case, precision, steps, warmup, tile=None, tune=True):
     import torch
     h = H.Hydro(case.n, case.gamma, case.cfl, precision=precision, lo=case.lo, hi=case.hi, bc=case.bc)
     h.set_primitive(case.W)
-    tile, _ = h.autotune(2)        # tuning steps are warm-up steps of the run
+    if tile or not tune:
+        if tile:
+            h.set_tile(*tile)
+        tiles = h.get_tile()
+    else:
+        tiles, _ = h.autotune(3)   # tuning steps are warm-up steps of the run
     h.step_auto(warmup)
     torch.cuda.synchronize()
     h.set_primitive(case.W)        # timed run starts from the seeded state
@@ -101,7 +112,7 @@ def run_precision(H, case, precision, steps, warmup):
         "stage_ms": [ms1 / max(n1, 1), ms2 / max(n2, 1)], "launches": [n1, n2],
         "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS, "totals": T.tolist(),
         "step_frac": rate * bytes_per_update(case.ndim) / 1e9 / HBM_PEAK_GBS,
-        "tile": list(tile),
+        "tiles": [list(t) for t in tiles],
     }
 
 
@@ -194,18 +205,23 @@ def cpu_baseline(case):
                       f"{'x'.join(map(str, case.n))} Mach-2 state, {el:.1f} s on the host"}
 
 
-def traffic_record(nc):
-    """HBM bytes per stage-kernel launch from the committed rocprofv3 counter
-    summary, when it was taken from the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "stage_kernel_256cubed_traffic.json")
+def traffic_record(precision, tiles):
+    """HBM bytes per step (stage-1 plus stage-2 launch) from the committed
+    rocprofv3 counter summary, when it was taken from the current kernel
+    source with the same stage tiles."""
+    path = os.path.join(ROOT, "profiles", "stage_kernel_256cubed_traffic.md")
     src = os.path.join(ROOT, "paper_2501_02317_amd", "csrc", "kernels.hip")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("kernels_sha256") != digest:
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
         return None
-    return rec.get("bytes_per_step_pair")
+    rec = json.loads(m.group(1))
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    entry = rec.get("by_precision", {}).get(precision)
+    if rec.get("kernels_sha256") != digest or not entry or entry.get("tiles") != tiles:
+        return None
+    return entry.get("bytes_per_step_pair")
 
 
 def main():
@@ -231,7 +247,8 @@ def main():
     for name, prec in (("mixed", H.MIXED), ("fp64", H.FP64)):
         if args.precision not in ("both", name):
             continue
-        res[name] = run_precision(H, case, prec, args.steps, args.warmup)
+        fixed = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
+        res[name] = run_precision(H, case, prec, args.steps, args.warmup, fixed, not args.no_tune)
         print(f"[bench] {name}: {res[name]['rate']:.3e} cell-updates/s, "
               f"{res[name]['ms_per_step']:.3f} ms/step, stage kernel {res[name]['achieved_gbs']:.0f} GB/s",
               file=sys.stderr, flush=True)
@@ -240,7 +257,7 @@ def main():
     nc = case.ndim + 2
     cells = case.ncells
     alg_per_launch_pair = 5 * nc * 8 * cells
-    traffic = traffic_record(nc)
+    traffic = traffic_record(head_name, head["tiles"])
     out = {
         "metric": METRIC,
         "value": head["rate"],
@@ -266,7 +283,7 @@ def main():
         "by_precision": {k: {"value": v["rate"], "ms_per_step": v["ms_per_step"],
                              "roofline_frac": v["frac"], "step_roofline_frac": v["step_frac"],
                              "stage_ms": v["stage_ms"], "achieved_gbs": v["achieved_gbs"],
-                             "tile": v["tile"]}
+                             "tiles": v["tiles"]}
                          for k, v in res.items()},
     }
     if "mixed" in res and "fp64" in res:

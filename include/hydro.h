@@ -155,18 +155,21 @@ int hydro_stage_rhs(hydro_t h, double dt, double* dU_host);
  * array with n_d + 4 cells on active axes; corner ghosts are set to 0. */
 int hydro_padded_primitive(hydro_t h, double* Wpad_host);
 
-/* Tile of the stage kernel: a work-group covers tx x ty cells of the
- * (x, y) plane (3-D: 32x8, 64x8 or 16x16; 1-D and 2-D: 64, 128 or 256 by
- * 1) and marches along the last active axis over chunks of kz planes.
- * kz = 0 (2-D and 3-D) picks the chunk length at each launch so that one
- * round of the work-groups the device holds at once covers the mesh (at
- * least 16 and at most 128 planes; in a batch, about 2048 work-groups per
- * member).  Every face flux is the same function of the same inputs for any
- * tile, so the results are bitwise independent of the tile; only speed
- * changes.  Unsupported shapes return HYDRO_E_INVAL.  hydro_create picks a
- * default (3-D 32 x 8, automatic kz). */
+/* Tile of a stage kernel: a work-group covers tx x ty cells of the (x, y)
+ * plane (3-D: 32x8, 64x8, 16x16 or 32x16; 1-D and 2-D: 64, 128 or 256 by 1)
+ * and marches along the last active axis over chunks of kz planes.  kz = 0
+ * (2-D and 3-D) picks the chunk length at each launch so that one round of
+ * the work-groups the device holds at once covers the mesh (at least 16 and
+ * at most 128 planes; in a batch, about 2048 work-groups per member).  The
+ * two stages have a tile each (the stage right-hand side uses stage 1's;
+ * a batch uses each member's stage-1 tile for both stages).  Every face flux
+ * is the same function of the same inputs for any tile, so the results are
+ * bitwise independent of the tiles; only speed changes.  hydro_create picks
+ * defaults.  Unsupported shapes or a stage other than 0 (both), 1 or 2 return
+ * HYDRO_E_INVAL; hydro_set_tile sets both stages. */
 int hydro_set_tile(hydro_t h, int tx, int ty, int kz);
-int hydro_get_tile(hydro_t h, int* tx, int* ty, int* kz);
+int hydro_set_stage_tile(hydro_t h, int stage, int tx, int ty, int kz);
+int hydro_get_stage_tile(hydro_t h, int stage, int* tx, int* ty, int* kz);
 
 /* The tiles the autotuner tries for a configuration: writes up to max
  * (tx, ty, kz) triples to tiles[3 * i ...] and returns their total number
@@ -175,14 +178,16 @@ int hydro_tile_candidates(const hydro_config* cfg, int* tiles, int max);
 
 /* Autotuner.  Advances the run by steps_per_tile real Heun steps per
  * candidate tile (device-resident dt as in hydro_step_auto, t_end 0 = no
- * clamp), each candidate timed with HIP events, then keeps the fastest tile
- * and returns it with its time per step.  The steps are part of the run
- * (results do not depend on the tile), so tuning can replace warm-up steps.
- * Blocks until done.  If the run reached its limit while tuning (timings of
- * skipped steps mean nothing) the tile is left as it was and the call returns
- * HYDRO_E_STATE; the handle stays usable.  steps_per_tile in [1, 1000]. */
-int hydro_autotune(hydro_t h, int steps_per_tile, double t_end, int* tx, int* ty, int* kz,
-                   double* ms_per_step);
+ * clamp), timing each stage with HIP events, and sets each stage's fastest
+ * tile; the tile in use is kept unless a candidate beats it by more than 2 %.
+ * tiles receives 6 ints (stage 1 tx, ty, kz, then stage 2) and ms_per_step
+ * 2 doubles (the chosen tiles' stage times per step).  The steps are part of
+ * the run (results do not depend on the tiles), so tuning can replace
+ * warm-up steps.  Blocks until done.  If the run reached its limit while
+ * tuning (timings of skipped steps mean nothing) the tiles are left as they
+ * were and the call returns HYDRO_E_STATE; the handle stays usable.
+ * steps_per_tile in [1, 64]. */
+int hydro_autotune(hydro_t h, int steps_per_tile, double t_end, int* tiles, double* ms_per_step);
 
 /* Event timing of the stage kernels, for measurement: after
  * hydro_profile(h, cap) the next cap launches of each stage kernel are

@@ -101,7 +101,7 @@ hipError_t launch_riemann(int precision, int ntan, double gamma, long long n, co
                           const double* WR, double* F, hipStream_t s);
 
 // Default tile for a mesh (kernel axes) and precision.
-Tile default_tile(const Geo& g, int precision);
+Tile default_tile(const Geo& g, int precision, int mode);
 // Whether the stage kernel is compiled for this tile shape.
 // Bounds of the automatic chunk length (Tile::kz == 0).
 constexpr int kMinAutoKz = 16;

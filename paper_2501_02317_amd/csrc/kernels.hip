@@ -1152,6 +1152,7 @@ hipError_t launch_stage_tile(const Tile& t, const LaunchCtx& L, hipStream_t s) {
         if (t.tx == 32 && t.ty == 8) return launch_stage_t<NDIM, R, MODE, 32, 8>(L, s);
         if (t.tx == 64 && t.ty == 8) return launch_stage_t<NDIM, R, MODE, 64, 8>(L, s);
         if (t.tx == 16 && t.ty == 16) return launch_stage_t<NDIM, R, MODE, 16, 16>(L, s);
+        if (t.tx == 32 && t.ty == 16) return launch_stage_t<NDIM, R, MODE, 32, 16>(L, s);
         return hipErrorInvalidValue;
     } else {
         if (t.ty != 1) return hipErrorInvalidValue;
@@ -1192,12 +1193,15 @@ hipError_t launch_any(int ndim, int precision, int mode, const Tile& t, const La
 
 }  // namespace
 
-Tile default_tile(const Geo& g, int precision) {
-    (void)precision;
+Tile default_tile(const Geo& g, int precision, int mode) {
     Tile t;
     if (g.ndim == 3) {
+        // 32 x 16 halves the share of halo cells and extra faces; the mixed
+        // stage 2 keeps 32 x 8, where its input ring still leaves three
+        // work-groups per CU
+        const bool narrow = precision == 1 && mode == MODE_STAGE2;
         t.tx = 32;
-        t.ty = 8;
+        t.ty = narrow ? 8 : 16;
     } else if (g.ndim == 2) {
         t.tx = g.n[0] >= 256 ? 256 : (g.n[0] >= 128 ? 128 : 64);
         t.ty = 1;
@@ -1213,17 +1217,18 @@ Tile default_tile(const Geo& g, int precision) {
 bool tile_supported(int ndim, const Tile& t) {
     if (t.kz < 0 || (t.kz == 0 && ndim == 1)) return false;
     if (ndim == 3)
-        return (t.tx == 32 && t.ty == 8) || (t.tx == 64 && t.ty == 8) || (t.tx == 16 && t.ty == 16);
+        return (t.tx == 32 && t.ty == 8) || (t.tx == 64 && t.ty == 8) || (t.tx == 16 && t.ty == 16) ||
+               (t.tx == 32 && t.ty == 16);
     return t.ty == 1 && (t.tx == 64 || t.tx == 128 || t.tx == 256);
 }
 
 int tile_candidates(const Geo& g, Tile* out, int max) {
-    static const int shapes3[3][2] = {{32, 8}, {64, 8}, {16, 16}};
-    static const int shapes12[3][2] = {{64, 1}, {128, 1}, {256, 1}};
+    static const int shapes3[4][2] = {{32, 8}, {64, 8}, {16, 16}, {32, 16}};
+    static const int shapes12[4][2] = {{64, 1}, {128, 1}, {256, 1}, {0, 0}};
     static const int kzs[5] = {0, 8, 16, 32, 64};  // 0: automatic
     const int(*shapes)[2] = g.ndim == 3 ? shapes3 : shapes12;
     int n = 0;
-    for (int s = 0; s < 3; ++s) {
+    for (int s = 0; s < (g.ndim == 3 ? 4 : 3); ++s) {
         // in 1-D and 2-D a row wider than twice the mesh only idles threads
         if (g.ndim < 3 && s > 0 && shapes[s][0] >= 2 * g.n[0]) continue;
         for (int q = 0; q < (g.ndim == 1 ? 1 : 5); ++q) {

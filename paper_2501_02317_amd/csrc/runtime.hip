@@ -17,7 +17,7 @@ using namespace hydro;
 struct hydro_ctx {
     hydro_config cfg;
     Geo geo;
-    Tile tile;
+    Tile tile[2];  // stage 1 (and the rhs), stage 2
     hipStream_t stream;
     int ncomp;
     double dV;
@@ -143,7 +143,7 @@ hipError_t timed_stage(hydro_t h, int mode, const StageArgs& a) {
     const bool rec = h->prof_cap > 0 && h->prof_n[st] < h->prof_cap;
     hipError_t e = hipSuccess;
     if (rec) e = hipEventRecord(h->prof_ev[st][2 * h->prof_n[st]], h->stream);
-    if (e == hipSuccess) e = launch_stage(h->cfg.precision, mode, h->tile, a, h->stream);
+    if (e == hipSuccess) e = launch_stage(h->cfg.precision, mode, h->tile[st], a, h->stream);
     if (rec && e == hipSuccess) {
         e = hipEventRecord(h->prof_ev[st][2 * h->prof_n[st] + 1], h->stream);
         h->prof_n[st] += 1;
@@ -199,7 +199,8 @@ int hydro_create(const hydro_config* cfg, void* d_workspace, size_t nbytes, void
     std::memset(h, 0, sizeof(*h));
     h->cfg = *cfg;
     h->geo = make_geo(cfg);
-    h->tile = default_tile(h->geo, cfg->precision);
+    h->tile[0] = default_tile(h->geo, cfg->precision, MODE_STAGE1);
+    h->tile[1] = default_tile(h->geo, cfg->precision, MODE_STAGE2);
     h->stream = (hipStream_t)hip_stream;
     h->ncomp = cfg->ndim + 2;
     h->dV = 1.0;
@@ -382,7 +383,7 @@ int hydro_stage_rhs(hydro_t h, double dt, double* dU_host) {
     a.dt_host = dt;
     a.in = h->U;
     a.out = h->U1;
-    hipError_t e = launch_stage(h->cfg.precision, MODE_RHS, h->tile, a, h->stream);
+    hipError_t e = launch_stage(h->cfg.precision, MODE_RHS, h->tile[0], a, h->stream);
     const size_t bytes = (size_t)h->ncomp * h->geo.ncells * sizeof(double);
     if (e == hipSuccess) e = hipMemcpyAsync(dU_host, h->U1, bytes, hipMemcpyDeviceToHost, h->stream);
     if (e != hipSuccess) return fail(h, e);
@@ -408,77 +409,102 @@ int hydro_padded_primitive(hydro_t h, double* Wpad_host) {
     return read_ctrl(h);
 }
 
-int hydro_set_tile(hydro_t h, int tx, int ty, int kz) {
+int hydro_set_stage_tile(hydro_t h, int stage, int tx, int ty, int kz) {
     int rc = usable(h);
     if (rc) return rc;
+    if (stage < 0 || stage > 2) return HYDRO_E_INVAL;
     Tile t;
     t.tx = tx;
     t.ty = ty;
     t.kz = kz;
     if (!tile_supported(h->cfg.ndim, t)) return HYDRO_E_INVAL;
-    h->tile = t;
+    if (stage != 2) h->tile[0] = t;
+    if (stage != 1) h->tile[1] = t;
     return HYDRO_OK;
 }
 
-int hydro_get_tile(hydro_t h, int* tx, int* ty, int* kz) {
+int hydro_set_tile(hydro_t h, int tx, int ty, int kz) { return hydro_set_stage_tile(h, 0, tx, ty, kz); }
+
+int hydro_get_stage_tile(hydro_t h, int stage, int* tx, int* ty, int* kz) {
     int rc = usable(h);
     if (rc) return rc;
-    if (!tx || !ty || !kz) return HYDRO_E_INVAL;
-    *tx = h->tile.tx;
-    *ty = h->tile.ty;
-    *kz = h->tile.kz;
+    if (!tx || !ty || !kz || (stage != 1 && stage != 2)) return HYDRO_E_INVAL;
+    const Tile& t = h->tile[stage - 1];
+    *tx = t.tx;
+    *ty = t.ty;
+    *kz = t.kz;
     return HYDRO_OK;
 }
 
-int hydro_autotune(hydro_t h, int steps_per_tile, double t_end, int* tx, int* ty, int* kz,
-                   double* ms_per_step) {
+int hydro_autotune(hydro_t h, int steps_per_tile, double t_end, int* tiles, double* ms_per_step) {
     int rc = usable(h);
     if (rc) return rc;
-    if (steps_per_tile < 1 || steps_per_tile > 1000 || !(t_end >= 0.0) || !std::isfinite(t_end) || !tx ||
-        !ty || !kz || !ms_per_step)
+    if (steps_per_tile < 1 || steps_per_tile > 64 || !(t_end >= 0.0) || !std::isfinite(t_end) || !tiles ||
+        !ms_per_step)
         return HYDRO_E_INVAL;
     constexpr int kMaxCand = 32;
     Tile cand[kMaxCand];
     const int nc = std::min(tile_candidates(h->geo, cand, kMaxCand), kMaxCand);
-    hipEvent_t ev[kMaxCand + 1];
-    int made = 0;
+    // per candidate and step: before stage 1, between the stages, after stage 2
+    std::vector<hipEvent_t> ev((size_t)nc * steps_per_tile * 3);
+    size_t made = 0;
     hipError_t e = hipSuccess;
-    for (; made <= nc && e == hipSuccess; ++made) e = hipEventCreate(&ev[made]);
+    for (; made < ev.size() && e == hipSuccess; ++made) e = hipEventCreate(&ev[made]);
     if (e != hipSuccess) --made;
-    const Tile keep = h->tile;
-    // The tuning steps are real steps of the run: each candidate advances the
-    // state, and the results do not depend on the tile.
+    const Tile keep[2] = {h->tile[0], h->tile[1]};
+    // The tuning steps are real steps of the run (the results do not depend
+    // on the tile): enqueue_step's launches with events between the stages.
     if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_SET_LIMITS, t_end, 0.0, h->cfg.cfl, h->stream);
     if (e == hipSuccess && !h->dt_valid) e = enqueue_dt(h);
-    if (e == hipSuccess) e = hipEventRecord(ev[0], h->stream);
     for (int c = 0; c < nc && e == hipSuccess; ++c) {
-        h->tile = cand[c];
-        for (int s = 0; s < steps_per_tile && e == hipSuccess; ++s) e = enqueue_step(h, true, 0.0);
-        if (e == hipSuccess) e = hipEventRecord(ev[c + 1], h->stream);
-    }
-    h->tile = keep;
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    int best = -1;
-    float best_ms = 0.0f;
-    for (int c = 0; c < nc && e == hipSuccess; ++c) {
-        float ms = 0.0f;
-        e = hipEventElapsedTime(&ms, ev[c], ev[c + 1]);
-        if (e == hipSuccess && (best < 0 || ms < best_ms)) {
-            best = c;
-            best_ms = ms;
+        for (int s = 0; s < steps_per_tile && e == hipSuccess; ++s) {
+            hipEvent_t* q = &ev[((size_t)c * steps_per_tile + s) * 3];
+            StageArgs a = stage_args(h);
+            a.use_device_dt = 1;
+            a.in = h->U;
+            a.out = h->U1;
+            e = hipEventRecord(q[0], h->stream);
+            if (e == hipSuccess) e = launch_stage(h->cfg.precision, MODE_STAGE1, cand[c], a, h->stream);
+            if (e == hipSuccess) e = hipEventRecord(q[1], h->stream);
+            a.in = h->U1;
+            a.base = h->U;
+            a.out = h->U;
+            a.want_dt = 1;
+            if (e == hipSuccess) e = launch_stage(h->cfg.precision, MODE_STAGE2, cand[c], a, h->stream);
+            if (e == hipSuccess) e = hipEventRecord(q[2], h->stream);
+            if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_FINALIZE_STEP, 0.0, 0.0, h->cfg.cfl, h->stream);
         }
     }
-    for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    std::vector<double> ms((size_t)nc * 2, 0.0);
+    for (int c = 0; c < nc && e == hipSuccess; ++c)
+        for (int s = 0; s < steps_per_tile && e == hipSuccess; ++s)
+            for (int st = 0; st < 2 && e == hipSuccess; ++st) {
+                const hipEvent_t* q = &ev[((size_t)c * steps_per_tile + s) * 3];
+                float t = 0.0f;
+                e = hipEventElapsedTime(&t, q[st], q[st + 1]);
+                ms[2 * c + st] += t;
+            }
+    for (size_t i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
     if (e != hipSuccess) return fail(h, e);
     rc = read_ctrl(h);
     if (rc) return rc;
     // a run that reached its limit while tuning skipped steps: no valid timing
-    if (h->host_ctrl->done || best < 0) return HYDRO_E_STATE;
-    h->tile = cand[best];
-    *tx = cand[best].tx;
-    *ty = cand[best].ty;
-    *kz = cand[best].kz;
-    *ms_per_step = (double)best_ms / steps_per_tile;
+    if (h->host_ctrl->done || nc < 1) return HYDRO_E_STATE;
+    for (int st = 0; st < 2; ++st) {
+        // the tile in use stays unless a candidate is faster by more than 2 %,
+        // so close timings do not flip the choice from run to run
+        int best = -1;
+        for (int c = 0; c < nc; ++c)
+            if (cand[c].tx == keep[st].tx && cand[c].ty == keep[st].ty && cand[c].kz == keep[st].kz) best = c;
+        for (int c = 0; c < nc; ++c)
+            if (best < 0 || ms[2 * c + st] < 0.98 * ms[2 * best + st]) best = c;
+        h->tile[st] = cand[best];
+        tiles[3 * st] = cand[best].tx;
+        tiles[3 * st + 1] = cand[best].ty;
+        tiles[3 * st + 2] = cand[best].kz;
+        ms_per_step[st] = ms[2 * best + st] / steps_per_tile;
+    }
     return HYDRO_OK;
 }
 
@@ -635,12 +661,12 @@ bool plan_batch(int n, const hydro_t* members, BatchPlan& P) {
         d.U1 = h->U1;
         d.ctrl = h->ctrl;
         d.geo = h->geo;
-        plan_tiles(h->geo, h->tile, d.tiles_x, d.tiles_y, d.chunks_z, d.kz);
+        plan_tiles(h->geo, h->tile[0], d.tiles_x, d.tiles_y, d.chunks_z, d.kz);
         order[i] = i;
     }
     auto key = [&](int i) {
         const hydro_t h = members[i];
-        return std::make_tuple(h->cfg.ndim, h->cfg.precision, h->tile.tx, h->tile.ty);
+        return std::make_tuple(h->cfg.ndim, h->cfg.precision, h->tile[0].tx, h->tile[0].ty);
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
     for (int idx = 0; idx < n; ++idx) {
@@ -650,7 +676,7 @@ bool plan_batch(int n, const hydro_t* members, BatchPlan& P) {
             hydro_batch_ctx::Group g;
             g.ndim = h->cfg.ndim;
             g.precision = h->cfg.precision;
-            g.tile = h->tile;
+            g.tile = h->tile[0];
             g.blk_off = (int)P.blk.size();
             g.nblk = 0;
             P.groups.push_back(g);

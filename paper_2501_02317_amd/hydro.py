@@ -49,10 +49,11 @@ _SIG = {
     "hydro_stage_rhs": (C.c_int, [_h, C.c_double, _dp]),
     "hydro_padded_primitive": (C.c_int, [_h, _dp]),
     "hydro_set_tile": (C.c_int, [_h, C.c_int, C.c_int, C.c_int]),
-    "hydro_get_tile": (C.c_int, [_h, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "hydro_set_stage_tile": (C.c_int, [_h, C.c_int, C.c_int, C.c_int, C.c_int]),
+    "hydro_get_stage_tile": (C.c_int, [_h, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                       C.POINTER(C.c_int)]),
     "hydro_tile_candidates": (C.c_int, [C.POINTER(Config), C.POINTER(C.c_int), C.c_int]),
-    "hydro_autotune": (C.c_int, [_h, C.c_int, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                 C.POINTER(C.c_int), _dp]),
+    "hydro_autotune": (C.c_int, [_h, C.c_int, C.c_double, C.POINTER(C.c_int), _dp]),
     "hydro_profile": (C.c_int, [_h, C.c_int]),
     "hydro_profile_read": (C.c_int, [_h, _dp, _dp, C.POINTER(C.c_int64)]),
     "hydro_set_run_limit": (C.c_int, [_h, C.c_int64, C.c_double]),
@@ -241,34 +242,42 @@ class Hydro:
         return Wp
 
     # ---- tiling
-    def set_tile(self, tx, ty, kz):
-        _check(_lib.hydro_set_tile(self._h, int(tx), int(ty), int(kz)), "hydro_set_tile")
+    def set_tile(self, tx, ty, kz, stage=0):
+        """Tile of stage 1 or 2, or of both (stage 0)."""
+        _check(_lib.hydro_set_stage_tile(self._h, int(stage), int(tx), int(ty), int(kz)),
+               "hydro_set_stage_tile")
 
-    def get_tile(self):
+    def get_tile(self, stage=None):
+        """(tx, ty, kz) of stage 1 or 2, or a pair of them (stage None)."""
+        if stage is None:
+            return self.get_tile(1), self.get_tile(2)
         tx, ty, kz = C.c_int(), C.c_int(), C.c_int()
-        _check(_lib.hydro_get_tile(self._h, C.byref(tx), C.byref(ty), C.byref(kz)), "hydro_get_tile")
+        _check(_lib.hydro_get_stage_tile(self._h, int(stage), C.byref(tx), C.byref(ty), C.byref(kz)),
+               "hydro_get_stage_tile")
         return tx.value, ty.value, kz.value
 
     def autotune(self, steps_per_tile=1, t_end=0.0, cache=None):
-        """Pick the fastest tile.  With a cache file (JSON) a tile stored for
-        the same device, dimensionality, size and precision is set directly;
-        otherwise hydro_autotune times every candidate over real steps of
-        this run and the winner is stored.  Returns (tile, steps advanced)."""
+        """Pick each stage's fastest tile.  With a cache file (JSON) tiles
+        stored for the same device, dimensionality, size and precision are
+        set directly; otherwise hydro_autotune times every candidate over
+        real steps of this run and the winners are stored.  Returns
+        ((stage-1 tile, stage-2 tile), steps advanced)."""
         key = None
         if cache:
             key = _tile_key(self.ndim, self.n, self.precision)
             entry = _cache_read(cache).get(key)
             if entry:
-                self.set_tile(*entry["tile"])
-                return tuple(entry["tile"]), 0
+                t1, t2 = (tuple(t) for t in entry["tiles"])
+                self.set_tile(*t1, stage=1)
+                self.set_tile(*t2, stage=2)
+                return (t1, t2), 0
         s0 = self.steps_done()
-        tx, ty, kz, ms = C.c_int(), C.c_int(), C.c_int(), C.c_double()
-        _check(_lib.hydro_autotune(self._h, int(steps_per_tile), float(t_end), C.byref(tx), C.byref(ty),
-                                   C.byref(kz), C.byref(ms)), "hydro_autotune")
-        tile = (tx.value, ty.value, kz.value)
+        tiles, ms = (C.c_int * 6)(), (C.c_double * 2)()
+        _check(_lib.hydro_autotune(self._h, int(steps_per_tile), float(t_end), tiles, ms), "hydro_autotune")
+        t1, t2 = tuple(tiles[0:3]), tuple(tiles[3:6])
         if cache:
-            _cache_store(cache, key, {"tile": list(tile), "ms_per_step": ms.value})
-        return tile, self.steps_done() - s0
+            _cache_store(cache, key, {"tiles": [list(t1), list(t2)], "ms_per_step": list(ms)})
+        return (t1, t2), self.steps_done() - s0
 
     # ---- measurement
     def profile(self, cap):

@@ -84,8 +84,8 @@ def test_tile_candidates(H):
     """The autotuner's candidate tiles: every one supported, none repeated,
     kz values that differ in the chunks they give."""
     c3 = H.tile_candidates(3, (256, 256, 256))
-    assert len(c3) == 15 and len(set(c3)) == 15
-    assert {(tx, ty) for tx, ty, _ in c3} == {(32, 8), (64, 8), (16, 16)}
+    assert len(c3) == 20 and len(set(c3)) == 20
+    assert {(tx, ty) for tx, ty, _ in c3} == {(32, 8), (64, 8), (16, 16), (32, 16)}
     assert {kz for *_, kz in c3} == {0, 8, 16, 32, 64}        # 0: automatic
     # a short marching axis: kz beyond it gives the same single chunk
     assert {kz for *_, kz in H.tile_candidates(3, (64, 64, 12))} == {0, 8, 16}

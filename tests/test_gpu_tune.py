@@ -24,17 +24,17 @@ def test_autotune_steps_are_steps_of_the_run(H, tmp_path, ndim):
     cache = str(tmp_path / "tiles.json")
     say("autotune", ndim, c.n)
     h = gpu_mesh(c, H.MIXED)
-    tile, k = h.autotune(1, cache=cache)
+    tiles, k = h.autotune(1, cache=cache)
     cands = H.tile_candidates(ndim, c.n, H.MIXED)
-    assert tile in cands and k == len(cands) and h.get_tile() == tile
+    assert all(t in cands for t in tiles) and k == len(cands) and h.get_tile() == tiles
     ref = gpu_mesh(c, H.MIXED)
     ref.step_auto(k)
     assert bitwise_equal(h.get_state(), ref.get_state())
     assert h.time() == ref.time() and h.steps_done() == ref.steps_done() == k
     # a cached tile is set without steps
     h2 = gpu_mesh(c, H.MIXED)
-    assert h2.autotune(1, cache=cache) == (tile, 0)
-    assert h2.get_tile() == tile and h2.steps_done() == 0
+    assert h2.autotune(1, cache=cache) == (tiles, 0)
+    assert h2.get_tile() == tiles and h2.steps_done() == 0
     for x in (h, ref, h2):
         x.close()
 
@@ -60,14 +60,18 @@ def test_results_bitwise_independent_of_tile(H, ndim, prec):
     c = (wl.turbulence_3d(n=(72, 44, 40), mach=1.5, seed=25) if ndim == 3
          else wl.shear_layer_2d(200, 136, seed=4031))
     ref = None
-    for tile in H.tile_candidates(ndim, c.n, prec):
-        say("tile", ndim, prec, tile)
+    cands = H.tile_candidates(ndim, c.n, prec)
+    # every candidate for both stages, then mixed pairs
+    pairs = [(t, t) for t in cands] + list(zip(cands, cands[1:] + cands[:1]))
+    for t1, t2 in pairs:
+        say("tiles", ndim, prec, t1, t2)
         h = gpu_mesh(c, prec)
-        h.set_tile(*tile)
+        h.set_tile(*t1, stage=1)
+        h.set_tile(*t2, stage=2)
         h.step_auto(4)
         U = h.get_state()
         h.close()
         if ref is None:
             ref = U
         else:
-            assert bitwise_equal(U, ref), tile
+            assert bitwise_equal(U, ref), (t1, t2)

@@ -19,6 +19,8 @@
 // same formulas.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <cfloat>
 #include <cmath>
 
@@ -503,7 +505,13 @@ __device__ __forceinline__ void to_prim(double gm1, const double (&u)[NDIM + 2],
 // the plane (4 TX + 4 TY <= TX TY).
 // Work-groups per CU the compiler is asked to fit: the FP32 path keeps four
 // 256-thread groups per CU (16 waves); FP64 needs more registers per thread.
-template <typename R, int MODE>
+// The input ring and the one-barrier schedule pay in 3-D only: the 2-D
+// kernels (one row of 64..256 cells) already run many small work-groups per
+// CU, and measured slower with either.
+constexpr bool kRing2D = false;
+constexpr bool kOne2D = false;
+
+template <int NDIM, typename R, int MODE>
 struct StageOccupancy {
     // Input ring: the raw input values of a cell, read for its conversion
     // when its plane enters the z stencil, are kept in a three-plane LDS ring
@@ -511,8 +519,19 @@ struct StageOccupancy {
     // in the mixed stage 2, whose update also reads U^n: there the ring's
     // LDS sets the occupancy to three work-groups per CU, which the
     // register use of that kernel allows without spills.
-    static constexpr bool kRing = sizeof(R) == 4 && MODE == MODE_STAGE2;
-    static constexpr int kBlocks = sizeof(R) == 4 ? (kRing ? 3 : 4) : 2;
+    static constexpr bool kRing = sizeof(R) == 4 && MODE == MODE_STAGE2 && (NDIM == 3 || kRing2D);
+    // target waves per SIMD (the register budget the compiler aims for)
+    static constexpr int kWaves = sizeof(R) == 4 ? (kRing ? 3 : 4) : 2;
+    template <int NT>
+    static constexpr int blocks() {
+        return kWaves * 256 / NT > 0 ? kWaves * 256 / NT : 1;
+    }
+    // One barrier per plane (double-buffered W and flux tiles): measured
+    // faster for the mixed stage 1 and the FP64 stage 2; the mixed stage 2
+    // would need a fourth ring plane and lose a work-group per CU.
+    static constexpr bool kOneBarrier =
+        (NDIM == 3 || kOne2D) &&
+        ((sizeof(R) == 4 && MODE == MODE_STAGE1) || (sizeof(R) == 8 && MODE == MODE_STAGE2));
 };
 
 template <int NDIM, typename R, int MODE, int TX, int TY>
@@ -581,17 +600,26 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
     const double lam2 = dt / g.dx[2];
     const Gas<R> gr = make_gas<R>(g.gamma);
 
-    constexpr bool RING = StageOccupancy<R, MODE>::kRing && HZ;
-    __shared__ double sRaw[RING ? 3 : 1][RING ? NC : 1][RING ? NT : 1];
-    __shared__ R sW[NC][TY + 4][TX + 4];
-    __shared__ R sFx[NC][TY][TX + 1];
-    __shared__ R sFy[HY ? NC : 1][HY ? TY + 1 : 1][TX];
+    constexpr bool RING = StageOccupancy<NDIM, R, MODE>::kRing && HZ;
+    // One barrier per plane: plane k's W and fluxes go to buffer k & 1 and
+    // the update of plane k-1 follows the face pass of plane k, so the
+    // barrier that publishes plane k's W also publishes plane k-1's fluxes.
+    constexpr bool ONE = StageOccupancy<NDIM, R, MODE>::kOneBarrier;
+    constexpr int NB = ONE ? 2 : 1;
+    constexpr int RS = ONE ? 4 : 3;  // ring slots: planes k-1 .. k+2 live at once
+    __shared__ double sRaw[RING ? RS : 1][RING ? NC : 1][RING ? NT : 1];
+    __shared__ R sW[NB][NC][TY + 4][TX + 4];
+    using FT = R;
+    __shared__ FT sFx[NB][NC][TY][TX + 1];
+    __shared__ FT sFy[NB][HY ? NC : 1][HY ? TY + 1 : 1][TX];
 
     bool bad = false;
     double rate = 0.0;
     // z pipeline entering iteration k: W_k, W_{k+1}, d = W_{k+1} - W_k, the
-    // left state of face k+1/2 (W_k + delta_k / 2) and the flux of face k-1/2
-    R wk[NC], wk1[NC], dk[NC], lz[NC], fzl[NC];
+    // left state of face k+1/2 (W_k + delta_k / 2); fza, fzb: the fluxes of
+    // faces k-3/2 and k-1/2 (fzb only, without ONE)
+    R wk[NC], wk1[NC], dk[NC], lz[NC];
+    FT fza[NC], fzb[NC];
     double ui[NC];  // raw interior plane k+2 in flight (HZ)
     int vmi = VM_NONE;
 
@@ -613,7 +641,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
             to_prim<NDIM, R>(gm1, u, vm == VM_NONE ? -1 : 2, vm, w[s], bad);
             if (RING && s >= 2) {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) sRaw[RING ? (z0 - 2 + s) % 3 : 0][RING ? c : 0][RING ? tid : 0] = u[c];
+                for (int c = 0; c < NC; ++c) sRaw[RING ? (z0 - 2 + s) % RS : 0][RING ? c : 0][RING ? tid : 0] = u[c];
             }
         }
         // planes z0-2 .. z0+1: face z0-1/2 and the left state of face z0+1/2,
@@ -630,14 +658,23 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
             wk1[c] = w[3][c];
             dk[c] = d2;
         }
-        face_flux_states<NDIM, 2, R>(gr, wl, wr, fzl);
+        {
+            R f[NC];
+            face_flux_states<NDIM, 2, R>(gr, wl, wr, f);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) fzb[c] = (FT)f[c];
+        }
         load_interior(z0 + 2, ui, vmi);
     }
 
-    for (int k = z0; k < z1; ++k) {
-        R wc[NC];
-        R fzh[NC];
-        if (act) {
+    for (int k = z0; k < z1 + (ONE ? 1 : 0); ++k) {
+        const int bw = ONE ? (k & 1) : 0;        // buffer of plane k
+        const int ku = ONE ? k - 1 : k;          // plane updated in this iteration
+        const int bu = ONE ? (ku & 1) : 0;       // its buffer
+        const bool live = !ONE || k < z1;        // plane k exists (the last ONE iteration only updates)
+        FT fzc[NC];                              // flux of face k+1/2
+        if (live && act) {
+            R wc[NC];
             if (HZ) {
                 // W_{k+2} arrived: z face k+1/2 from (W_k, W_{k+1}, W_{k+2})
                 R w2[NC], wr[NC];
@@ -645,7 +682,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                 // plane k+2 is an interior plane whenever its update comes
                 if (RING) {
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) sRaw[RING ? (k + 2) % 3 : 0][RING ? c : 0][RING ? tid : 0] = ui[c];
+                    for (int c = 0; c < NC; ++c) sRaw[RING ? (k + 2) % RS : 0][RING ? c : 0][RING ? tid : 0] = ui[c];
                 }
                 // plane k+3 is W_{k'+2} of the next iteration k' = k+1; it lies at
                 // most two planes outside the mesh only while that iteration exists
@@ -662,7 +699,12 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                     wk1[c] = w2[c];
                     w2[c] = lnext;  // reuse: left state of face k+3/2
                 }
-                face_flux_states<NDIM, 2, R>(gr, lz, wr, fzh);
+                {
+                    R f[NC];
+                    face_flux_states<NDIM, 2, R>(gr, lz, wr, f);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) fzc[c] = (FT)f[c];
+                }
 #pragma unroll
                 for (int c = 0; c < NC; ++c) lz[c] = w2[c];
             } else {
@@ -671,49 +713,49 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                 to_prim<NDIM, R>(gm1, u, -1, VM_NONE, wc, bad);
             }
 #pragma unroll
-            for (int c = 0; c < NC; ++c) sW[c][ly + 2][lx + 2] = wc[c];
+            for (int c = 0; c < NC; ++c) sW[bw][c][ly + 2][lx + 2] = wc[c];
         }
-        if (hact) {
+        if (live && hact) {
             double uh[NC];
             R wh[NC];
             load_u<NC>(a.in, N, (long long)k * P + hcol, uh);
             // not checked here: every cell is checked by the tile that owns it
             to_prim<NDIM, R, false>(gm1, uh, hvax, hvm, wh, bad);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) sW[c][hy + 2][hx + 2] = wh[c];
+            for (int c = 0; c < NC; ++c) sW[bw][c][hy + 2][hx + 2] = wh[c];
         }
         __syncthreads();
 
-        // x faces: face i separates tile columns i-1 and i; LDS columns i..i+3
-        if (ly < ay && lx <= ax) {
-            R w0[NC], w1[NC], w2[NC], w3[NC], F[NC];
+        if (live) {
+            // x faces: face i separates tile columns i-1 and i; LDS columns i..i+3
+            if (ly < ay && lx <= ax) {
+                R w0[NC], w1[NC], w2[NC], w3[NC], F[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                w0[c] = sW[c][ly + 2][lx];
-                w1[c] = sW[c][ly + 2][lx + 1];
-                w2[c] = sW[c][ly + 2][lx + 2];
-                w3[c] = sW[c][ly + 2][lx + 3];
+                for (int c = 0; c < NC; ++c) {
+                    w0[c] = sW[bw][c][ly + 2][lx];
+                    w1[c] = sW[bw][c][ly + 2][lx + 1];
+                    w2[c] = sW[bw][c][ly + 2][lx + 2];
+                    w3[c] = sW[bw][c][ly + 2][lx + 3];
+                }
+                face_flux<NDIM, 0, R>(gr, w0, w1, w2, w3, F);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) sFx[bw][c][ly][lx] = (FT)F[c];
             }
-            face_flux<NDIM, 0, R>(gr, w0, w1, w2, w3, F);
+            if (HY && lx < ax && ly <= ay) {
+                R w0[NC], w1[NC], w2[NC], w3[NC], F[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) sFx[c][ly][lx] = F[c];
-        }
-        if (HY && lx < ax && ly <= ay) {
-            R w0[NC], w1[NC], w2[NC], w3[NC], F[NC];
+                for (int c = 0; c < NC; ++c) {
+                    w0[c] = sW[bw][c][ly][lx + 2];
+                    w1[c] = sW[bw][c][ly + 1][lx + 2];
+                    w2[c] = sW[bw][c][ly + 2][lx + 2];
+                    w3[c] = sW[bw][c][ly + 3][lx + 2];
+                }
+                face_flux<NDIM, 1, R>(gr, w0, w1, w2, w3, F);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                w0[c] = sW[c][ly][lx + 2];
-                w1[c] = sW[c][ly + 1][lx + 2];
-                w2[c] = sW[c][ly + 2][lx + 2];
-                w3[c] = sW[c][ly + 3][lx + 2];
+                for (int c = 0; c < NC; ++c) sFy[bw][HY ? c : 0][HY ? ly : 0][lx] = (FT)F[c];
             }
-            face_flux<NDIM, 1, R>(gr, w0, w1, w2, w3, F);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) sFy[HY ? c : 0][HY ? ly : 0][lx] = F[c];
-        }
-        // faces past the last thread column / row of a full tile; in 3-D the
-        // x and y ones share one code path (axis chosen per lane)
-        {
+            // faces past the last thread column / row of a full tile; in 3-D the
+            // x and y ones share one code path (axis chosen per lane)
             const int ex = (ax == TX) ? ay : 0;
             const int ey = (HY && ay == TY) ? ax : 0;
             for (int e = tid; e < ex + ey; e += NT) {
@@ -725,41 +767,44 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                     const int dr = yaxis ? 1 : 0, dc = yaxis ? 0 : 1;
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
-                        w0[c] = sW[c][r0][c0];
-                        w1[c] = sW[c][r0 + dr][c0 + dc];
-                        w2[c] = sW[c][r0 + 2 * dr][c0 + 2 * dc];
-                        w3[c] = sW[c][r0 + 3 * dr][c0 + 3 * dc];
+                        w0[c] = sW[bw][c][r0][c0];
+                        w1[c] = sW[bw][c][r0 + dr][c0 + dc];
+                        w2[c] = sW[bw][c][r0 + 2 * dr][c0 + 2 * dc];
+                        w3[c] = sW[bw][c][r0 + 3 * dr][c0 + 3 * dc];
                     }
                     face_flux_xy<R>(gr, yaxis, w0, w1, w2, w3, F);
                     if (yaxis) {
 #pragma unroll
-                        for (int c = 0; c < NC; ++c) sFy[c][TY][e - ex] = F[c];
+                        for (int c = 0; c < NC; ++c) sFy[bw][c][TY][e - ex] = (FT)F[c];
                     } else {
 #pragma unroll
-                        for (int c = 0; c < NC; ++c) sFx[c][e][TX] = F[c];
+                        for (int c = 0; c < NC; ++c) sFx[bw][c][e][TX] = (FT)F[c];
                     }
                 } else {
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
-                        w0[c] = sW[c][e + 2][TX];
-                        w1[c] = sW[c][e + 2][TX + 1];
-                        w2[c] = sW[c][e + 2][TX + 2];
-                        w3[c] = sW[c][e + 2][TX + 3];
+                        w0[c] = sW[bw][c][e + 2][TX];
+                        w1[c] = sW[bw][c][e + 2][TX + 1];
+                        w2[c] = sW[bw][c][e + 2][TX + 2];
+                        w3[c] = sW[bw][c][e + 2][TX + 3];
                     }
                     face_flux<NDIM, 0, R>(gr, w0, w1, w2, w3, F);
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) sFx[c][e][TX] = F[c];
+                    for (int c = 0; c < NC; ++c) sFx[bw][c][e][TX] = (FT)F[c];
                 }
             }
         }
-        __syncthreads();
+        if (!ONE) __syncthreads();
 
-        if (act) {
-            const long long cell = (long long)k * P + col;
+        if (act && ku >= z0) {
+            const long long cell = (long long)ku * P + col;
+            // z fluxes of faces ku-1/2 and ku+1/2
+            const FT(&zlo)[NC] = ONE ? fza : fzb;
+            const FT(&zhi)[NC] = ONE ? fzb : fzc;
             double uin[NC], ubase[NC];
             if (RING) {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) uin[c] = sRaw[RING ? k % 3 : 0][RING ? c : 0][RING ? tid : 0];
+                for (int c = 0; c < NC; ++c) uin[c] = sRaw[RING ? ku % RS : 0][RING ? c : 0][RING ? tid : 0];
             } else if (MODE != MODE_RHS) {
                 load_u<NC>(a.in, N, cell, uin);
             }
@@ -768,11 +813,11 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 double acc = 0.0;
-                acc = acc + lam0 * ((double)sFx[c][ly][lx] - (double)sFx[c][ly][lx + 1]);
+                acc = acc + lam0 * ((double)sFx[bu][c][ly][lx] - (double)sFx[bu][c][ly][lx + 1]);
                 if (HY)
-                    acc = acc + lam1 * ((double)sFy[HY ? c : 0][HY ? ly : 0][lx] -
-                                        (double)sFy[HY ? c : 0][HY ? ly + 1 : 0][lx]);
-                if (HZ) acc = acc + lam2 * ((double)fzl[c] - (double)fzh[c]);
+                    acc = acc + lam1 * ((double)sFy[bu][HY ? c : 0][HY ? ly : 0][lx] -
+                                        (double)sFy[bu][HY ? c : 0][HY ? ly + 1 : 0][lx]);
+                if (HZ) acc = acc + lam2 * ((double)zlo[c] - (double)zhi[c]);
                 double r;
                 if (MODE == MODE_RHS)
                     r = acc;
@@ -789,9 +834,12 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                 const double cr = cfl_rate<NDIM>(g, w);
                 rate = cr > rate ? cr : rate;
             }
-            if (HZ) {
+        }
+        if (HZ && act) {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) fzl[c] = fzh[c];
+            for (int c = 0; c < NC; ++c) {
+                if (ONE) fza[c] = fzb[c];
+                fzb[c] = fzc[c];
             }
         }
     }
@@ -811,7 +859,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
 }
 
 template <int NDIM, typename R, int MODE, int TX, int TY>
-__global__ __launch_bounds__(TX * TY, (StageOccupancy<R, MODE>::kBlocks)) void stage_kernel(StageArgs a) {
+__global__ __launch_bounds__(TX * TY, (StageOccupancy<NDIM, R, MODE>::template blocks<TX * TY>())) void stage_kernel(StageArgs a) {
     if (a.use_device_dt && a.ctrl->done) return;  // uniform over the grid
     stage_body<NDIM, R, MODE, TX, TY>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
@@ -819,7 +867,7 @@ __global__ __launch_bounds__(TX * TY, (StageOccupancy<R, MODE>::kBlocks)) void s
 // Batched stage: work-group -> (member, work-group of the member) from a
 // table; members that reached their run limit are skipped.
 template <int NDIM, typename R, int MODE, int TX, int TY>
-__global__ __launch_bounds__(TX * TY, (StageOccupancy<R, MODE>::kBlocks)) void stage_kernel_batch(
+__global__ __launch_bounds__(TX * TY, (StageOccupancy<NDIM, R, MODE>::template blocks<TX * TY>())) void stage_kernel_batch(
     const MeshDesc* __restrict__ descs, const int2* __restrict__ blk) {
     const int2 e = blk[xcd_remap(blockIdx.x, gridDim.x)];
     const MeshDesc& d = descs[e.x];

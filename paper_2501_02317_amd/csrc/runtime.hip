@@ -492,13 +492,15 @@ int hydro_autotune(hydro_t h, int steps_per_tile, double t_end, int* tiles, doub
     // a run that reached its limit while tuning skipped steps: no valid timing
     if (h->host_ctrl->done || nc < 1) return HYDRO_E_STATE;
     for (int st = 0; st < 2; ++st) {
-        // the tile in use stays unless a candidate is faster by more than 2 %,
-        // so close timings do not flip the choice from run to run
-        int best = -1;
+        // the tile in use stays unless a candidate is faster by more than 5 %
+        // (about the run-to-run spread of a few steps' timing), so close
+        // timings do not flip the choice from run to run
+        int keep_c = -1, best = -1;
         for (int c = 0; c < nc; ++c)
-            if (cand[c].tx == keep[st].tx && cand[c].ty == keep[st].ty && cand[c].kz == keep[st].kz) best = c;
+            if (cand[c].tx == keep[st].tx && cand[c].ty == keep[st].ty && cand[c].kz == keep[st].kz) keep_c = c;
         for (int c = 0; c < nc; ++c)
-            if (best < 0 || ms[2 * c + st] < 0.98 * ms[2 * best + st]) best = c;
+            if (best < 0 || ms[2 * c + st] < ms[2 * best + st]) best = c;
+        if (keep_c >= 0 && !(ms[2 * best + st] < 0.95 * ms[2 * keep_c + st])) best = keep_c;
         h->tile[st] = cand[best];
         tiles[3 * st] = cand[best].tx;
         tiles[3 * st + 1] = cand[best].ty;

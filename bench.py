@@ -43,7 +43,10 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 2-D workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--batch-count", type=int, default=512)
-    ap.add_argument("--serve-count", type=int, default=300)
+    ap.add_argument("--serve-count", type=int, default=2000)
+    ap.add_argument("--serve-calib", type=int, default=300,
+                    help="requests of the saturation run that measures capacity (and of its "
+                         "one-at-a-time baseline)")
     ap.add_argument("--tile", default="",
                     help="fixed tile tx,ty,kz (kz 0: automatic) for both stages instead of autotuning")
     ap.add_argument("--no-tune", action="store_true",
@@ -161,29 +164,36 @@ def run_batch(H, wl, count, steps, precision):
             "launch_groups": info["groups"], "graph": info["graph"]}
 
 
-def run_serving(count):
-    """Served capacity at saturation (all requests at t = 0) against the same
-    requests served one at a time; then a Poisson stream offered at 0.8 x the
-    measured capacity, with p50/p99 completion latency."""
+def run_serving(count, calib):
+    """Served capacity at saturation (calib requests, all at t = 0) against
+    the same requests served one at a time; then a Poisson stream of count
+    requests offered at 0.8 x the measured capacity, with p50/p99 completion
+    latency."""
     from paper_2501_02317_amd import serving as S
-    sat = S.request_stream(count, 1.0, seed=502)
+
+    def log(line):
+        print(line, file=sys.stderr, flush=True)
+
+    sat = S.request_stream(calib, 1.0, seed=502)
     for r in sat:
         r.arrival = 0.0
     work = sum(r.cells * r.steps for r in sat)
-    t_served = S.Server(96 << 30, steps_per_iter=16).run(sat, time_limit=300.0)
+    t_served = S.Server(96 << 30, steps_per_iter=16).run(sat, time_limit=300.0, log=log)
     capacity = work / t_served
     t0 = time.perf_counter()
-    for r in S.request_stream(count, 1.0, seed=502):
+    for r in S.request_stream(calib, 1.0, seed=502):
         S.serve_alone(r)
     t_one = time.perf_counter() - t0
+    log(f"[serve] capacity {capacity:.3e} cell-updates/s, one at a time {work / t_one:.3e}")
     rate = 0.8 * capacity / S.mean_work()
     reqs = S.request_stream(count, rate, seed=501)
     srv = S.Server(96 << 30, steps_per_iter=16)
-    srv.run(reqs, time_limit=300.0)
+    srv.run(reqs, time_limit=600.0, log=log)
     rep = S.latency_report(reqs)
     rep["offered_rate_per_s"] = rate
     rep["offered_load_frac"] = 0.8
     rep["requests"] = count
+    rep["calibration_requests"] = calib
     rep["iterations"] = srv.iterations
     rep["saturated_cell_updates_per_s"] = capacity
     rep["one_at_a_time_cell_updates_per_s"] = work / t_one
@@ -295,7 +305,7 @@ def main():
               f"{out['batch']['one_at_a_time_cell_updates_per_s']:.3e}", file=sys.stderr, flush=True)
     if not args.no_serve:
         print("[bench] serving ...", file=sys.stderr, flush=True)
-        out["serving"] = run_serving(args.serve_count)
+        out["serving"] = run_serving(args.serve_count, args.serve_calib)
         print(f"[bench] serving: p50 {out['serving']['p50_s']:.3f} s p99 {out['serving']['p99_s']:.3f} s",
               file=sys.stderr, flush=True)
     if not args.no_cpu:

@@ -176,10 +176,11 @@ int hydro_get_stage_tile(hydro_t h, int stage, int* tx, int* ty, int* kz);
  * (HYDRO_E_INVAL for an invalid configuration or max < 0). */
 int hydro_tile_candidates(const hydro_config* cfg, int* tiles, int max);
 
-/* Autotuner.  Advances the run by steps_per_tile real Heun steps per
- * candidate tile (device-resident dt as in hydro_step_auto, t_end 0 = no
- * clamp), timing each stage with HIP events, and sets each stage's fastest
- * tile; the tile in use is kept unless a candidate beats it by more than 5 %.
+/* Autotuner.  Advances the run by one untimed step and then steps_per_tile
+ * real Heun steps per candidate tile, the candidates taking turns (device-
+ * resident dt as in hydro_step_auto, t_end 0 = no clamp), timing each stage
+ * with HIP events, and sets each stage's fastest tile; the tile in use is
+ * kept unless a candidate beats it by more than 5 %.
  * tiles receives 6 ints (stage 1 tx, ty, kz, then stage 2) and ms_per_step
  * 2 doubles (the chosen tiles' stage times per step).  The steps are part of
  * the run (results do not depend on the tiles), so tuning can replace

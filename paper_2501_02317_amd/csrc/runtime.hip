@@ -454,10 +454,13 @@ int hydro_autotune(hydro_t h, int steps_per_tile, double t_end, int* tiles, doub
     const Tile keep[2] = {h->tile[0], h->tile[1]};
     // The tuning steps are real steps of the run (the results do not depend
     // on the tile): enqueue_step's launches with events between the stages.
+    // One untimed step first, then the candidates in turn, round after round,
+    // so clock ramp-up or drift does not favour the candidates timed last.
     if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_SET_LIMITS, t_end, 0.0, h->cfg.cfl, h->stream);
     if (e == hipSuccess && !h->dt_valid) e = enqueue_dt(h);
-    for (int c = 0; c < nc && e == hipSuccess; ++c) {
-        for (int s = 0; s < steps_per_tile && e == hipSuccess; ++s) {
+    if (e == hipSuccess) e = enqueue_step(h, true, 0.0);
+    for (int s = 0; s < steps_per_tile && e == hipSuccess; ++s) {
+        for (int c = 0; c < nc && e == hipSuccess; ++c) {
             hipEvent_t* q = &ev[((size_t)c * steps_per_tile + s) * 3];
             StageArgs a = stage_args(h);
             a.use_device_dt = 1;

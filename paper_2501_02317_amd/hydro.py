@@ -260,7 +260,8 @@ class Hydro:
         """Pick each stage's fastest tile.  With a cache file (JSON) tiles
         stored for the same device, dimensionality, size and precision are
         set directly; otherwise hydro_autotune times every candidate over
-        real steps of this run and the winners are stored.  Returns
+        real steps of this run (after one untimed step) and the winners are
+        stored.  Returns
         ((stage-1 tile, stage-2 tile), steps advanced)."""
         key = None
         if cache:

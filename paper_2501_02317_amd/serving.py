@@ -161,9 +161,11 @@ class Server:
         r.admitted = now
         return {"req": r, "h": h, "off": off, "W": W}
 
-    def run(self, requests, time_limit=None):
-        """Serve requests (their arrival fields are offsets from the start)."""
+    def run(self, requests, time_limit=None, log=None, log_every=10.0):
+        """Serve requests (their arrival fields are offsets from the start).
+        log: optional callable given a progress line every log_every seconds."""
         pending = collections.deque(sorted(requests, key=lambda q: q.arrival))
+        total, finished, next_log = len(pending), 0, log_every
         queue = collections.deque()
         active = []
         batch = None
@@ -201,6 +203,7 @@ class Server:
                 if d or f:
                     r = m["req"]
                     r.finished = now
+                    finished += 1
                     r.failed = bool(f)
                     if r.rid in self.keep:
                         r.result = m["h"].get_state()
@@ -210,6 +213,10 @@ class Server:
                 else:
                     keep.append(m)
             active = keep
+            if log is not None and now >= next_log:
+                log(f"[serve] {now:.0f} s: {finished}/{total} finished, {len(active)} resident, "
+                    f"{len(queue)} queued, {self.iterations} iterations")
+                next_log = now + log_every
         if batch is not None:
             batch.close()
         for m in active:
@@ -224,6 +231,7 @@ def latency_report(requests, warmup_frac=0.05):
     skip = int(len(done) * warmup_frac)
     lat = np.array([r.finished - r.arrival for r in done[skip:]])
     wait = np.array([r.admitted - r.arrival for r in done[skip:]])
+    serv = np.array([r.finished - r.admitted for r in done[skip:]])
     work = sum(r.cells * r.steps for r in done)
     t0 = min(r.arrival for r in requests)
     t1 = max(r.finished for r in done) if done else t0
@@ -233,6 +241,7 @@ def latency_report(requests, warmup_frac=0.05):
         "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
         "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
         "mean_queue_s": float(wait.mean()) if len(wait) else None,
+        "mean_service_s": float(serv.mean()) if len(serv) else None,
         "cell_updates_per_s": work / (t1 - t0) if t1 > t0 else None,
     }
 

@@ -58,7 +58,7 @@ def test_results_in_the_mix_equal_alone():
     import torch
     assert torch.cuda.is_available()
     from paper_2501_02317_amd import serving as S
-    reqs = S.request_stream(16, 400.0, seed=11, n2=(64, 160), n3=(32, 48), steps=(10, 40))
+    reqs = S.request_stream(32, 800.0, seed=11, n2=(64, 160), n3=(32, 48), steps=(10, 40))
     say("serving mix", len(reqs))
     srv = S.Server(2 << 30, steps_per_iter=8, keep_results=[r.rid for r in reqs])
     srv.run(reqs)

@@ -137,6 +137,8 @@ def run_batch(H, wl, count, steps, precision):
     cells = sum(c.ncells for c in cases)
     b = H.Batch(ms, use_graph=True)
     reset()
+    rule, _ = b.autotune(2)                       # tile rule for the batch (real steps)
+    reset()
     b.step(steps)                                 # warm-up: captures the graph
     s.synchronize()
     reset()
@@ -161,7 +163,7 @@ def run_batch(H, wl, count, steps, precision):
             "batched_cell_updates_per_s": cells * steps / t_batch,
             "one_at_a_time_cell_updates_per_s": cells * steps / t_one,
             "speedup": t_one / t_batch, "batched_s": t_batch, "one_at_a_time_s": t_one,
-            "launch_groups": info["groups"], "graph": info["graph"]}
+            "launch_groups": info["groups"], "graph": info["graph"], "tile_rule": rule}
 
 
 def run_serving(count, calib):

@@ -223,6 +223,21 @@ size_t hydro_batch_workspace_bytes(int n, const hydro_t* members);
 int hydro_batch_create(int n, const hydro_t* members, void* d_workspace, size_t nbytes, int use_graph,
                        hydro_batch_t* out);
 int hydro_batch_step(hydro_batch_t b, int nsteps);
+
+/* Batch autotuner.  Tries tile rules for the members of one or two
+ * dimensions (a common row width of 64, 128 or 256 cells or each member's
+ * own, with each member's own or a fixed chunk length of 16, 32 or 64
+ * planes; 3-D members keep their tiles) by timing steps_per_rule batched
+ * steps per rule, the rules taking turns after one untimed step, and keeps
+ * the fastest rule (the members' own tiles unless beaten by more than 5 %):
+ * it becomes the members' tile for both stages.  The steps are real steps of
+ * every member (the results do not depend on the tiles) and count against
+ * their run limits.  *rule receives the rule index (0: members' own tiles)
+ * and *ms_per_step its time per batched step.  Blocks.  steps_per_rule in
+ * [1, 64].  The batch workspace (hydro_batch_workspace_bytes) is sized for
+ * every rule. */
+int hydro_batch_autotune(hydro_batch_t b, int steps_per_rule, int* rule, double* ms_per_step);
+
 /* Per-member run-limit flag (done[i] = 1 once member i reached its limit),
  * optional completed step counts and sticky error flags (bit 0:
  * non-physical state); blocks on the batch stream. */

@@ -654,24 +654,46 @@ struct BatchPlan {
     std::vector<hydro_batch_ctx::Group> groups;
 };
 
+// Tile rules of the batch autotuner for members of one or two dimensions:
+// a row width for every such member (0: the member's own) and a chunk length
+// (-1: the member's own, 0: about 2048 work-groups per member).  Rule 0
+// keeps every member's tile.  3-D members keep their tiles.
+struct BatchRule {
+    int tx, kz;
+};
+constexpr BatchRule kBatchRules[] = {{0, -1}, {64, -1}, {128, -1}, {256, -1}, {0, 16},   {64, 16},
+                                     {128, 16}, {0, 32}, {64, 32},   {128, 32},  {0, 64},  {64, 64}};
+constexpr int kNumBatchRules = (int)(sizeof(kBatchRules) / sizeof(kBatchRules[0]));
+
+Tile rule_tile(const hydro_t h, int rule) {
+    Tile t = h->tile[0];
+    if (h->cfg.ndim == 3 || rule <= 0 || rule >= kNumBatchRules) return t;
+    if (kBatchRules[rule].tx > 0) t.tx = kBatchRules[rule].tx;
+    if (kBatchRules[rule].kz >= 0) t.kz = kBatchRules[rule].kz;
+    return t;
+}
+
 // Members grouped by (ndim, precision, tile); each group's work-groups are
 // contiguous in the table, members in the caller's order within a group.
-bool plan_batch(int n, const hydro_t* members, BatchPlan& P) {
+// Member i runs tile rule_tile(members[i], rule).
+bool plan_batch(int n, const hydro_t* members, BatchPlan& P, int rule = 0) {
     P.desc.resize(n);
     std::vector<int> order(n);
+    std::vector<Tile> tiles(n);
     for (int i = 0; i < n; ++i) {
         const hydro_t h = members[i];
+        tiles[i] = rule_tile(h, rule);
         MeshDesc& d = P.desc[i];
         d.U = h->U;
         d.U1 = h->U1;
         d.ctrl = h->ctrl;
         d.geo = h->geo;
-        plan_tiles(h->geo, h->tile[0], d.tiles_x, d.tiles_y, d.chunks_z, d.kz);
+        plan_tiles(h->geo, tiles[i], d.tiles_x, d.tiles_y, d.chunks_z, d.kz);
         order[i] = i;
     }
     auto key = [&](int i) {
         const hydro_t h = members[i];
-        return std::make_tuple(h->cfg.ndim, h->cfg.precision, h->tile[0].tx, h->tile[0].ty);
+        return std::make_tuple(h->cfg.ndim, h->cfg.precision, tiles[i].tx, tiles[i].ty);
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
     for (int idx = 0; idx < n; ++idx) {
@@ -681,7 +703,7 @@ bool plan_batch(int n, const hydro_t* members, BatchPlan& P) {
             hydro_batch_ctx::Group g;
             g.ndim = h->cfg.ndim;
             g.precision = h->cfg.precision;
-            g.tile = h->tile[0];
+            g.tile = tiles[i];
             g.blk_off = (int)P.blk.size();
             g.nblk = 0;
             P.groups.push_back(g);
@@ -740,9 +762,14 @@ extern "C" {
 
 size_t hydro_batch_workspace_bytes(int n, const hydro_t* members) {
     if (!members_ok(n, members)) return 0;
-    BatchPlan P;
-    if (!plan_batch(n, members, P)) return 0;
-    return batch_bytes(P);
+    // large enough for the work-group table of any tile rule the autotuner tries
+    size_t most = 0;
+    for (int r = 0; r < kNumBatchRules; ++r) {
+        BatchPlan P;
+        if (!plan_batch(n, members, P, r)) return 0;
+        most = std::max(most, batch_bytes(P));
+    }
+    return most;
 }
 
 int hydro_batch_create(int n, const hydro_t* members, void* d_workspace, size_t nbytes, int use_graph,
@@ -751,7 +778,7 @@ int hydro_batch_create(int n, const hydro_t* members, void* d_workspace, size_t 
     if (((uintptr_t)d_workspace) % kAlign != 0) return HYDRO_E_INVAL;
     BatchPlan P;
     if (!plan_batch(n, members, P)) return HYDRO_E_INVAL;
-    if (nbytes < batch_bytes(P)) return HYDRO_E_INVAL;
+    if (nbytes < hydro_batch_workspace_bytes(n, members)) return HYDRO_E_INVAL;
     hydro_batch_ctx* b = new (std::nothrow) hydro_batch_ctx;
     if (!b) return HYDRO_E_NOMEM;
     b->members.assign(members, members + n);
@@ -820,6 +847,76 @@ int hydro_batch_step(hydro_batch_t b, int nsteps) {
         return HYDRO_E_DEVICE;
     }
     for (hydro_t h : b->members) h->dt_valid = true;
+    return HYDRO_OK;
+}
+
+int hydro_batch_autotune(hydro_batch_t b, int steps_per_rule, int* rule_out, double* ms_per_step) {
+    if (!b || !rule_out || !ms_per_step || steps_per_rule < 1 || steps_per_rule > 64) return HYDRO_E_INVAL;
+    if (b->broken) return HYDRO_E_STATE;
+    const int n = (int)b->members.size();
+    for (hydro_t h : b->members)
+        if (h->broken) return HYDRO_E_STATE;
+    std::vector<BatchPlan> plans(kNumBatchRules);
+    for (int r = 0; r < kNumBatchRules; ++r)
+        if (!plan_batch(n, b->members.data(), plans[r], r)) return HYDRO_E_INVAL;
+    drop_graph(b);
+    std::vector<hipEvent_t> ev((size_t)kNumBatchRules * steps_per_rule * 2);
+    size_t made = 0;
+    hipError_t e = hipSuccess;
+    for (; made < ev.size() && e == hipSuccess; ++made) e = hipEventCreate(&ev[made]);
+    if (e != hipSuccess) --made;
+    auto upload = [&](const BatchPlan& P) {
+        hipError_t x = hipMemcpyAsync(b->d_desc, P.desc.data(), P.desc.size() * sizeof(MeshDesc),
+                                      hipMemcpyHostToDevice, b->stream);
+        if (x == hipSuccess)
+            x = hipMemcpyAsync(b->d_blk, P.blk.data(), P.blk.size() * sizeof(int2), hipMemcpyHostToDevice,
+                               b->stream);
+        if (x == hipSuccess) x = hipStreamSynchronize(b->stream);  // P's host data in use until here
+        b->groups = P.groups;
+        return x;
+    };
+    for (hydro_t h : b->members)
+        if (!h->dt_valid && e == hipSuccess) e = enqueue_dt(h);
+    // one untimed step, then the rules in turn, round after round (real steps
+    // of every member; the results do not depend on the tiles)
+    if (e == hipSuccess) e = enqueue_batch_step(b);
+    for (int s = 0; s < steps_per_rule && e == hipSuccess; ++s)
+        for (int r = 0; r < kNumBatchRules && e == hipSuccess; ++r) {
+            hipEvent_t* q = &ev[((size_t)s * kNumBatchRules + r) * 2];
+            e = upload(plans[r]);
+            if (e == hipSuccess) e = hipEventRecord(q[0], b->stream);
+            if (e == hipSuccess) e = enqueue_batch_step(b);
+            if (e == hipSuccess) e = hipEventRecord(q[1], b->stream);
+        }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    std::vector<double> ms(kNumBatchRules, 0.0);
+    for (int s = 0; s < steps_per_rule && e == hipSuccess; ++s)
+        for (int r = 0; r < kNumBatchRules && e == hipSuccess; ++r) {
+            const hipEvent_t* q = &ev[((size_t)s * kNumBatchRules + r) * 2];
+            float t = 0.0f;
+            e = hipEventElapsedTime(&t, q[0], q[1]);
+            ms[r] += t;
+        }
+    for (size_t i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+    int best = 0;
+    if (e == hipSuccess) {
+        // rule 0 (the members' own tiles) stays unless beaten by more than 5 %
+        for (int r = 1; r < kNumBatchRules; ++r)
+            if (ms[r] < ms[best]) best = r;
+        if (!(ms[best] < 0.95 * ms[0])) best = 0;
+        for (hydro_t h : b->members)
+            if (h->cfg.ndim < 3) h->tile[0] = h->tile[1] = rule_tile(h, best);
+        BatchPlan P;
+        if (!plan_batch(n, b->members.data(), P, 0)) e = hipErrorInvalidValue;
+        if (e == hipSuccess) e = upload(P);
+    }
+    if (e != hipSuccess) {
+        b->broken = true;
+        return HYDRO_E_DEVICE;
+    }
+    for (hydro_t h : b->members) h->dt_valid = true;
+    *rule_out = best;
+    *ms_per_step = ms[best] / steps_per_rule;
     return HYDRO_OK;
 }
 

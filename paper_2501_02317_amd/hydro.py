@@ -54,6 +54,7 @@ _SIG = {
                                        C.POINTER(C.c_int)]),
     "hydro_tile_candidates": (C.c_int, [C.POINTER(Config), C.POINTER(C.c_int), C.c_int]),
     "hydro_autotune": (C.c_int, [_h, C.c_int, C.c_double, C.POINTER(C.c_int), _dp]),
+    "hydro_batch_autotune": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int), _dp]),
     "hydro_profile": (C.c_int, [_h, C.c_int]),
     "hydro_profile_read": (C.c_int, [_h, _dp, _dp, C.POINTER(C.c_int64)]),
     "hydro_set_run_limit": (C.c_int, [_h, C.c_int64, C.c_double]),
@@ -335,6 +336,14 @@ class Batch:
         fl = (C.c_int * n)()
         _check(_lib.hydro_batch_status(self._b, d, st, fl), "hydro_batch_status")
         return list(d), list(st), list(fl)
+
+    def autotune(self, steps_per_rule=2):
+        """Pick the fastest tile rule for the batch's 1-D/2-D members over real
+        batched steps; returns (rule index, ms per batched step)."""
+        r, ms = C.c_int(), C.c_double()
+        _check(_lib.hydro_batch_autotune(self._b, int(steps_per_rule), C.byref(r), C.byref(ms)),
+               "hydro_batch_autotune")
+        return r.value, ms.value
 
     def info(self):
         g, w, gr = C.c_int(), C.c_int64(), C.c_int()

@@ -137,3 +137,30 @@ def test_batch_workload_subset_tracks_oracle(H, precision, tol):
         assert np.all(err <= tol), (c.name, err)
         assert abs(t - t_o) <= (1e-14 if prec == 0 else 1e-6) * t_o
     print("worst relL1 per component", worst)
+
+
+def test_batch_autotune_steps_are_steps_of_the_run(H):
+    """The batch autotuner's timing steps are ordinary batched steps: tuned
+    then stepped equals stepped straight through, bitwise."""
+    import torch
+    cases = [(c, p, 0, 0.0) for c, p, _, _ in member_cases()]
+    say("batch autotune")
+    s = torch.cuda.Stream()
+    A = [make(H, c, p, s) for c, p, _, _ in cases]
+    B = [make(H, c, p, s) for c, p, _, _ in cases]
+    ba = H.Batch(A, use_graph=True)
+    rule, ms = ba.autotune(2)
+    k = A[0].steps_done()
+    assert k == 1 + 2 * 12 and all(h.steps_done() == k for h in A)
+    ba.step(5)
+    bb = H.Batch(B, use_graph=True)
+    bb.step(k + 5)
+    s.synchronize()
+    for (c, *_), ha, hb in zip(cases, A, B):
+        assert bitwise_equal(ha.get_state(), hb.get_state()), c.name
+        assert ha.time() == hb.time()
+    print("chosen rule", rule, "ms per step", ms, ba.info())
+    for x in (ba, bb):
+        x.close()
+    for h in A + B:
+        h.close()

@@ -520,15 +520,19 @@ struct StageOccupancy {
     // LDS sets the occupancy to three work-groups per CU, which the
     // register use of that kernel allows without spills.
     static constexpr bool kRing = sizeof(R) == 4 && MODE == MODE_STAGE2 && (NDIM == 3 || kRing2D);
-    // target waves per SIMD (the register budget the compiler aims for)
+    // occupancy range (waves per SIMD) the compiler aims for: at least
+    // kWaves (its register budget), at most kWavesMax (8: no bound)
     static constexpr int kWaves = sizeof(R) == 4 ? (kRing ? 3 : 4) : 2;
-    template <int NT>
-    static constexpr int blocks() {
-        return kWaves * 256 / NT > 0 ? kWaves * 256 / NT : 1;
-    }
+    static constexpr int kWavesMax = 8;
     // One barrier per plane (double-buffered W and flux tiles): measured
     // faster for the mixed stage 1 and the FP64 stage 2; the mixed stage 2
     // would need a fourth ring plane and lose a work-group per CU.
+    // The marching loop unrolled by two with two prefetch buffers, so that
+    // the prefetched plane is not copied between loop-carried registers
+    // (which makes the compiler wait for the load in the iteration that
+    // issued it).  It pays where registers allow: the mixed 3-D stage 2; the
+    // mixed stage 1 would spill at its four-wave register budget.
+    static constexpr bool kUnroll2 = NDIM == 3 && sizeof(R) == 4 && MODE == MODE_STAGE2;
     static constexpr bool kOneBarrier =
         (NDIM == 3 || kOne2D) &&
         ((sizeof(R) == 4 && MODE == MODE_STAGE1) || (sizeof(R) == 8 && MODE == MODE_STAGE2));
@@ -620,8 +624,10 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
     // faces k-3/2 and k-1/2 (fzb only, without ONE)
     R wk[NC], wk1[NC], dk[NC], lz[NC];
     FT fza[NC], fzb[NC];
-    double ui[NC];  // raw interior plane k+2 in flight (HZ)
-    int vmi = VM_NONE;
+    // raw interior plane k+2 in flight (HZ), in two buffers that alternate
+    // between iterations so a load lands directly where it is consumed
+    double uiA[NC], uiB[NC];
+    int vmA = VM_NONE, vmB = VM_NONE;
 
     // interior plane z (any z: outside the mesh it is a ghost plane)
     auto load_interior = [&](int z, double (&u)[NC], int& vm) {
@@ -664,10 +670,14 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) fzb[c] = (FT)f[c];
         }
-        load_interior(z0 + 2, ui, vmi);
+        load_interior(z0 + 2, uiA, vmA);
     }
 
-    for (int k = z0; k < z1 + (ONE ? 1 : 0); ++k) {
+    // One iteration: plane k enters the stencil (its raw data ui, the ghost
+    // treatment vmi), plane k+3 is loaded into un (vmn), and one plane is
+    // updated.
+    auto plane = [&](const int k, double(&ui)[NC], int& vmi, double(&un)[NC],
+                     int& vmn) __attribute__((always_inline)) {
         const int bw = ONE ? (k & 1) : 0;        // buffer of plane k
         const int ku = ONE ? k - 1 : k;          // plane updated in this iteration
         const int bu = ONE ? (ku & 1) : 0;       // its buffer
@@ -686,7 +696,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                 }
                 // plane k+3 is W_{k'+2} of the next iteration k' = k+1; it lies at
                 // most two planes outside the mesh only while that iteration exists
-                if (k + 1 < z1) load_interior(k + 3, ui, vmi);
+                if (k + 1 < z1) load_interior(k + 3, un, vmn);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const R d2 = w2[c] - wk1[c];
@@ -842,6 +852,16 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                 fzb[c] = fzc[c];
             }
         }
+    };
+
+    const int kend = z1 + (ONE ? 1 : 0);
+    if constexpr (StageOccupancy<NDIM, R, MODE>::kUnroll2 && HZ) {
+        for (int k = z0; k < kend; k += 2) {
+            plane(k, uiA, vmA, uiB, vmB);
+            if (k + 1 < kend) plane(k + 1, uiB, vmB, uiA, vmA);
+        }
+    } else {
+        for (int k = z0; k < kend; ++k) plane(k, uiA, vmA, uiA, vmA);
     }
 
     if (bad) atomicOr(&a.ctrl->flags, FLAG_NONPHYSICAL);
@@ -859,7 +879,9 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
 }
 
 template <int NDIM, typename R, int MODE, int TX, int TY>
-__global__ __launch_bounds__(TX * TY, (StageOccupancy<NDIM, R, MODE>::template blocks<TX * TY>())) void stage_kernel(StageArgs a) {
+__global__ __launch_bounds__(TX * TY)
+__attribute__((amdgpu_waves_per_eu(StageOccupancy<NDIM, R, MODE>::kWaves, StageOccupancy<NDIM, R, MODE>::kWavesMax)))
+void stage_kernel(StageArgs a) {
     if (a.use_device_dt && a.ctrl->done) return;  // uniform over the grid
     stage_body<NDIM, R, MODE, TX, TY>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
@@ -867,7 +889,9 @@ __global__ __launch_bounds__(TX * TY, (StageOccupancy<NDIM, R, MODE>::template b
 // Batched stage: work-group -> (member, work-group of the member) from a
 // table; members that reached their run limit are skipped.
 template <int NDIM, typename R, int MODE, int TX, int TY>
-__global__ __launch_bounds__(TX * TY, (StageOccupancy<NDIM, R, MODE>::template blocks<TX * TY>())) void stage_kernel_batch(
+__global__ __launch_bounds__(TX * TY)
+__attribute__((amdgpu_waves_per_eu(StageOccupancy<NDIM, R, MODE>::kWaves, StageOccupancy<NDIM, R, MODE>::kWavesMax)))
+void stage_kernel_batch(
     const MeshDesc* __restrict__ descs, const int2* __restrict__ blk) {
     const int2 e = blk[xcd_remap(blockIdx.x, gridDim.x)];
     const MeshDesc& d = descs[e.x];

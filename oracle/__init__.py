@@ -22,7 +22,11 @@ BC_PERIODIC, BC_FREE, BC_OUTFLOW, BC_REFLECT = 0, 1, 2, 3
 
 class _Mesh(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 3), ("lo", C.c_double * 3),
-                ("hi", C.c_double * 3), ("gamma", C.c_double), ("bc", (C.c_int32 * 2) * 3)]
+                ("hi", C.c_double * 3), ("gamma", C.c_double), ("bc", (C.c_int32 * 2) * 3),
+                ("integrator", C.c_int32)]
+
+
+HEUN, VL2 = 0, 1
 
 
 @dataclass
@@ -33,6 +37,7 @@ class Mesh:
     lo: tuple = None
     hi: tuple = None
     bc: tuple = None  # per active axis: (low, high); default periodic
+    integrator: int = 0  # HEUN or VL2 (Sec. 3.3), used by run()
 
     def __post_init__(self):
         self.n = tuple(int(v) for v in self.n)
@@ -73,6 +78,7 @@ class Mesh:
             for s in range(2):
                 m.bc[d][s] = self.bc[d][s] if active else BC_PERIODIC
         m.gamma = self.gamma
+        m.integrator = self.integrator
         return m
 
 
@@ -98,6 +104,8 @@ def lib():
             "orc_fill_ghosts": (C.c_int, [mp, _dp]),
             "orc_rhs": (C.c_int, [mp, _dp, C.c_double, _dp]),
             "orc_heun_step": (C.c_int, [mp, _dp, C.c_double]),
+            "orc_rhs_prim": (C.c_int, [mp, _dp, C.c_double, C.c_int, _dp]),
+            "orc_vl2_step": (C.c_int, [mp, _dp, C.c_double]),
             "orc_run": (C.c_int, [mp, _dp, C.c_double, C.c_int, C.c_double, _dp,
                                   C.POINTER(C.c_int), _dp]),
             "orc_totals": (None, [mp, _dp, _dp]),
@@ -208,8 +216,23 @@ def heun_step(mesh, U, dt):
     return U
 
 
+def rhs_prim(mesh, W, dt, order):
+    """Stage right-hand side from a primitive state, order 1 (piecewise
+    constant) or 2 (PLM)."""
+    W = _field(mesh, W)
+    dU = np.empty_like(W)
+    _check(lib().orc_rhs_prim(C.byref(mesh.to_c()), _p(W), float(dt), int(order), _p(dU)), "rhs_prim")
+    return dU
+
+
+def vl2_step(mesh, U, dt):
+    U = _field(mesh, U).copy()
+    _check(lib().orc_vl2_step(C.byref(mesh.to_c()), _p(U), float(dt)), "vl2_step")
+    return U
+
+
 def run(mesh, U, cfl, max_steps=0, t_end=0.0, t0=0.0):
-    """Run CFL-limited Heun steps; returns (U, t, steps, dts)."""
+    """Run CFL-limited steps of the mesh's integrator; returns (U, t, steps, dts)."""
     U = _field(mesh, U).copy()
     t = C.c_double(t0)
     steps = C.c_int(0)

@@ -32,6 +32,7 @@ enum { VM_NONE = 0, VM_NEG = 1, VM_CLIP_LO = 2, VM_CLIP_HI = 3 };
 static int mesh_ok(const orc_mesh* m) {
     if (!m || m->ndim < 1 || m->ndim > 3) return 0;
     if (!(m->gamma > 1.0) || !isfinite(m->gamma)) return 0;
+    if (m->integrator != ORC_HEUN && m->integrator != ORC_VL2) return 0;
     for (int d = 0; d < 3; ++d) {
         if (d < m->ndim) {
             if (m->n[d] < 1 || !(m->hi[d] > m->lo[d])) return 0;
@@ -237,12 +238,18 @@ void orc_plm_face(const double w[4], double* wl, double* wr) {
 /* Flux through the face between w4[1] and w4[2] along axis d, from the
  * global-frame primitive states of the four cells around it: reconstruct each
  * component, rotate so the face normal is the first velocity, solve, rotate back. */
-static void face_flux(int ndim, double g, int d, const double (*w4)[MAXC], double* F) {
+static void face_flux(int ndim, double g, int d, int order, const double (*w4)[MAXC], double* F) {
     int nc = ndim + 2;
     double wl[MAXC], wr[MAXC];
     for (int c = 0; c < nc; ++c) {
-        double col[4] = {w4[0][c], w4[1][c], w4[2][c], w4[3][c]};
-        orc_plm_face(col, &wl[c], &wr[c]);
+        if (order == 1) {
+            /* piecewise-constant reconstruction: the face states are the cells' values */
+            wl[c] = w4[1][c];
+            wr[c] = w4[2][c];
+        } else {
+            double col[4] = {w4[0][c], w4[1][c], w4[2][c], w4[3][c]};
+            orc_plm_face(col, &wl[c], &wr[c]);
+        }
     }
     double WLn[MAXC], WRn[MAXC], Fn[MAXC];
     WLn[0] = wl[0];
@@ -355,6 +362,8 @@ int orc_fill_ghosts(const orc_mesh* m, double* Wpad) {
 
 /* ------------------------------------------------------------- stage rhs */
 
+static int rhs_padded(const orc_mesh* m, double* Wp, double dt, int order, double* dU);
+
 int orc_rhs(const orc_mesh* m, const double* U, double dt, double* dU) {
     if (!mesh_ok(m)) return -1;
     int ndim = m->ndim, nc = ndim + 2;
@@ -380,6 +389,46 @@ int orc_rhs(const orc_mesh* m, const double* U, double dt, double* dU) {
         free(Wp);
         return bad;
     }
+    int rc = rhs_padded(m, Wp, dt, 2, dU);
+    free(Wp);
+    return rc;
+}
+
+int orc_rhs_prim(const orc_mesh* m, const double* W, double dt, int order, double* dU) {
+    if (!mesh_ok(m) || (order != 1 && order != 2)) return -1;
+    int nc = m->ndim + 2;
+    int64_t N = ncells(m);
+    int n0 = m->n[0], n1 = m->n[1], n2 = m->n[2];
+    padgeo pg = pad_geometry(m);
+    double* Wp = (double*)calloc((size_t)(nc * pg.total), sizeof(double));
+    if (!Wp) return -1;
+    int bad = 0;
+    for (int k = 0; k < n2; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n0; ++i) {
+                int64_t cell = ((int64_t)k * n1 + j) * n0 + i;
+                double w[MAXC];
+                for (int c = 0; c < nc; ++c) w[c] = W[c * N + cell];
+                if (!(w[0] > 0.0) || !(w[nc - 1] > 0.0)) ++bad;
+                for (int c = 0; c < nc; ++c)
+                    if (!isfinite(w[c])) ++bad;
+                int64_t o = pidx(&pg, i, j, k);
+                for (int c = 0; c < nc; ++c) Wp[c * pg.total + o] = w[c];
+            }
+    int rc = bad ? bad : rhs_padded(m, Wp, dt, order, dU);
+    free(Wp);
+    return rc;
+}
+
+/* Stage right-hand side from the padded primitive array Wp (interior filled;
+ * the ghosts are filled here by the boundary rules), with piecewise-constant
+ * (order 1) or PLM (order 2) face states. */
+static int rhs_padded(const orc_mesh* m, double* Wp, double dt, int order, double* dU) {
+    int ndim = m->ndim, nc = ndim + 2;
+    double g = m->gamma;
+    int64_t N = ncells(m);
+    int n0 = m->n[0], n1 = m->n[1], n2 = m->n[2];
+    padgeo pg = pad_geometry(m);
     orc_fill_ghosts(m, Wp);
 
     /* face fluxes: axis d has n_d + 1 faces per line; face f separates cells f-1 and f */
@@ -391,7 +440,6 @@ int orc_rhs(const orc_mesh* m, const double* U, double dt, double* dU) {
         Fd[d] = (double*)malloc((size_t)(nc * nf) * sizeof(double));
         if (!Fd[d]) {
             for (int e = 0; e < d; ++e) free(Fd[e]);
-            free(Wp);
             return -1;
         }
 #pragma omp parallel for schedule(static)
@@ -407,7 +455,7 @@ int orc_rhs(const orc_mesh* m, const double* U, double dt, double* dU) {
                         for (int c = 0; c < nc; ++c) w4[s][c] = Wp[c * pg.total + o];
                     }
                     double F[MAXC];
-                    face_flux(ndim, g, d, w4, F);
+                    face_flux(ndim, g, d, order, w4, F);
                     int64_t fo = ((int64_t)fk * fext[d][1] + fj) * fext[d][0] + fi;
                     for (int c = 0; c < nc; ++c) Fd[d][c * (nf) + fo] = F[c];
                 }
@@ -437,7 +485,6 @@ int orc_rhs(const orc_mesh* m, const double* U, double dt, double* dU) {
                 }
             }
     for (int d = 0; d < ndim; ++d) free(Fd[d]);
-    free(Wp);
     return 0;
 }
 
@@ -465,6 +512,41 @@ int orc_heun_step(const orc_mesh* m, double* U, double dt) {
         for (int64_t q = 0; q < tot; ++q) U[q] = 0.5 * U[q] + 0.5 * (U1[q] + dU[q]);
     }
     free(U1);
+    free(dU);
+    return rc;
+}
+
+/* The memory-optimised van Leer integrator (Sec. 3.3): a half-step
+ * predictor with piecewise-constant states, U* = U^n + (dt/2) L_1(U^n),
+ * kept only as primitive variables W* = W(U*); then the full step from the
+ * PLM fluxes of W*, U^{n+1} = U^n + dt L_2(W*).  The predictor never enters
+ * U^{n+1} directly, so it may be stored at reduced precision. */
+int orc_vl2_step(const orc_mesh* m, double* U, double dt) {
+    if (!mesh_ok(m) || !(dt > 0.0) || !isfinite(dt)) return -1;
+    int ndim = m->ndim, nc = ndim + 2;
+    int64_t N = ncells(m), tot = nc * N;
+    double* W = (double*)malloc((size_t)tot * sizeof(double));
+    double* dU = (double*)malloc((size_t)tot * sizeof(double));
+    if (!W || !dU) {
+        free(W);
+        free(dU);
+        return -1;
+    }
+    int rc = orc_cons_to_prim(m, U, W);
+    if (rc == 0) rc = orc_rhs_prim(m, W, 0.5 * dt, 1, dU);
+    if (rc == 0) {
+        /* W* = W(U^n + dU), cell by cell */
+        for (int64_t i = 0; i < N && rc == 0; ++i) {
+            double u[MAXC], w[MAXC];
+            for (int c = 0; c < nc; ++c) u[c] = U[c * N + i] + dU[c * N + i];
+            if (!cons_to_prim_cell(ndim, m->gamma, u, w)) rc = 1;
+            for (int c = 0; c < nc; ++c) W[c * N + i] = w[c];
+        }
+    }
+    if (rc == 0) rc = orc_rhs_prim(m, W, dt, 2, dU);
+    if (rc == 0)
+        for (int64_t q = 0; q < tot; ++q) U[q] = U[q] + dU[q];
+    free(W);
     free(dU);
     return rc;
 }
@@ -506,7 +588,7 @@ int orc_run(const orc_mesh* m, double* U, double cfl, int max_steps, double t_en
             dt = t_end - *t;
             last = 1;
         }
-        rc = orc_heun_step(m, U, dt);
+        rc = m->integrator == ORC_VL2 ? orc_vl2_step(m, U, dt) : orc_heun_step(m, U, dt);
         if (rc) break;
         if (dts) dts[s] = dt;
         *t = last ? t_end : *t + dt;
@@ -588,8 +670,8 @@ static int cell_rhs(const field_src* f, int64_t cell, double* dU) {
             w5[s][1 + d] = apply_vmode(w5[s][1 + d], vmode);
         }
         double Fm[MAXC], Fp[MAXC];
-        face_flux(ndim, m->gamma, d, (const double(*)[MAXC])&w5[0], Fm);
-        face_flux(ndim, m->gamma, d, (const double(*)[MAXC])&w5[1], Fp);
+        face_flux(ndim, m->gamma, d, 2, (const double(*)[MAXC])&w5[0], Fm);
+        face_flux(ndim, m->gamma, d, 2, (const double(*)[MAXC])&w5[1], Fp);
         double lam = f->dt / cell_width(m, d);
         for (int c = 0; c < nc; ++c) acc[c] = acc[c] + lam * (Fm[c] - Fp[c]);
     }

@@ -36,6 +36,9 @@ extern "C" {
 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_FREE = 1, ORC_BC_OUTFLOW = 2, ORC_BC_REFLECT = 3 };
 
+/* Time integrators of Sec. 3.3: Heun (default) and the memory-optimised van Leer. */
+enum { ORC_HEUN = 0, ORC_VL2 = 1 };
+
 typedef struct {
     int32_t ndim;
     int32_t n[3];
@@ -43,6 +46,7 @@ typedef struct {
     double hi[3];
     double gamma;
     int32_t bc[3][2];
+    int32_t integrator; /* ORC_HEUN or ORC_VL2; used by orc_run */
 } orc_mesh;
 
 /* Number of conserved components, 2 + ndim; -1 for an invalid mesh. */
@@ -82,6 +86,15 @@ int orc_rhs(const orc_mesh* m, const double* U, double dt, double* dU);
 
 /* One Heun step in place (Sec. 3.3). */
 int orc_heun_step(const orc_mesh* m, double* U, double dt);
+
+/* Stage right-hand side, as orc_rhs, from an interior primitive state W with
+ * piecewise-constant (order 1) or PLM (order 2) face states. */
+int orc_rhs_prim(const orc_mesh* m, const double* W, double dt, int order, double* dU);
+
+/* One step of the memory-optimised van Leer integrator (Sec. 3.3):
+ * W* = W(U^n + (dt/2) L_1(U^n)) with piecewise-constant states, then
+ * U^{n+1} = U^n + dt L_2(W*) with PLM states, in place. */
+int orc_vl2_step(const orc_mesh* m, double* U, double dt);
 
 /*
  * Run with the CFL step: at most max_steps steps (max_steps <= 0 means no

@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 2-D workload")
+    ap.add_argument("--no-vl2", action="store_true", help="skip the van Leer integrator leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-count", type=int, default=2000)
@@ -70,13 +71,26 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": n * 8, "launches": 5}), flush=True)
 
 
-def bytes_per_update(ndim):
-    return 5 * (ndim + 2) * 8
+def stage_bytes(ndim, precision, integrator):
+    """Algorithmic bytes per cell of the stage-1 and stage-2 launches.
+    Heun: read U^n, write U1 (FP64); read U1 and U^n, write U^{n+1}.  van
+    Leer: read U^n, write the predicted primitive state (compute type); read
+    it and U^n, write U^{n+1}."""
+    nc = ndim + 2
+    if integrator == 0:
+        return 2 * nc * 8, 3 * nc * 8
+    r = 8 if precision == 0 else 4
+    return nc * (8 + r), nc * (r + 16)
 
 
-def run_precision(H, case, precision, steps, warmup, tile=None, tune=True):
+def bytes_per_update(ndim, precision=0, integrator=0):
+    return sum(stage_bytes(ndim, precision, integrator))
+
+
+def run_precision(H, case, precision, steps, warmup, tile=None, tune=True, integrator=0):
     import torch
-    h = H.Hydro(case.n, case.gamma, case.cfl, precision=precision, lo=case.lo, hi=case.hi, bc=case.bc)
+    h = H.Hydro(case.n, case.gamma, case.cfl, precision=precision, lo=case.lo, hi=case.hi, bc=case.bc,
+                integrator=integrator)
     h.set_primitive(case.W)
     if tile or not tune:
         if tile:
@@ -107,14 +121,15 @@ def run_precision(H, case, precision, steps, warmup, tile=None, tune=True):
     cells = case.ncells
     rate = cells * steps / (ms * 1e-3)
     nc = case.ndim + 2
-    alg_bytes = (2 * nc * 8 * n1 + 3 * nc * 8 * n2) * cells   # stage-1 and stage-2 launches
+    b1, b2 = stage_bytes(case.ndim, precision, integrator)
+    alg_bytes = (b1 * n1 + b2 * n2) * cells                  # stage-1 and stage-2 launches
     kern_ms = ms1 + ms2
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     return {
         "rate": rate, "ms_per_step": ms / steps, "wall_s": wall, "t_sim": t_sim,
         "stage_ms": [ms1 / max(n1, 1), ms2 / max(n2, 1)], "launches": [n1, n2],
         "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS, "totals": T.tolist(),
-        "step_frac": rate * bytes_per_update(case.ndim) / 1e9 / HBM_PEAK_GBS,
+        "step_frac": rate * bytes_per_update(case.ndim, precision, integrator) / 1e9 / HBM_PEAK_GBS,
         "tiles": [list(t) for t in tiles],
     }
 
@@ -300,6 +315,19 @@ def main():
     }
     if "mixed" in res and "fp64" in res:
         out["mixed_over_fp64"] = res["mixed"]["rate"] / res["fp64"]["rate"]
+    if not args.no_vl2:
+        # the memory-optimised van Leer integrator on the same workload
+        vl = {}
+        for name, prec in (("mixed", H.MIXED), ("fp64", H.FP64)):
+            if args.precision not in ("both", name):
+                continue
+            r = run_precision(H, case, prec, args.steps, args.warmup, None, not args.no_tune, integrator=1)
+            vl[name] = {"value": r["rate"], "ms_per_step": r["ms_per_step"], "stage_ms": r["stage_ms"],
+                        "achieved_gbs": r["achieved_gbs"], "roofline_frac": r["frac"],
+                        "alg_bytes_per_cell_update": bytes_per_update(case.ndim, prec, 1), "tiles": r["tiles"]}
+            print(f"[bench] vl2 {name}: {r['rate']:.3e} cell-updates/s, {r['ms_per_step']:.3f} ms/step, "
+                  f"stage kernels {r['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
+        out["vl2"] = vl
     if not args.no_batch:
         print("[bench] batched 2-D workload ...", file=sys.stderr, flush=True)
         out["batch"] = run_batch(H, wl, args.batch_count, 300, H.MIXED)

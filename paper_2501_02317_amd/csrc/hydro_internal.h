@@ -79,7 +79,9 @@ struct MeshDesc {
     int tiles_x, tiles_y, chunks_z, kz;
 };
 
-enum StageMode : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2 };
+// Stage kernels: the Heun stages (and the stage right-hand side), and the
+// van Leer predictor and corrector (Sec. 3.3).
+enum StageMode : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2, MODE_VL2_PRED = 3, MODE_VL2_CORR = 4 };
 
 hipError_t launch_stage(int precision, int mode, const Tile& tile, StageArgs a, hipStream_t s);
 // Fill the tiling fields of a descriptor for a tile.

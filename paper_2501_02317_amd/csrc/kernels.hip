@@ -185,10 +185,12 @@ __device__ __forceinline__ void hllc(const Gas<R>& gas, const R (&WL)[NT + 3], c
     R Uk[NC], Fk[NC];
     Uk[0] = rho;
     Uk[1] = mu;
+    // tangential |t|^2 as a sum of rounded squares: symmetric in the
+    // tangential components, so interchanging two axes is bitwise
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
         Uk[2 + k] = rho * W[2 + k];
-        tsq = O::fma(W[2 + k], W[2 + k], tsq);
+        tsq = tsq + W[2 + k] * W[2 + k];
     }
     const R vsq = O::fma(u, u, tsq);
     const R E = O::fma(p, gas.inv_gm1, R(0.5) * rho * vsq);
@@ -223,7 +225,8 @@ __device__ __forceinline__ void hllc(const Gas<R>& gas, const R (&WL)[NT + 3], c
 // global-frame primitive states of the four cells around it: PLM per
 // component, rotate the face normal to the first velocity slot, HLLC, rotate
 // back.  Tangential velocities keep increasing component order.
-template <int NDIM, int AX, typename R>
+// FIRST: piecewise-constant states (the face states are w1 and w2).
+template <int NDIM, int AX, typename R, bool FIRST = false>
 __device__ __forceinline__ void face_flux(const Gas<R>& g, const R (&w0)[NDIM + 2], const R (&w1)[NDIM + 2],
                                           const R (&w2)[NDIM + 2], const R (&w3)[NDIM + 2],
                                           R (&F)[NDIM + 2]) {
@@ -233,10 +236,15 @@ __device__ __forceinline__ void face_flux(const Gas<R>& g, const R (&w0)[NDIM + 
     R wl[NC], wr[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        const R dj = minmod(w1[c] - w0[c], w2[c] - w1[c]);
-        const R dj1 = minmod(w2[c] - w1[c], w3[c] - w2[c]);
-        wl[c] = Ops<R>::fma(R(0.5), dj, w1[c]);
-        wr[c] = Ops<R>::fma(R(-0.5), dj1, w2[c]);
+        if constexpr (FIRST) {
+            wl[c] = w1[c];
+            wr[c] = w2[c];
+        } else {
+            const R dj = minmod(w1[c] - w0[c], w2[c] - w1[c]);
+            const R dj1 = minmod(w2[c] - w1[c], w3[c] - w2[c]);
+            wl[c] = Ops<R>::fma(R(0.5), dj, w1[c]);
+            wr[c] = Ops<R>::fma(R(-0.5), dj1, w2[c]);
+        }
     }
     R L[NT + 3], Rs[NT + 3], Fn[NT + 3];
     L[0] = wl[0];
@@ -272,16 +280,21 @@ __device__ __forceinline__ void face_flux(const Gas<R>& g, const R (&w0)[NDIM + 
 // Flux through an in-plane face of a 3-D tile whose axis (0: x, 1: y) is a
 // run-time value: the same arithmetic as face_flux<3, 0 or 1>, with the
 // rotation done by selects so faces of both axes share one code path.
-template <typename R>
+template <typename R, bool FIRST = false>
 __device__ __forceinline__ void face_flux_xy(const Gas<R>& g, bool yaxis, const R (&w0)[5], const R (&w1)[5],
                                              const R (&w2)[5], const R (&w3)[5], R (&F)[5]) {
     R wl[5], wr[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-        const R dj = minmod(w1[c] - w0[c], w2[c] - w1[c]);
-        const R dj1 = minmod(w2[c] - w1[c], w3[c] - w2[c]);
-        wl[c] = Ops<R>::fma(R(0.5), dj, w1[c]);
-        wr[c] = Ops<R>::fma(R(-0.5), dj1, w2[c]);
+        if constexpr (FIRST) {
+            wl[c] = w1[c];
+            wr[c] = w2[c];
+        } else {
+            const R dj = minmod(w1[c] - w0[c], w2[c] - w1[c]);
+            const R dj1 = minmod(w2[c] - w1[c], w3[c] - w2[c]);
+            wl[c] = Ops<R>::fma(R(0.5), dj, w1[c]);
+            wr[c] = Ops<R>::fma(R(-0.5), dj1, w2[c]);
+        }
     }
     // normal velocity first, then the other in-plane one, then z
     R L[5] = {wl[0], yaxis ? wl[2] : wl[1], yaxis ? wl[1] : wl[2], wl[3], wl[4]};
@@ -495,6 +508,31 @@ __device__ __forceinline__ void to_prim(double gm1, const double (&u)[NDIM + 2],
     for (int c = 0; c < NC; ++c) W[c] = (R)w[c];
 }
 
+// The stencil input of a cell as primitive variables in R: conserved FP64
+// values converted (to_prim), or, with PRIM, stored primitive values of type
+// R (the van Leer predictor state) held as doubles, with the boundary
+// treatment of the normal velocity applied.
+template <int NDIM, typename R, bool PRIM, bool CHECK = true>
+__device__ __forceinline__ void in_to_w(double gm1, const double (&u)[NDIM + 2], int vax, int vm,
+                                        R (&W)[NDIM + 2], bool& bad) {
+    constexpr int NC = NDIM + 2;
+    if constexpr (PRIM) {
+        const int vc = vax == 0 ? 1 : (vax == 1 ? 2 : NDIM);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) W[c] = (R)((vax >= 0 && c == vc) ? apply_vmode(u[c], vm) : u[c]);
+    } else {
+        to_prim<NDIM, R, CHECK>(gm1, u, vax, vm, W, bad);
+    }
+}
+
+// NC values of one cell from a field of type T (layout [comp][cell]) as doubles.
+template <int NC, typename T>
+__device__ __forceinline__ void load_as_double(const T* __restrict__ F, long long N, long long cell,
+                                               double (&u)[NC]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) u[c] = (double)F[c * N + cell];
+}
+
 // One stage over a TX x TY tile column and a chunk of kz planes.
 //
 // Software pipeline per plane k (kernel z): raw U of the interior plane k+3
@@ -544,6 +582,17 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
     constexpr bool HY = (NDIM == 3);
     constexpr bool HZ = (NDIM >= 2);
     constexpr int NT = TX * TY;
+    // van Leer modes: the predictor (piecewise-constant states, half step,
+    // writes the predicted primitive state of type R into a.out) and the
+    // corrector (reads that state as its stencil input, PLM, full step from
+    // U^n in a.base, writes U^{n+1} to a.out)
+    constexpr bool PRED = MODE == MODE_VL2_PRED;
+    constexpr bool CORR = MODE == MODE_VL2_CORR;
+    constexpr bool FIRST = PRED;
+    constexpr bool PRIM_IN = CORR;
+    constexpr bool NEED_UIN = MODE == MODE_STAGE1 || MODE == MODE_STAGE2 || PRED;
+    constexpr bool NEED_BASE = MODE == MODE_STAGE2 || CORR;
+    constexpr bool EPILOGUE = MODE == MODE_STAGE2 || CORR;
     static_assert(HY || TY == 1, "tile rows need a second in-plane axis");
     static_assert(4 * TX + (HY ? 4 * TY : 0) <= NT || !HY, "one halo cell per thread");
     static_assert(HY || TX >= 4, "one halo cell per thread");
@@ -598,7 +647,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
         }
     }
 
-    const double dt = a.use_device_dt ? device_dt(a.ctrl) : a.dt_host;
+    const double dt_step = a.use_device_dt ? device_dt(a.ctrl) : a.dt_host;
+    const double dt = PRED ? 0.5 * dt_step : dt_step;  // the predictor advances half a step
     const double lam0 = dt / g.dx[0];
     const double lam1 = dt / g.dx[1];
     const double lam2 = dt / g.dx[2];
@@ -630,11 +680,17 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
     int vmA = VM_NONE, vmB = VM_NONE;
 
     // interior plane z (any z: outside the mesh it is a ghost plane)
+    auto load_in = [&](long long cell, double (&u)[NC]) {
+        if constexpr (PRIM_IN)
+            load_as_double<NC>(reinterpret_cast<const R*>(a.in), N, cell, u);
+        else
+            load_u<NC>(a.in, N, cell, u);
+    };
     auto load_interior = [&](int z, double (&u)[NC], int& vm) {
         vm = VM_NONE;
         int zr = z;
         if (z < 0 || z >= n2) zr = resolve(g, 2, z, vm);
-        load_u<NC>(a.in, N, (long long)zr * P + col, u);
+        load_in((long long)zr * P + col, u);
     };
 
     if (HZ && act) {
@@ -644,7 +700,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
             int vm;
             double u[NC];
             load_interior(z0 - 2 + s, u, vm);
-            to_prim<NDIM, R>(gm1, u, vm == VM_NONE ? -1 : 2, vm, w[s], bad);
+            in_to_w<NDIM, R, PRIM_IN>(gm1, u, vm == VM_NONE ? -1 : 2, vm, w[s], bad);
             if (RING && s >= 2) {
 #pragma unroll
                 for (int c = 0; c < NC; ++c) sRaw[RING ? (z0 - 2 + s) % RS : 0][RING ? c : 0][RING ? tid : 0] = u[c];
@@ -657,8 +713,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
         for (int c = 0; c < NC; ++c) {
             const R d0 = w[1][c] - w[0][c], d1 = w[2][c] - w[1][c], d2 = w[3][c] - w[2][c];
             const R s1 = minmod(d0, d1), s2 = minmod(d1, d2);
-            wl[c] = Ops<R>::fma(R(0.5), s1, w[1][c]);
-            wr[c] = Ops<R>::fma(R(-0.5), s2, w[2][c]);
+            wl[c] = FIRST ? w[1][c] : Ops<R>::fma(R(0.5), s1, w[1][c]);
+            wr[c] = FIRST ? w[2][c] : Ops<R>::fma(R(-0.5), s2, w[2][c]);
             lz[c] = Ops<R>::fma(R(0.5), s2, w[2][c]);
             wk[c] = w[2][c];
             wk1[c] = w[3][c];
@@ -688,7 +744,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
             if (HZ) {
                 // W_{k+2} arrived: z face k+1/2 from (W_k, W_{k+1}, W_{k+2})
                 R w2[NC], wr[NC];
-                to_prim<NDIM, R>(gm1, ui, vmi == VM_NONE ? -1 : 2, vmi, w2, bad);
+                in_to_w<NDIM, R, PRIM_IN>(gm1, ui, vmi == VM_NONE ? -1 : 2, vmi, w2, bad);
                 // plane k+2 is an interior plane whenever its update comes
                 if (RING) {
 #pragma unroll
@@ -697,30 +753,43 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                 // plane k+3 is W_{k'+2} of the next iteration k' = k+1; it lies at
                 // most two planes outside the mesh only while that iteration exists
                 if (k + 1 < z1) load_interior(k + 3, un, vmn);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const R d2 = w2[c] - wk1[c];
-                    const R s1 = minmod(dk[c], d2);
-                    wr[c] = Ops<R>::fma(R(-0.5), s1, wk1[c]);
-                    const R lnext = Ops<R>::fma(R(0.5), s1, wk1[c]);
-                    wc[c] = wk[c];
-                    dk[c] = d2;
-                    wk[c] = wk1[c];
-                    wk1[c] = w2[c];
-                    w2[c] = lnext;  // reuse: left state of face k+3/2
-                }
-                {
+                if constexpr (FIRST) {
+                    // face k+1/2 from the cells' values W_k and W_{k+1}
                     R f[NC];
-                    face_flux_states<NDIM, 2, R>(gr, lz, wr, f);
+                    face_flux_states<NDIM, 2, R>(gr, wk, wk1, f);
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) fzc[c] = (FT)f[c];
+                    for (int c = 0; c < NC; ++c) {
+                        fzc[c] = (FT)f[c];
+                        wc[c] = wk[c];
+                        wk[c] = wk1[c];
+                        wk1[c] = w2[c];
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        const R d2 = w2[c] - wk1[c];
+                        const R s1 = minmod(dk[c], d2);
+                        wr[c] = Ops<R>::fma(R(-0.5), s1, wk1[c]);
+                        const R lnext = Ops<R>::fma(R(0.5), s1, wk1[c]);
+                        wc[c] = wk[c];
+                        dk[c] = d2;
+                        wk[c] = wk1[c];
+                        wk1[c] = w2[c];
+                        w2[c] = lnext;  // reuse: left state of face k+3/2
+                    }
+                    {
+                        R f[NC];
+                        face_flux_states<NDIM, 2, R>(gr, lz, wr, f);
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) fzc[c] = (FT)f[c];
+                    }
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) lz[c] = w2[c];
                 }
-#pragma unroll
-                for (int c = 0; c < NC; ++c) lz[c] = w2[c];
             } else {
                 double u[NC];
-                load_u<NC>(a.in, N, (long long)k * P + col, u);
-                to_prim<NDIM, R>(gm1, u, -1, VM_NONE, wc, bad);
+                load_in((long long)k * P + col, u);
+                in_to_w<NDIM, R, PRIM_IN>(gm1, u, -1, VM_NONE, wc, bad);
             }
 #pragma unroll
             for (int c = 0; c < NC; ++c) sW[bw][c][ly + 2][lx + 2] = wc[c];
@@ -728,9 +797,9 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
         if (live && hact) {
             double uh[NC];
             R wh[NC];
-            load_u<NC>(a.in, N, (long long)k * P + hcol, uh);
+            load_in((long long)k * P + hcol, uh);
             // not checked here: every cell is checked by the tile that owns it
-            to_prim<NDIM, R, false>(gm1, uh, hvax, hvm, wh, bad);
+            in_to_w<NDIM, R, PRIM_IN, false>(gm1, uh, hvax, hvm, wh, bad);
 #pragma unroll
             for (int c = 0; c < NC; ++c) sW[bw][c][hy + 2][hx + 2] = wh[c];
         }
@@ -747,7 +816,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                     w2[c] = sW[bw][c][ly + 2][lx + 2];
                     w3[c] = sW[bw][c][ly + 2][lx + 3];
                 }
-                face_flux<NDIM, 0, R>(gr, w0, w1, w2, w3, F);
+                face_flux<NDIM, 0, R, FIRST>(gr, w0, w1, w2, w3, F);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) sFx[bw][c][ly][lx] = (FT)F[c];
             }
@@ -760,7 +829,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                     w2[c] = sW[bw][c][ly + 2][lx + 2];
                     w3[c] = sW[bw][c][ly + 3][lx + 2];
                 }
-                face_flux<NDIM, 1, R>(gr, w0, w1, w2, w3, F);
+                face_flux<NDIM, 1, R, FIRST>(gr, w0, w1, w2, w3, F);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) sFy[bw][HY ? c : 0][HY ? ly : 0][lx] = (FT)F[c];
             }
@@ -782,7 +851,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                         w2[c] = sW[bw][c][r0 + 2 * dr][c0 + 2 * dc];
                         w3[c] = sW[bw][c][r0 + 3 * dr][c0 + 3 * dc];
                     }
-                    face_flux_xy<R>(gr, yaxis, w0, w1, w2, w3, F);
+                    face_flux_xy<R, FIRST>(gr, yaxis, w0, w1, w2, w3, F);
                     if (yaxis) {
 #pragma unroll
                         for (int c = 0; c < NC; ++c) sFy[bw][c][TY][e - ex] = (FT)F[c];
@@ -798,7 +867,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                         w2[c] = sW[bw][c][e + 2][TX + 2];
                         w3[c] = sW[bw][c][e + 2][TX + 3];
                     }
-                    face_flux<NDIM, 0, R>(gr, w0, w1, w2, w3, F);
+                    face_flux<NDIM, 0, R, FIRST>(gr, w0, w1, w2, w3, F);
 #pragma unroll
                     for (int c = 0; c < NC; ++c) sFx[bw][c][e][TX] = (FT)F[c];
                 }
@@ -815,10 +884,10 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
             if (RING) {
 #pragma unroll
                 for (int c = 0; c < NC; ++c) uin[c] = sRaw[RING ? ku % RS : 0][RING ? c : 0][RING ? tid : 0];
-            } else if (MODE != MODE_RHS) {
+            } else if (NEED_UIN) {
                 load_u<NC>(a.in, N, cell, uin);
             }
-            if (MODE == MODE_STAGE2) load_u<NC>(a.base, N, cell, ubase);
+            if (NEED_BASE) load_u<NC>(a.base, N, cell, ubase);
             double unew[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
@@ -831,14 +900,24 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                 double r;
                 if (MODE == MODE_RHS)
                     r = acc;
-                else if (MODE == MODE_STAGE1)
+                else if (MODE == MODE_STAGE1 || PRED)
                     r = uin[c] + acc;
+                else if (CORR)
+                    r = ubase[c] + acc;
                 else
                     r = 0.5 * ubase[c] + 0.5 * (uin[c] + acc);
-                a.out[c * N + cell] = r;
+                if (!PRED) a.out[c * N + cell] = r;
                 unew[c] = r;
             }
-            if (MODE == MODE_STAGE2 && a.want_dt) {
+            if (PRED) {
+                // the predicted state is kept only as primitive variables of type R
+                double w[NC];
+                bad |= !cons_to_prim<NDIM>(gm1, unew, w);
+                R* wout = reinterpret_cast<R*>(a.out);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) wout[c * N + cell] = (R)w[c];
+            }
+            if (EPILOGUE && a.want_dt) {
                 double w[NC];
                 bad |= !cons_to_prim<NDIM>(gm1, unew, w);
                 const double cr = cfl_rate<NDIM>(g, w);
@@ -865,7 +944,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
     }
 
     if (bad) atomicOr(&a.ctrl->flags, FLAG_NONPHYSICAL);
-    if (MODE == MODE_STAGE2 && a.want_dt) {
+    if (EPILOGUE && a.want_dt) {
         __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
         rate = wave_max(rate);
         if ((tid & 63) == 0) red[tid >> 6] = rate;
@@ -905,10 +984,10 @@ void stage_kernel_batch(
     a.tiles_y = d.tiles_y;
     a.chunks_z = d.chunks_z;
     a.kz = d.kz;
-    if (MODE == MODE_STAGE1) {
+    if (MODE == MODE_STAGE1 || MODE == MODE_VL2_PRED) {
         a.in = d.U;
         a.base = d.U;
-        a.out = d.U1;
+        a.out = d.U1;  // van Leer: the predicted primitive state, type R
         a.want_dt = 0;
     } else {
         a.in = d.U1;
@@ -1089,8 +1168,8 @@ __global__ __launch_bounds__(256) void totals_pass2(int nparts, const double* __
 
 // m_d = rho v_d, E = p/(gamma - 1) + (1/2) sum_d m_d v_d
 template <int NDIM>
-__global__ __launch_bounds__(256) void prim_to_cons_kernel(Geo g, const double* __restrict__ W,
-                                                           double* __restrict__ U) {
+// W and U may be the same array (each cell is read before it is written).
+__global__ __launch_bounds__(256) void prim_to_cons_kernel(Geo g, const double* W, double* U) {
     constexpr int NC = NDIM + 2;
     for (long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x; cell < g.ncells;
          cell += (long long)gridDim.x * blockDim.x) {
@@ -1243,6 +1322,8 @@ hipError_t launch_stage_mode(int mode, const Tile& t, const LaunchCtx& L, hipStr
             return launch_stage_tile<NDIM, R, MODE_RHS>(t, L, s);
         case MODE_STAGE1: return launch_stage_tile<NDIM, R, MODE_STAGE1>(t, L, s);
         case MODE_STAGE2: return launch_stage_tile<NDIM, R, MODE_STAGE2>(t, L, s);
+        case MODE_VL2_PRED: return launch_stage_tile<NDIM, R, MODE_VL2_PRED>(t, L, s);
+        case MODE_VL2_CORR: return launch_stage_tile<NDIM, R, MODE_VL2_CORR>(t, L, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1271,7 +1352,7 @@ Tile default_tile(const Geo& g, int precision, int mode) {
         // 32 x 16 halves the share of halo cells and extra faces; the mixed
         // stage 2 keeps 32 x 8, where its input ring still leaves three
         // work-groups per CU
-        const bool narrow = precision == 1 && mode == MODE_STAGE2;
+        const bool narrow = precision == 1 && mode == MODE_STAGE2;  // the Heun stage 2 only
         t.tx = 32;
         t.ty = narrow ? 8 : 16;
     } else if (g.ndim == 2) {
@@ -1344,7 +1425,7 @@ hipError_t launch_stage(int precision, int mode, const Tile& t, StageArgs a, hip
 
 hipError_t launch_stage_batch(int ndim, int precision, int mode, const Tile& tile, const MeshDesc* d,
                               const int2* blk, int nblk, hipStream_t s) {
-    if (mode != MODE_STAGE1 && mode != MODE_STAGE2) return hipErrorInvalidValue;
+    if (mode == MODE_RHS) return hipErrorInvalidValue;
     LaunchCtx L{nullptr, d, blk, nblk};
     return launch_any(ndim, precision, mode, tile, L, s);
 }

@@ -46,6 +46,7 @@ bool config_ok(const hydro_config* c) {
     if (!(c->gamma > 1.0) || !std::isfinite(c->gamma)) return false;
     if (!(c->cfl > 0.0) || !(c->cfl <= 1.0)) return false;
     if (c->precision != HYDRO_FP64 && c->precision != HYDRO_MIXED) return false;
+    if (c->integrator != HYDRO_HEUN && c->integrator != HYDRO_VL2) return false;
     long long cells = 1;
     for (int d = 0; d < 3; ++d) {
         if (d < c->ndim) {
@@ -73,6 +74,17 @@ long long ncells_of(const hydro_config* c) { return (long long)c->n[0] * c->n[1]
 size_t state_bytes(const hydro_config* c) {
     return align_up((size_t)(c->ndim + 2) * (size_t)ncells_of(c) * sizeof(double));
 }
+
+// The second field: the Heun predictor U1 (FP64), or the van Leer predicted
+// primitive state in the compute precision.
+size_t second_bytes(const hydro_config* c) {
+    if (c->integrator == HYDRO_HEUN) return state_bytes(c);
+    const size_t r = c->precision == HYDRO_FP64 ? sizeof(double) : sizeof(float);
+    return align_up((size_t)(c->ndim + 2) * (size_t)ncells_of(c) * r);
+}
+
+int stage1_mode(const hydro_config* c) { return c->integrator == HYDRO_VL2 ? MODE_VL2_PRED : MODE_STAGE1; }
+int stage2_mode(const hydro_config* c) { return c->integrator == HYDRO_VL2 ? MODE_VL2_CORR : MODE_STAGE2; }
 
 // Kernel-axis geometry (see hydro_internal.h).
 Geo make_geo(const hydro_config* c) {
@@ -139,7 +151,7 @@ StageArgs stage_args(hydro_t h) {
 
 // Launch one stage, bracketed by events when profiling is on.
 hipError_t timed_stage(hydro_t h, int mode, const StageArgs& a) {
-    const int st = mode == MODE_STAGE2 ? 1 : 0;
+    const int st = (mode == MODE_STAGE2 || mode == MODE_VL2_CORR) ? 1 : 0;
     const bool rec = h->prof_cap > 0 && h->prof_n[st] < h->prof_cap;
     hipError_t e = hipSuccess;
     if (rec) e = hipEventRecord(h->prof_ev[st][2 * h->prof_n[st]], h->stream);
@@ -151,21 +163,23 @@ hipError_t timed_stage(hydro_t h, int mode, const StageArgs& a) {
     return e;
 }
 
-// One Heun step: stage 1 then stage 2 in place, dt either from the host or
+// One step: stage 1 (Heun: U1 = U^n + dt L(U^n); van Leer: the predicted
+// primitive state) then stage 2 in place over U^n, dt either from the host or
 // from the device control block (clamped to the run limit kept there).
 hipError_t enqueue_step(hydro_t h, bool device_dt, double dt) {
     StageArgs a = stage_args(h);
     a.use_device_dt = device_dt ? 1 : 0;
     a.dt_host = dt;
     a.in = h->U;
+    a.base = h->U;
     a.out = h->U1;
-    hipError_t e = timed_stage(h, MODE_STAGE1, a);
+    hipError_t e = timed_stage(h, stage1_mode(&h->cfg), a);
     if (e != hipSuccess) return e;
     a.in = h->U1;
     a.base = h->U;
     a.out = h->U;
     a.want_dt = device_dt ? 1 : 0;
-    e = timed_stage(h, MODE_STAGE2, a);
+    e = timed_stage(h, stage2_mode(&h->cfg), a);
     if (e != hipSuccess) return e;
     if (device_dt) return launch_ctrl(h->ctrl, CTRL_FINALIZE_STEP, 0.0, 0.0, h->cfg.cfl, h->stream);
     return launch_ctrl(h->ctrl, CTRL_ADVANCE_T, dt, 0.0, h->cfg.cfl, h->stream);
@@ -185,7 +199,7 @@ extern "C" {
 
 size_t hydro_workspace_bytes(const hydro_config* cfg) {
     if (!config_ok(cfg)) return 0;
-    return 2 * state_bytes(cfg) + align_up(sizeof(Ctrl)) +
+    return state_bytes(cfg) + second_bytes(cfg) + align_up(sizeof(Ctrl)) +
            align_up((size_t)kTotalsParts * kMaxComp * 2 * sizeof(double));
 }
 
@@ -199,18 +213,18 @@ int hydro_create(const hydro_config* cfg, void* d_workspace, size_t nbytes, void
     std::memset(h, 0, sizeof(*h));
     h->cfg = *cfg;
     h->geo = make_geo(cfg);
-    h->tile[0] = default_tile(h->geo, cfg->precision, MODE_STAGE1);
-    h->tile[1] = default_tile(h->geo, cfg->precision, MODE_STAGE2);
+    h->tile[0] = default_tile(h->geo, cfg->precision, stage1_mode(cfg));
+    h->tile[1] = default_tile(h->geo, cfg->precision, stage2_mode(cfg));
     h->stream = (hipStream_t)hip_stream;
     h->ncomp = cfg->ndim + 2;
     h->dV = 1.0;
     for (int d = 0; d < cfg->ndim; ++d) h->dV *= (cfg->hi[d] - cfg->lo[d]) / cfg->n[d];
     char* p = (char*)d_workspace;
-    const size_t sb = state_bytes(cfg);
+    const size_t sb = state_bytes(cfg), sb2 = second_bytes(cfg);
     h->U = (double*)p;
     p += sb;
-    h->U1 = (double*)p;
-    p += sb;
+    h->U1 = (double*)p;  // van Leer: holds values of the compute type
+    p += sb2;
     h->ctrl = (Ctrl*)p;
     p += align_up(sizeof(Ctrl));
     h->parts = (double*)p;
@@ -218,7 +232,7 @@ int hydro_create(const hydro_config* cfg, void* d_workspace, size_t nbytes, void
         delete h;
         return HYDRO_E_NOMEM;
     }
-    hipError_t e = hipMemsetAsync(h->U, 0, 2 * sb, h->stream);
+    hipError_t e = hipMemsetAsync(h->U, 0, sb + sb2, h->stream);
     if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_INIT, 0.0, 0.0, cfg->cfl, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
@@ -247,8 +261,9 @@ int hydro_set_primitive(hydro_t h, const double* W_host) {
     if (rc) return rc;
     if (!W_host) return HYDRO_E_INVAL;
     const size_t bytes = (size_t)h->ncomp * h->geo.ncells * sizeof(double);
-    hipError_t e = hipMemcpyAsync(h->U1, W_host, bytes, hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess) e = launch_prim_to_cons(h->geo, h->U1, h->U, h->stream);
+    // staged in U itself and converted in place
+    hipError_t e = hipMemcpyAsync(h->U, W_host, bytes, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = launch_prim_to_cons(h->geo, h->U, h->U, h->stream);
     if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_INIT, 0.0, 0.0, h->cfg.cfl, h->stream);
     h->dt_valid = false;
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -382,10 +397,19 @@ int hydro_stage_rhs(hydro_t h, double dt, double* dU_host) {
     StageArgs a = stage_args(h);
     a.dt_host = dt;
     a.in = h->U;
-    a.out = h->U1;
-    hipError_t e = launch_stage(h->cfg.precision, MODE_RHS, h->tile[0], a, h->stream);
     const size_t bytes = (size_t)h->ncomp * h->geo.ncells * sizeof(double);
-    if (e == hipSuccess) e = hipMemcpyAsync(dU_host, h->U1, bytes, hipMemcpyDeviceToHost, h->stream);
+    // the Heun predictor buffer holds FP64 values of this size; the van Leer
+    // one may not, so a temporary buffer takes the result then
+    double* d_buf = h->U1;
+    hipError_t e = hipSuccess;
+    if (h->cfg.integrator != HYDRO_HEUN) e = hipMallocAsync((void**)&d_buf, bytes, h->stream);
+    a.out = d_buf;
+    if (e == hipSuccess) e = launch_stage(h->cfg.precision, MODE_RHS, h->tile[0], a, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dU_host, d_buf, bytes, hipMemcpyDeviceToHost, h->stream);
+    if (h->cfg.integrator != HYDRO_HEUN && d_buf && d_buf != h->U1) {
+        hipError_t e2 = hipFreeAsync(d_buf, h->stream);
+        if (e == hipSuccess) e = e2;
+    }
     if (e != hipSuccess) return fail(h, e);
     return read_ctrl(h);
 }
@@ -467,13 +491,13 @@ int hydro_autotune(hydro_t h, int steps_per_tile, double t_end, int* tiles, doub
             a.in = h->U;
             a.out = h->U1;
             e = hipEventRecord(q[0], h->stream);
-            if (e == hipSuccess) e = launch_stage(h->cfg.precision, MODE_STAGE1, cand[c], a, h->stream);
+            if (e == hipSuccess) e = launch_stage(h->cfg.precision, stage1_mode(&h->cfg), cand[c], a, h->stream);
             if (e == hipSuccess) e = hipEventRecord(q[1], h->stream);
             a.in = h->U1;
             a.base = h->U;
             a.out = h->U;
             a.want_dt = 1;
-            if (e == hipSuccess) e = launch_stage(h->cfg.precision, MODE_STAGE2, cand[c], a, h->stream);
+            if (e == hipSuccess) e = launch_stage(h->cfg.precision, stage2_mode(&h->cfg), cand[c], a, h->stream);
             if (e == hipSuccess) e = hipEventRecord(q[2], h->stream);
             if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_FINALIZE_STEP, 0.0, 0.0, h->cfg.cfl, h->stream);
         }
@@ -633,7 +657,7 @@ struct hydro_batch_ctx {
     MeshDesc* d_desc;  // descriptor table in the caller's workspace
     int2* d_blk;       // work-group table, grouped
     struct Group {
-        int ndim, precision;
+        int ndim, precision, integrator;
         Tile tile;
         int blk_off, nblk;
     };
@@ -693,7 +717,7 @@ bool plan_batch(int n, const hydro_t* members, BatchPlan& P, int rule = 0) {
     }
     auto key = [&](int i) {
         const hydro_t h = members[i];
-        return std::make_tuple(h->cfg.ndim, h->cfg.precision, tiles[i].tx, tiles[i].ty);
+        return std::make_tuple(h->cfg.ndim, h->cfg.precision, h->cfg.integrator, tiles[i].tx, tiles[i].ty);
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
     for (int idx = 0; idx < n; ++idx) {
@@ -703,6 +727,7 @@ bool plan_batch(int n, const hydro_t* members, BatchPlan& P, int rule = 0) {
             hydro_batch_ctx::Group g;
             g.ndim = h->cfg.ndim;
             g.precision = h->cfg.precision;
+            g.integrator = h->cfg.integrator;
             g.tile = tiles[i];
             g.blk_off = (int)P.blk.size();
             g.nblk = 0;
@@ -738,12 +763,12 @@ hipError_t enqueue_batch_step(hydro_batch_t b) {
     hipError_t e = hipSuccess;
     for (const auto& g : b->groups)
         if (e == hipSuccess)
-            e = launch_stage_batch(g.ndim, g.precision, MODE_STAGE1, g.tile, b->d_desc, b->d_blk + g.blk_off,
-                                   g.nblk, b->stream);
+            e = launch_stage_batch(g.ndim, g.precision, g.integrator == HYDRO_VL2 ? MODE_VL2_PRED : MODE_STAGE1,
+                                   g.tile, b->d_desc, b->d_blk + g.blk_off, g.nblk, b->stream);
     for (const auto& g : b->groups)
         if (e == hipSuccess)
-            e = launch_stage_batch(g.ndim, g.precision, MODE_STAGE2, g.tile, b->d_desc, b->d_blk + g.blk_off,
-                                   g.nblk, b->stream);
+            e = launch_stage_batch(g.ndim, g.precision, g.integrator == HYDRO_VL2 ? MODE_VL2_CORR : MODE_STAGE2,
+                                   g.tile, b->d_desc, b->d_blk + g.blk_off, g.nblk, b->stream);
     if (e == hipSuccess) e = launch_ctrl_batch(b->d_desc, (int)b->members.size(), b->stream);
     return e;
 }

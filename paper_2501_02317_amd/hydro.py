@@ -10,6 +10,9 @@ import ctypes as C
 import os
 
 import numpy as np
+# PyTorch first: its HIP runtime is then the one the library binds to, so
+# device memory from torch and the library's own HIP calls share a runtime.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhydro.so")
@@ -22,10 +25,13 @@ BC_PERIODIC, BC_FREE, BC_OUTFLOW, BC_REFLECT = 0, 1, 2, 3
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONPHYSICAL, E_STATE = 0, -1, -2, -3, -4, -5
 
 
+HEUN, VL2 = 0, 1
+
+
 class Config(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 3), ("lo", C.c_double * 3),
                 ("hi", C.c_double * 3), ("gamma", C.c_double), ("cfl", C.c_double),
-                ("precision", C.c_int32), ("bc", (C.c_int32 * 2) * 3)]
+                ("precision", C.c_int32), ("bc", (C.c_int32 * 2) * 3), ("integrator", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -91,7 +97,7 @@ def strerror(status):
     return _lib.hydro_strerror(int(status)).decode()
 
 
-def make_config(n, gamma, cfl, precision=FP64, lo=None, hi=None, bc=None):
+def make_config(n, gamma, cfl, precision=FP64, lo=None, hi=None, bc=None, integrator=HEUN):
     """Config for the active axes' cell counts n (x first)."""
     nd = len(n)
     cfg = Config()
@@ -109,6 +115,7 @@ def make_config(n, gamma, cfl, precision=FP64, lo=None, hi=None, bc=None):
     cfg.gamma = float(gamma)
     cfg.cfl = float(cfl)
     cfg.precision = int(precision)
+    cfg.integrator = int(integrator)
     return cfg
 
 
@@ -127,10 +134,11 @@ class Hydro:
     """
 
     def __init__(self, n, gamma, cfl, precision=FP64, lo=None, hi=None, bc=None, device=None,
-                 stream=None, workspace=None):
+                 stream=None, workspace=None, integrator=HEUN):
         import torch
 
-        self.cfg = make_config(n, gamma, cfl, precision, lo, hi, bc)
+        self.cfg = make_config(n, gamma, cfl, precision, lo, hi, bc, integrator)
+        self.integrator = int(integrator)
         self.ndim = len(n)
         self.n = tuple(int(v) for v in n)
         self.precision = int(precision)

@@ -13,14 +13,14 @@ def say(*a):
     sys.stdout.flush()
 
 
-def oracle_mesh(case):
-    return O.Mesh(case.n, case.gamma, case.lo, case.hi, case.bc)
+def oracle_mesh(case, integrator=0):
+    return O.Mesh(case.n, case.gamma, case.lo, case.hi, case.bc, integrator=integrator)
 
 
-def gpu_mesh(case, precision):
+def gpu_mesh(case, precision, integrator=0):
     from paper_2501_02317_amd import hydro as H
     h = H.Hydro(case.n, case.gamma, case.cfl, precision=precision, lo=case.lo, hi=case.hi,
-                bc=case.bc)
+                bc=case.bc, integrator=integrator)
     h.set_primitive(case.W)
     return h
 

@@ -358,6 +358,28 @@ def test_mirror_and_transpose_bitwise_on_gpu(H, precision):
     h1.close(), h2.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_transpose_bitwise_3d(H, precision):
+    """x <-> y interchange in 3-D, on a mesh whose tiles are partial in
+    both in-plane axes."""
+    c = wl.turbulence_3d(n=(24, 24, 20), mach=1.0, seed=8, steps=6)
+    WT = np.swapaxes(c.W, 2, 3).copy()
+    WT[[1, 2]] = WT[[2, 1]]
+    say("transpose 3-D", precision)
+    h = gpu_mesh(c, precision)
+    h.step_auto(6)
+    U = h.get_state()
+    h.close()
+    c.W = WT
+    h = gpu_mesh(c, precision)
+    h.step_auto(6)
+    UT = h.get_state()
+    h.close()
+    back = np.swapaxes(UT, 2, 3).copy()
+    back[[1, 2]] = back[[2, 1]]
+    assert bitwise_equal(back, U)
+
+
 def test_deterministic_and_restart_bitwise(H):
     c = wl.turbulence_3d(n=(40, 24, 20), mach=1.5, seed=14, steps=10)
     say("determinism")

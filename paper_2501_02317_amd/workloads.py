@@ -20,6 +20,8 @@ Workloads (paper sections in brackets):
                       p = 1/gamma so c_s = 1 at rho = 1.
   * shear_layer_2d -- double tanh shear layer with density ratio 1:2
                       [Sec. 4.5].
+  * implosion_2d   -- diagonal two-state problem in a reflecting box
+                      [Sec. 4.3, eq. lw-init].
   * batch_sizes    -- ragged 2-D mesh sizes for the batched workload.
 """
 from dataclasses import dataclass, field
@@ -106,6 +108,23 @@ def two_state_1d(left, right, N=256, gamma=1.4, cfl=0.4, t_end=0.2, x0=0.5, name
 
 def sod_1d(N=256):
     return two_state_1d((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), N=N, name="sod_1d")
+
+
+def implosion_2d(N=256, side=0.3, t_end=2.5, gamma=1.4, cfl=0.4):
+    """Diagonal two-state problem with reflecting walls (the implosion of
+    Sec. 4.3, eq. lw-init): (rho, p, v) = (0.125, 0.14, 0) where x + y <
+    0.15, (1, 1, 0) elsewhere, on the square [0, side]^2 (side: a reading,
+    twice the leg of the low-pressure triangle).  Symmetric under x <-> y."""
+    n = (N, N)
+    x, y = _centres(n, (0.0, 0.0), (side, side))
+    low = (x[None, :] + y[:, None]) < 0.15
+    rho = np.where(low, 0.125, 1.0)
+    p = np.where(low, 0.14, 1.0)
+    zero = np.zeros((N, N))
+    W = _pack(n, rho.reshape(_shape(n)), [zero.reshape(_shape(n)), zero.reshape(_shape(n))],
+              p.reshape(_shape(n)))
+    bc = ((REFLECT, REFLECT), (REFLECT, REFLECT))
+    return Case(f"implosion_{N}", n, (0.0, 0.0), (side, side), gamma, cfl, W, bc=bc, t_end=t_end)
 
 
 def random_two_state(seed, gamma=1.4):

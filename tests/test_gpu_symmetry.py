@@ -1,0 +1,58 @@
+"""Directional symmetry with reflecting walls (Sec. 4.3): the diagonal
+implosion (eq. lw-init) run on the GPU to t = 2.5 stays exactly symmetric
+about the diagonal in both precisions and with both integrators, and
+matches the oracle early in the run."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2501_02317_amd import workloads as wl
+from gpu_util import gpu_mesh, oracle_mesh, rel_l1, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2501_02317_amd import hydro
+    return hydro
+
+
+def diagonal_mirror(U):
+    T = np.swapaxes(U, 2, 3).copy()
+    T[[1, 2]] = T[[2, 1]]
+    return T
+
+
+@pytest.mark.parametrize("precision,integrator", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_implosion_stays_symmetric(H, precision, integrator):
+    c = wl.implosion_2d(N=256, t_end=2.5)
+    say("implosion", precision, integrator)
+    h = gpu_mesh(c, precision, integrator)
+    h.step_auto(100000, c.t_end)
+    U = h.get_state()
+    t, s = h.time(), h.steps_done()
+    h.close()
+    print(f"precision {precision} integrator {integrator}: {s} steps to t={t}")
+    assert t == c.t_end and s > 1000
+    assert np.array_equal(diagonal_mirror(U), U)
+
+
+@pytest.mark.parametrize("integrator", [0, 1])
+def test_implosion_matches_oracle_early(H, integrator):
+    c = wl.implosion_2d(N=128, t_end=0.045)
+    m = oracle_mesh(c, integrator)
+    U0 = O.prim_to_cons(m, c.W)
+    U_o, t_o, s_o, _ = O.run(m, U0, c.cfl, t_end=c.t_end)
+    say("implosion vs oracle", integrator)
+    for precision, tol in ((0, 1e-12), (1, 1e-3)):
+        h = gpu_mesh(c, precision, integrator)
+        h.step_auto(s_o + 3, c.t_end)
+        U, t, s = h.get_state(), h.time(), h.steps_done()
+        h.close()
+        err = rel_l1(U, U_o)
+        print(f"integrator {integrator} precision {precision}: relL1 {err}, steps {s} vs {s_o}")
+        assert t == c.t_end and s == s_o
+        assert np.all(err <= tol), err

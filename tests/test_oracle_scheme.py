@@ -307,3 +307,18 @@ def test_sampled_cells_match_full_mesh_bitwise(ndim, bc):
     assert np.array_equal(O.rhs_cells(m, U0, dt, cells), dU[:, cells])
     U1 = O.heun_step(m, U0, dt).reshape(m.ncomp, -1)
     assert np.array_equal(O.step_cells(m, U0, dt, cells), U1[:, cells])
+
+
+@pytest.mark.parametrize("integrator", [0, 1])
+def test_diagonal_implosion_keeps_reflection_symmetry(integrator):
+    """Sec. 4.3: a state symmetric about the diagonal, in a reflecting box,
+    stays exactly symmetric (x <-> y with v_x <-> v_y), both integrators."""
+    c = wl.implosion_2d(N=48, t_end=0.05)
+    m = O.Mesh(c.n, c.gamma, c.lo, c.hi, c.bc, integrator=integrator)
+    U, t, s, _ = O.run(m, O.prim_to_cons(m, c.W), c.cfl, t_end=c.t_end)
+    assert t == 0.05 and s > 20
+    T = np.swapaxes(U, 2, 3).copy()
+    T[[1, 2]] = T[[2, 1]]
+    assert np.array_equal(T, U)
+    W = O.cons_to_prim(m, U)
+    assert not np.allclose(W[0], c.W[0])          # the shock has moved

@@ -13,7 +13,9 @@
  *
  * Data conventions
  *   - ndim in {1,2,3}; n[d] interior cells on axis d; axes d >= ndim must
- *     have n[d] == 1.  ncomp = 2 + ndim.
+ *     have n[d] == 1.  ncomp = 2 + ndim.  A plane of the kernels' marching
+ *     axis (n[0] * n[1] cells in 3-D, n[0] in 1-D and 2-D) must hold fewer
+ *     than 2^29 cells.
  *   - Conserved state U = (rho, m_1..m_ndim, E), primitive W = (rho,
  *     v_1..v_ndim, p): only in-plane momenta are carried.
  *   - Host and device fields are FP64, layout [comp][k][j][i] with i (x)

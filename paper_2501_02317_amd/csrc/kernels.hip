@@ -525,6 +525,42 @@ __device__ __forceinline__ void in_to_w(double gm1, const double (&u)[NDIM + 2],
     }
 }
 
+// Access to one plane of a [comp][cell] field through a buffer resource:
+// the plane base (component base + plane offset, the same for the whole
+// work-group) lives in scalar registers and the thread supplies a 32-bit
+// byte offset, so no per-thread 64-bit address arithmetic is needed.  The
+// resource covers exactly the plane (extent bytes): an offset outside it
+// reads 0 and writes nothing.
+constexpr int kBufferWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9)
+typedef unsigned int u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T* F, long long uniform_off,
+                                                             uint32_t extent_bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(F + uniform_off), (short)0, (int)extent_bytes,
+                                             kBufferWord3);
+}
+
+template <typename T>
+__device__ __forceinline__ T plane_load(const T* F, long long uniform_off, uint32_t extent_bytes,
+                                        uint32_t thread_bytes) {
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(F, uniform_off, extent_bytes);
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, thread_bytes, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, thread_bytes, 0, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void plane_store(T* F, long long uniform_off, uint32_t extent_bytes,
+                                            uint32_t thread_bytes, T v) {
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(F, uniform_off, extent_bytes);
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, thread_bytes, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, thread_bytes, 0, 0);
+}
+
 // NC values of one cell from a field of type T (layout [comp][cell]) as doubles.
 template <int NC, typename T>
 __device__ __forceinline__ void load_as_double(const T* __restrict__ F, long long N, long long cell,
@@ -680,17 +716,24 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
     int vmA = VM_NONE, vmB = VM_NONE;
 
     // interior plane z (any z: outside the mesh it is a ghost plane)
-    auto load_in = [&](long long cell, double (&u)[NC]) {
-        if constexpr (PRIM_IN)
-            load_as_double<NC>(reinterpret_cast<const R*>(a.in), N, cell, u);
-        else
-            load_u<NC>(a.in, N, cell, u);
+    // cell (plane offset poff, the same for the work-group) + (in-plane index tc)
+    const uint32_t ext8 = (uint32_t)P * 8u, extR = (uint32_t)P * (uint32_t)sizeof(R);
+    auto load_in = [&](long long poff, uint32_t tc, double (&u)[NC]) {
+        if constexpr (PRIM_IN) {
+            const R* F = reinterpret_cast<const R*>(a.in);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) u[c] = (double)plane_load(F, c * N + poff, extR, tc * (uint32_t)sizeof(R));
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) u[c] = plane_load(a.in, c * N + poff, ext8, tc * 8u);
+        }
     };
+    const uint32_t col32 = (uint32_t)col, hcol32 = (uint32_t)hcol;
     auto load_interior = [&](int z, double (&u)[NC], int& vm) {
         vm = VM_NONE;
         int zr = z;
         if (z < 0 || z >= n2) zr = resolve(g, 2, z, vm);
-        load_in((long long)zr * P + col, u);
+        load_in((long long)zr * P, col32, u);
     };
 
     if (HZ && act) {
@@ -788,7 +831,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                 }
             } else {
                 double u[NC];
-                load_in((long long)k * P + col, u);
+                load_in((long long)k * P, col32, u);
                 in_to_w<NDIM, R, PRIM_IN>(gm1, u, -1, VM_NONE, wc, bad);
             }
 #pragma unroll
@@ -797,7 +840,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
         if (live && hact) {
             double uh[NC];
             R wh[NC];
-            load_in((long long)k * P + hcol, uh);
+            load_in((long long)k * P, hcol32, uh);
             // not checked here: every cell is checked by the tile that owns it
             in_to_w<NDIM, R, PRIM_IN, false>(gm1, uh, hvax, hvm, wh, bad);
 #pragma unroll
@@ -876,7 +919,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
         if (!ONE) __syncthreads();
 
         if (act && ku >= z0) {
-            const long long cell = (long long)ku * P + col;
+            const long long kuP = (long long)ku * P;  // plane offset of the updated cell
+            const uint32_t colb = col32 * (uint32_t)sizeof(double);
             // z fluxes of faces ku-1/2 and ku+1/2
             const FT(&zlo)[NC] = ONE ? fza : fzb;
             const FT(&zhi)[NC] = ONE ? fzb : fzc;
@@ -885,9 +929,13 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
 #pragma unroll
                 for (int c = 0; c < NC; ++c) uin[c] = sRaw[RING ? ku % RS : 0][RING ? c : 0][RING ? tid : 0];
             } else if (NEED_UIN) {
-                load_u<NC>(a.in, N, cell, uin);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) uin[c] = plane_load(a.in, c * N + kuP, ext8, colb);
             }
-            if (NEED_BASE) load_u<NC>(a.base, N, cell, ubase);
+            if (NEED_BASE) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) ubase[c] = plane_load(a.base, c * N + kuP, ext8, colb);
+            }
             double unew[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
@@ -906,7 +954,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                     r = ubase[c] + acc;
                 else
                     r = 0.5 * ubase[c] + 0.5 * (uin[c] + acc);
-                if (!PRED) a.out[c * N + cell] = r;
+                if (!PRED) plane_store(a.out, c * N + kuP, ext8, colb, r);
                 unew[c] = r;
             }
             if (PRED) {
@@ -915,7 +963,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                 bad |= !cons_to_prim<NDIM>(gm1, unew, w);
                 R* wout = reinterpret_cast<R*>(a.out);
 #pragma unroll
-                for (int c = 0; c < NC; ++c) wout[c * N + cell] = (R)w[c];
+                for (int c = 0; c < NC; ++c)
+                    plane_store(wout, c * N + kuP, extR, col32 * (uint32_t)sizeof(R), (R)w[c]);
             }
             if (EPILOGUE && a.want_dt) {
                 double w[NC];
@@ -1349,10 +1398,12 @@ hipError_t launch_any(int ndim, int precision, int mode, const Tile& t, const La
 Tile default_tile(const Geo& g, int precision, int mode) {
     Tile t;
     if (g.ndim == 3) {
-        // 32 x 16 halves the share of halo cells and extra faces; the mixed
-        // stage 2 keeps 32 x 8, where its input ring still leaves three
-        // work-groups per CU
-        const bool narrow = precision == 1 && mode == MODE_STAGE2;  // the Heun stage 2 only
+        // From a sweep at 256^3: 32 x 16 halves the share of halo cells and
+        // extra faces where the occupancy allows it; 32 x 8 where a larger
+        // work-group would cost occupancy (the mixed Heun stage 2 beside its
+        // input ring; the FP64 kernels other than the double-buffered Heun
+        // stage 2).
+        const bool narrow = precision == 1 ? mode == MODE_STAGE2 : mode != MODE_STAGE2;
         t.tx = 32;
         t.ty = narrow ? 8 : 16;
     } else if (g.ndim == 2) {

@@ -66,6 +66,10 @@ bool config_ok(const hydro_config* c) {
         cells *= c->n[d];
         if (cells > (1ll << 40)) return false;
     }
+    // the stage kernels address one plane of the marching axis (x-y in 3-D,
+    // a row in 1-D and 2-D) with 32-bit byte offsets
+    const long long plane = (long long)c->n[0] * (c->ndim == 3 ? c->n[1] : 1);
+    if (plane * 8 >= (1ll << 32)) return false;
     return true;
 }
 

@@ -108,6 +108,8 @@ def lib():
             "orc_vl2_step": (C.c_int, [mp, _dp, C.c_double]),
             "orc_run": (C.c_int, [mp, _dp, C.c_double, C.c_int, C.c_double, _dp,
                                   C.POINTER(C.c_int), _dp]),
+            "orc_run_blocks": (C.c_int, [mp, C.POINTER(C.c_int32), _dp, C.c_double, C.c_int, C.c_double,
+                                         _dp, C.POINTER(C.c_int), _dp]),
             "orc_totals": (None, [mp, _dp, _dp]),
             "orc_rhs_cells": (C.c_int, [mp, _dp, C.c_double, C.c_int, _i64p, _dp]),
             "orc_step_cells": (C.c_int, [mp, _dp, C.c_double, C.c_int, _i64p, _dp]),
@@ -241,6 +243,21 @@ def run(mesh, U, cfl, max_steps=0, t_end=0.0, t0=0.0):
     rc = lib().orc_run(C.byref(mesh.to_c()), _p(U), float(cfl), int(max_steps), float(t_end),
                        C.byref(t), C.byref(steps), _p(dts) if max_steps > 0 else C.cast(None, _dp))
     _check(rc, "run")
+    return U, t.value, steps.value, dts[: steps.value] if max_steps > 0 else None
+
+
+def run_blocks(mesh, blocks, U, cfl, max_steps=0, t_end=0.0, t0=0.0):
+    """run() on the mesh split into blocks[0] x blocks[1] x blocks[2] equal
+    blocks with c-boundary ghost exchange; U in the mesh layout."""
+    U = _field(mesh, U).copy()
+    B = (C.c_int32 * 3)(*(list(blocks) + [1] * (3 - len(blocks))))
+    t = C.c_double(t0)
+    steps = C.c_int(0)
+    cap = max_steps if max_steps > 0 else 1_000_000
+    dts = np.zeros(cap)
+    rc = lib().orc_run_blocks(C.byref(mesh.to_c()), B, _p(U), float(cfl), int(max_steps), float(t_end),
+                              C.byref(t), C.byref(steps), _p(dts) if max_steps > 0 else C.cast(None, _dp))
+    _check(rc, "run_blocks")
     return U, t.value, steps.value, dts[: steps.value] if max_steps > 0 else None
 
 

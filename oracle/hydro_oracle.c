@@ -331,8 +331,9 @@ static int64_t pidx(const padgeo* p, int i, int j, int k) {
     return ((int64_t)(k + p->pad[2]) * p->P[1] + (j + p->pad[1])) * p->P[0] + (i + p->pad[0]);
 }
 
-int orc_fill_ghosts(const orc_mesh* m, double* Wpad) {
-    if (!mesh_ok(m)) return -1;
+/* Ghosts of the sides whose cside[d][s] is set were written by a neighbouring
+ * block (c-boundaries); the others follow the p-boundary rules. */
+static void fill_ghosts_masked(const orc_mesh* m, double* Wpad, const int (*cside)[2]) {
     int nc = m->ndim + 2;
     padgeo pg = pad_geometry(m);
     for (int d = 0; d < m->ndim; ++d) {
@@ -344,6 +345,7 @@ int orc_fill_ghosts(const orc_mesh* m, double* Wpad) {
         for (int a = 0; a < m->n[e1]; ++a)
             for (int b = 0; b < m->n[e2]; ++b)
                 for (int q = 0; q < 4; ++q) {
+                    if (cside && cside[d][q < 2 ? 0 : 1]) continue;
                     int vmode;
                     int src = ghost_src(m, d, ghosts[q], &vmode);
                     int gi[3], si[3];
@@ -357,12 +359,22 @@ int orc_fill_ghosts(const orc_mesh* m, double* Wpad) {
                     Wpad[(1 + d) * pg.total + go] = apply_vmode(Wpad[(1 + d) * pg.total + go], vmode);
                 }
     }
+}
+
+int orc_fill_ghosts(const orc_mesh* m, double* Wpad) {
+    if (!mesh_ok(m)) return -1;
+    fill_ghosts_masked(m, Wpad, NULL);
     return 0;
 }
 
 /* ------------------------------------------------------------- stage rhs */
 
-static int rhs_padded(const orc_mesh* m, double* Wp, double dt, int order, double* dU);
+static int rhs_core(const orc_mesh* m, const double* dx, const int (*cside)[2], double* Wp, double dt,
+                    int order, double* dU);
+
+static int rhs_padded(const orc_mesh* m, double* Wp, double dt, int order, double* dU) {
+    return rhs_core(m, NULL, NULL, Wp, dt, order, dU);
+}
 
 int orc_rhs(const orc_mesh* m, const double* U, double dt, double* dU) {
     if (!mesh_ok(m)) return -1;
@@ -421,15 +433,17 @@ int orc_rhs_prim(const orc_mesh* m, const double* W, double dt, int order, doubl
 }
 
 /* Stage right-hand side from the padded primitive array Wp (interior filled;
- * the ghosts are filled here by the boundary rules), with piecewise-constant
- * (order 1) or PLM (order 2) face states. */
-static int rhs_padded(const orc_mesh* m, double* Wp, double dt, int order, double* dU) {
+ * the ghosts of sides not marked in cside are filled here by the boundary
+ * rules), with piecewise-constant (order 1) or PLM (order 2) face states.
+ * dx: cell widths (NULL: those of m). */
+static int rhs_core(const orc_mesh* m, const double* dx, const int (*cside)[2], double* Wp, double dt,
+                    int order, double* dU) {
     int ndim = m->ndim, nc = ndim + 2;
     double g = m->gamma;
     int64_t N = ncells(m);
     int n0 = m->n[0], n1 = m->n[1], n2 = m->n[2];
     padgeo pg = pad_geometry(m);
-    orc_fill_ghosts(m, Wp);
+    fill_ghosts_masked(m, Wp, cside);
 
     /* face fluxes: axis d has n_d + 1 faces per line; face f separates cells f-1 and f */
     double* Fd[3] = {NULL, NULL, NULL};
@@ -463,7 +477,7 @@ static int rhs_padded(const orc_mesh* m, double* Wp, double dt, int order, doubl
 
     /* dU_i = sum over d (in order) of dt/dx_d (F_{d,i-1/2} - F_{d,i+1/2}) */
     double lam[3];
-    for (int d = 0; d < ndim; ++d) lam[d] = dt / cell_width(m, d);
+    for (int d = 0; d < ndim; ++d) lam[d] = dt / (dx ? dx[d] : cell_width(m, d));
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < n2; ++k)
         for (int j = 0; j < n1; ++j)
@@ -594,6 +608,261 @@ int orc_run(const orc_mesh* m, double* U, double cfl, int max_steps, double t_en
         *t = last ? t_end : *t + dt;
         ++s;
     }
+    if (steps_done) *steps_done = s;
+    return rc;
+}
+
+/* ------------------------------------------------------ multi-block mesh */
+
+/* The mesh split into B[0] x B[1] x B[2] blocks of equal extents (every block
+ * holds the same number of cells).  Block b = b0 + B0 (b1 + B1 b2) keeps its
+ * cells in its own array, layout [b][comp][k][j][i] of the block's extents,
+ * and its own padded primitive array.  At a face shared with another block
+ * (a c-boundary) its ghost layers are the neighbour's n_gh interior layers
+ * next to that face, which the neighbour writes straight into them; at the
+ * faces of the whole mesh the p-boundary rules of Sec. 3.1.1 fill them.  A
+ * periodic axis links the blocks at its two ends (one block on that axis is
+ * its own neighbour, which is the periodic rule itself). */
+typedef struct {
+    orc_mesh mb;   /* one block: the block's extents, the mesh's boundary codes */
+    int B[3];
+    int nblk;
+    int64_t nb;    /* cells per block */
+    double dx[3];  /* the mesh's cell widths */
+} blockgeo;
+
+static int block_geometry(const orc_mesh* m, const int32_t* blocks, blockgeo* bg) {
+    if (!mesh_ok(m) || !blocks) return 0;
+    bg->mb = *m;
+    bg->nblk = 1;
+    for (int d = 0; d < 3; ++d) {
+        int B = blocks[d];
+        if (B < 1 || (d >= m->ndim && B != 1) || m->n[d] % B != 0) return 0;
+        /* a neighbour supplies all n_gh ghost layers of a shared face */
+        if (B > 1 && m->n[d] / B < NGH) return 0;
+        bg->B[d] = B;
+        bg->nblk *= B;
+        bg->mb.n[d] = m->n[d] / B;
+        bg->dx[d] = d < m->ndim ? cell_width(m, d) : 1.0;
+    }
+    bg->nb = ncells(&bg->mb);
+    return mesh_ok(&bg->mb);
+}
+
+/* The block across side s (0: low, 1: high) of axis d from block b, or -1 at
+ * a face of the whole mesh that is not periodic. */
+static int block_nbr(const blockgeo* bg, int b, int d, int s) {
+    int c[3] = {b % bg->B[0], (b / bg->B[0]) % bg->B[1], b / (bg->B[0] * bg->B[1])};
+    int q = c[d] + (s ? 1 : -1);
+    if (q < 0 || q >= bg->B[d]) {
+        if (bg->mb.bc[d][s] != ORC_BC_PERIODIC) return -1;
+        q = (q + bg->B[d]) % bg->B[d];
+    }
+    c[d] = q;
+    return c[0] + bg->B[0] * (c[1] + bg->B[1] * c[2]);
+}
+
+/* Stage right-hand side of every block from X (conserved, or primitive when
+ * prim is set), block layout; see orc_rhs and orc_rhs_prim. */
+static int blocks_rhs(const blockgeo* bg, const double* X, int prim, double dt, int order, double* dU) {
+    const orc_mesh* mb = &bg->mb;
+    int ndim = mb->ndim, nc = ndim + 2;
+    int n0 = mb->n[0], n1 = mb->n[1], n2 = mb->n[2];
+    int64_t nb = bg->nb;
+    padgeo pg = pad_geometry(mb);
+    double* Wp = (double*)calloc((size_t)bg->nblk * nc * pg.total, sizeof(double));
+    if (!Wp) return -1;
+    int bad = 0;
+    /* each block: its interior primitive state */
+    for (int b = 0; b < bg->nblk; ++b) {
+        const double* Xb = X + (int64_t)b * nc * nb;
+        double* Wb = Wp + (int64_t)b * nc * pg.total;
+        for (int k = 0; k < n2; ++k)
+            for (int j = 0; j < n1; ++j)
+                for (int i = 0; i < n0; ++i) {
+                    int64_t cell = ((int64_t)k * n1 + j) * n0 + i;
+                    double x[MAXC], w[MAXC];
+                    for (int c = 0; c < nc; ++c) x[c] = Xb[c * nb + cell];
+                    if (prim) {
+                        for (int c = 0; c < nc; ++c) {
+                            w[c] = x[c];
+                            if (!isfinite(w[c])) ++bad;
+                        }
+                        if (!(w[0] > 0.0) || !(w[nc - 1] > 0.0)) ++bad;
+                    } else if (!cons_to_prim_cell(ndim, mb->gamma, x, w)) {
+                        ++bad;
+                    }
+                    int64_t o = pidx(&pg, i, j, k);
+                    for (int c = 0; c < nc; ++c) Wb[c * pg.total + o] = w[c];
+                }
+    }
+    if (bad) {
+        free(Wp);
+        return bad;
+    }
+    /* c-boundaries: each block writes its n_gh interior layers next to a
+     * shared face into the neighbour's ghost layers on the other side of it
+     * (its low layers 0, 1 become the low neighbour's ghosts N, N+1; its high
+     * layers N-2, N-1 the high neighbour's ghosts -2, -1) */
+    for (int b = 0; b < bg->nblk; ++b) {
+        const double* Ws = Wp + (int64_t)b * nc * pg.total;
+        for (int d = 0; d < ndim; ++d) {
+            int N = mb->n[d];
+            int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
+            for (int s = 0; s < 2; ++s) {
+                int nbr = block_nbr(bg, b, d, s);
+                if (nbr < 0) continue;
+                double* Wd = Wp + (int64_t)nbr * nc * pg.total;
+                for (int a = 0; a < mb->n[e1]; ++a)
+                    for (int bb = 0; bb < mb->n[e2]; ++bb)
+                        for (int L = 0; L < NGH; ++L) {
+                            int si[3], di[3];
+                            si[d] = s == 0 ? L : N - NGH + L;
+                            di[d] = s == 0 ? N + L : -NGH + L;
+                            si[e1] = di[e1] = a;
+                            si[e2] = di[e2] = bb;
+                            int64_t so = pidx(&pg, si[0], si[1], si[2]);
+                            int64_t go = pidx(&pg, di[0], di[1], di[2]);
+                            for (int c = 0; c < nc; ++c) Wd[c * pg.total + go] = Ws[c * pg.total + so];
+                        }
+            }
+        }
+    }
+    /* each block: the p-boundary ghosts, the fluxes and the update */
+    int rc = 0;
+    for (int b = 0; b < bg->nblk && rc == 0; ++b) {
+        int cside[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+        for (int d = 0; d < ndim; ++d)
+            for (int s = 0; s < 2; ++s) cside[d][s] = block_nbr(bg, b, d, s) >= 0;
+        rc = rhs_core(mb, bg->dx, (const int(*)[2])cside, Wp + (int64_t)b * nc * pg.total, dt, order,
+                      dU + (int64_t)b * nc * nb);
+    }
+    free(Wp);
+    return rc;
+}
+
+/* conserved -> primitive over all blocks; returns the count of bad cells */
+static int blocks_cons_to_prim(const blockgeo* bg, const double* U, double* W) {
+    int nc = bg->mb.ndim + 2, bad = 0;
+    for (int b = 0; b < bg->nblk; ++b)
+        for (int64_t i = 0; i < bg->nb; ++i) {
+            const int64_t o = (int64_t)b * nc * bg->nb + i;
+            double u[MAXC], w[MAXC];
+            for (int c = 0; c < nc; ++c) u[c] = U[o + c * bg->nb];
+            if (!cons_to_prim_cell(bg->mb.ndim, bg->mb.gamma, u, w)) ++bad;
+            for (int c = 0; c < nc; ++c) W[o + c * bg->nb] = w[c];
+        }
+    return bad;
+}
+
+static int blocks_heun_step(const blockgeo* bg, double* U, double dt) {
+    int64_t tot = (int64_t)bg->nblk * (bg->mb.ndim + 2) * bg->nb;
+    double* U1 = (double*)malloc((size_t)tot * sizeof(double));
+    double* dU = (double*)malloc((size_t)tot * sizeof(double));
+    int rc = (U1 && dU) ? blocks_rhs(bg, U, 0, dt, 2, dU) : -1;
+    if (rc == 0) {
+        for (int64_t q = 0; q < tot; ++q) U1[q] = U[q] + dU[q];
+        rc = blocks_rhs(bg, U1, 0, dt, 2, dU);
+    }
+    if (rc == 0)
+        for (int64_t q = 0; q < tot; ++q) U[q] = 0.5 * U[q] + 0.5 * (U1[q] + dU[q]);
+    free(U1);
+    free(dU);
+    return rc;
+}
+
+static int blocks_vl2_step(const blockgeo* bg, double* U, double dt) {
+    int64_t tot = (int64_t)bg->nblk * (bg->mb.ndim + 2) * bg->nb;
+    double* W = (double*)malloc((size_t)tot * sizeof(double));
+    double* dU = (double*)malloc((size_t)tot * sizeof(double));
+    int rc = (W && dU) ? blocks_cons_to_prim(bg, U, W) : -1;
+    if (rc == 0) rc = blocks_rhs(bg, W, 1, 0.5 * dt, 1, dU);
+    if (rc == 0) {
+        /* W* = W(U^n + dU), cell by cell */
+        for (int64_t q = 0; q < tot; ++q) dU[q] = U[q] + dU[q];
+        rc = blocks_cons_to_prim(bg, dU, W) ? 1 : 0;
+    }
+    if (rc == 0) rc = blocks_rhs(bg, W, 1, dt, 2, dU);
+    if (rc == 0)
+        for (int64_t q = 0; q < tot; ++q) U[q] = U[q] + dU[q];
+    free(W);
+    free(dU);
+    return rc;
+}
+
+/* the global CFL step: the smallest over blocks of each block's own step */
+static double blocks_cfl_dt(const blockgeo* bg, const double* U, double cfl) {
+    int ndim = bg->mb.ndim, nc = ndim + 2;
+    double g = bg->mb.gamma, best = INFINITY;
+    for (int b = 0; b < bg->nblk; ++b) {
+        double bb = INFINITY;
+        for (int64_t i = 0; i < bg->nb; ++i) {
+            double u[MAXC], w[MAXC];
+            for (int c = 0; c < nc; ++c) u[c] = U[(int64_t)b * nc * bg->nb + c * bg->nb + i];
+            if (!cons_to_prim_cell(ndim, g, u, w)) return -1.0;
+            double cs = sqrt(g * w[nc - 1] / w[0]);
+            for (int d = 0; d < ndim; ++d) {
+                double cand = bg->dx[d] / (fabs(w[1 + d]) + cs);
+                if (cand < bb) bb = cand;
+            }
+        }
+        if (bb < best) best = bb;
+    }
+    return cfl * best;
+}
+
+/* mesh layout <-> block layout */
+static void blocks_relayout(const orc_mesh* m, const blockgeo* bg, double* mesh_f, double* blk_f, int to_blocks) {
+    int nc = m->ndim + 2;
+    int64_t N = ncells(m);
+    const int* nb = bg->mb.n;
+    for (int k = 0; k < m->n[2]; ++k)
+        for (int j = 0; j < m->n[1]; ++j)
+            for (int i = 0; i < m->n[0]; ++i) {
+                int b = i / nb[0] + bg->B[0] * (j / nb[1] + bg->B[1] * (k / nb[2]));
+                int64_t lc = ((int64_t)(k % nb[2]) * nb[1] + (j % nb[1])) * nb[0] + (i % nb[0]);
+                int64_t gc = ((int64_t)k * m->n[1] + j) * m->n[0] + i;
+                for (int c = 0; c < nc; ++c) {
+                    double* bp = blk_f + (int64_t)b * nc * bg->nb + c * bg->nb + lc;
+                    double* mp = mesh_f + c * N + gc;
+                    if (to_blocks)
+                        *bp = *mp;
+                    else
+                        *mp = *bp;
+                }
+            }
+}
+
+int orc_run_blocks(const orc_mesh* m, const int32_t blocks[3], double* U, double cfl, int max_steps,
+                   double t_end, double* t, int* steps_done, double* dts) {
+    blockgeo bg;
+    if (!block_geometry(m, blocks, &bg) || !t || !(cfl > 0.0)) return -1;
+    if (max_steps <= 0 && !(t_end > 0.0)) return -1;
+    int64_t tot = (int64_t)bg.nblk * (m->ndim + 2) * bg.nb;
+    double* Ub = (double*)malloc((size_t)tot * sizeof(double));
+    if (!Ub) return -1;
+    blocks_relayout(m, &bg, U, Ub, 1);
+    int s = 0, rc = 0;
+    while (max_steps <= 0 || s < max_steps) {
+        if (t_end > 0.0 && !(*t < t_end)) break;
+        double dt = blocks_cfl_dt(&bg, Ub, cfl);
+        if (!(dt > 0.0)) {
+            rc = 1;
+            break;
+        }
+        int last = 0;
+        if (t_end > 0.0 && dt >= t_end - *t) {
+            dt = t_end - *t;
+            last = 1;
+        }
+        rc = m->integrator == ORC_VL2 ? blocks_vl2_step(&bg, Ub, dt) : blocks_heun_step(&bg, Ub, dt);
+        if (rc) break;
+        if (dts) dts[s] = dt;
+        *t = last ? t_end : *t + dt;
+        ++s;
+    }
+    blocks_relayout(m, &bg, U, Ub, 0);
+    free(Ub);
     if (steps_done) *steps_done = s;
     return rc;
 }

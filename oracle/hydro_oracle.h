@@ -105,6 +105,19 @@ int orc_vl2_step(const orc_mesh* m, double* U, double dt);
 int orc_run(const orc_mesh* m, double* U, double cfl, int max_steps, double t_end, double* t,
             int* steps_done, double* dts);
 
+/*
+ * orc_run on the mesh split into blocks[0] x blocks[1] x blocks[2] blocks of
+ * equal extents (blocks[d] divides n[d]; a split axis gives every block at
+ * least 2 cells on it; blocks[d] = 1 for d >= ndim).  Each block keeps its
+ * own cells and ghost zones: at a face shared by two blocks (a c-boundary,
+ * which a periodic axis adds between its end blocks) each block writes its
+ * two interior layers next to the face into the other's ghost zone; the
+ * faces of the whole mesh follow the p-boundary rules; the time step is the
+ * smallest over the blocks.  U is read and written in the mesh layout.
+ */
+int orc_run_blocks(const orc_mesh* m, const int32_t blocks[3], double* U, double cfl, int max_steps,
+                   double t_end, double* t, int* steps_done, double* dts);
+
 /* dV-weighted conserved totals, compensated (Neumaier) sums in storage order. */
 void orc_totals(const orc_mesh* m, const double* U, double* totals);
 

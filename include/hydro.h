@@ -29,8 +29,11 @@
  *   - Device memory is owned by the caller: hydro_create carves its state
  *     out of a caller-provided device workspace of at least
  *     hydro_workspace_bytes(cfg) bytes (256-byte aligned), which must outlive
- *     the handle.  The handle itself owns only host metadata and a small
- *     pinned host staging buffer.
+ *     the handle.  The handle itself owns only host metadata, a small
+ *     pinned host staging buffer and, once hydro_set_block_streams turns them
+ *     on, its block streams and events.  hydro_stage_rhs,
+ *     hydro_padded_primitive and the host transfers of a split mesh take a
+ *     temporary device buffer (stream-ordered allocation) for the call.
  *   - All device work is enqueued on the caller's HIP stream given at
  *     creation (NULL = the legacy default stream).
  *   - hydro_step / hydro_step_auto return after enqueueing.  hydro_cfl_dt,
@@ -96,7 +99,24 @@ typedef struct {
     int32_t precision; /* enum hydro_precision */
     int32_t bc[3][2];  /* enum hydro_bc per axis side (low, high) */
     int32_t integrator; /* enum hydro_integrator */
+    int32_t blocks[3]; /* blocks per axis (0 or 1: one); see "Blocks" below */
 } hydro_config;
+
+/*
+ * Blocks.  A mesh may be split into blocks[0] x blocks[1] x blocks[2] blocks
+ * of equal extents, as the paper's framework splits a domain into blocks of
+ * the same size: blocks[d] must divide n[d], a split axis must leave every
+ * block at least 2 cells on it, blocks[d] = 1 for d >= ndim, and there are at
+ * most 1024 blocks.  The device state is then stored block after block,
+ * [block][comp][k][j][i] of the block's extents, with block index
+ * b0 + blocks[0] (b1 + blocks[1] b2); every host transfer and
+ * hydro_get_state_device / hydro_set_primitive_device still use the mesh
+ * layout above, and hydro_state_device returns the block layout.  The faces
+ * between blocks are c-boundaries (Sec. 3, block boundaries): a stage reads a
+ * block's ghost cells straight from the neighbouring block's cells on the
+ * same device, with no ghost storage and no copy; the faces of the whole mesh
+ * follow the boundary rules.  Results are bitwise those of the unsplit mesh.
+ */
 
 /* Device bytes a handle for cfg needs; 0 when cfg is invalid. */
 size_t hydro_workspace_bytes(const hydro_config* cfg);
@@ -123,7 +143,8 @@ int hydro_get_state(hydro_t h, double* U_host);
 /* Copy the current conserved state to a device array (async). */
 int hydro_get_state_device(hydro_t h, double* d_U);
 
-/* Device address of the current conserved state (valid until the next step). */
+/* Device address of the current conserved state (valid until the next step;
+ * the block layout when the mesh is split). */
 int hydro_state_device(hydro_t h, const double** d_U);
 
 /* CFL step of the current state, cfl * min over cells and active axes of
@@ -212,6 +233,19 @@ int hydro_autotune(hydro_t h, int steps_per_tile, double t_end, int* tiles, doub
  * their counts (launches[0], launches[1]), and restarts the recording. */
 int hydro_profile(hydro_t h, int cap);
 int hydro_profile_read(hydro_t h, double* ms_stage1, double* ms_stage2, int64_t* launches);
+
+/*
+ * How the stages of a split mesh are launched (Sec. 3, Fig. hydro_proc: each
+ * block's work on a stream of its own).  on = 0 (the default): one launch per
+ * stage covers every block.  on = 1: each block's stages are launched on
+ * their own, spread over four streams the handle creates (default priority,
+ * not synchronising with the legacy default stream); a block's stage 2
+ * waits only for its face neighbours' stage 1, and the step's time-step
+ * update waits for every block.  The results do not depend on the choice.
+ * Stage timing (hydro_profile) records only the one-launch form.  No effect
+ * on a mesh of one block.  Blocks until the handle's stream has drained.
+ */
+int hydro_set_block_streams(hydro_t h, int on);
 
 int hydro_destroy(hydro_t h);
 

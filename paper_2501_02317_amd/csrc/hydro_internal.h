@@ -43,9 +43,18 @@ enum CtrlOp : int {
 // is the physical y axis and kernel axis 1 has extent 1; for 1-D only
 // kernel axis 0 is active.  The cell index (k * n1 + j) * n0 + i is the
 // physical storage index in every case.
+//
+// A mesh may be split into blocks[0] x blocks[1] x blocks[2] blocks of equal
+// extents (kernel axes); n and ncells are those of one block.  Fields are
+// stored block after block, [block][comp][cell of the block], with block
+// index b0 + blocks[0] (b1 + blocks[1] b2).  The boundary codes are those of
+// the whole mesh: a side of a block inside the mesh, or on a periodic axis,
+// reads its ghosts from the neighbouring block (a c-boundary); one block on a
+// periodic axis is its own neighbour.
 struct Geo {
     int ndim;
     int n[3];
+    int blocks[3];
     double dx[3];
     double inv_dx[3];
     int bc[3][2];
@@ -67,7 +76,8 @@ struct StageArgs {
     double dt_host;      // dt when use_device_dt == 0
     int use_device_dt;   // dt from ctrl (clamped to its t_end); skip the mesh when done
     int want_dt;         // stage 2: accumulate the next CFL candidate
-    int tiles_x, tiles_y, chunks_z, kz;
+    int tiles_x, tiles_y, chunks_z, kz;  // per block
+    int blk0, nblk;      // the launch covers blocks blk0 .. blk0 + nblk - 1
 };
 
 // One member of a batch: the stage kernels build StageArgs from it.
@@ -96,7 +106,11 @@ hipError_t launch_dt(const Geo& g, const double* U, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_ctrl(Ctrl* c, int op, double a0, double a1, double cfl, hipStream_t s);
 hipError_t launch_totals(const Geo& g, const double* U, double* partials, int nparts, Ctrl* ctrl,
                          hipStream_t s);
+// W and U in the block layout; in place when W == U.
 hipError_t launch_prim_to_cons(const Geo& g, const double* W, double* U, hipStream_t s);
+// Copy a field between the mesh layout [comp][k][j][i] (mesh) and the block
+// layout (blk): to_blocks != 0 reads mesh and writes blk, else the reverse.
+hipError_t launch_relayout(const Geo& g, double* mesh, double* blk, int to_blocks, hipStream_t s);
 hipError_t launch_padded_prim(const Geo& g, int precision, const double* U, double* Wpad, Ctrl* ctrl,
                               hipStream_t s);
 hipError_t launch_riemann(int precision, int ntan, double gamma, long long n, const double* WL,
@@ -115,5 +129,9 @@ bool tile_supported(int ndim, const Tile& t);
 int tile_candidates(const Geo& g, Tile* out, int max);
 // Number of totals partials the runtime reserves.
 constexpr int kTotalsParts = 1024;
+// Blocks of one mesh: each needs one totals partial at least.
+constexpr int kMaxBlocks = kTotalsParts;
+
+inline int geo_nblk(const Geo& g) { return g.blocks[0] * g.blocks[1] * g.blocks[2]; }
 
 }  // namespace hydro

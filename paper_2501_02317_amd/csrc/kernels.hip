@@ -349,10 +349,11 @@ __device__ __forceinline__ void face_flux_states(const Gas<R>& g, const R (&wl)[
 
 // ---------------------------------------------------------------- boundaries
 
-// Interior index for coordinate q on kernel axis ax and the treatment of
-// the normal velocity (Sec. 3.1.1; each side read as the left-x case).
-__device__ __forceinline__ int resolve(const Geo& g, int ax, int q, int& vmode) {
-    const int N = g.n[ax];
+// Interior index for coordinate q on kernel axis ax of the whole mesh
+// (extent n * blocks) and the treatment of the normal velocity (Sec. 3.1.1;
+// each side read as the left-x case).
+__device__ __forceinline__ int resolve_mesh(const Geo& g, int ax, int q, int& vmode) {
+    const int N = g.n[ax] * g.blocks[ax];
     vmode = VM_NONE;
     if (q >= 0 && q < N) return q;
     if (q < 0) {
@@ -371,6 +372,59 @@ __device__ __forceinline__ int resolve(const Geo& g, int ax, int q, int& vmode) 
     }
 }
 
+// The sides of one block: the block-index offset of the neighbour a side
+// reads its ghosts from (a c-boundary: inside the mesh, or across a periodic
+// axis), or kNoLink at a face of the mesh with a p-boundary rule.
+constexpr int kNoLink = 0x7fffffff;
+struct Links {
+    int lo[3], hi[3];
+};
+
+__device__ __forceinline__ Links block_links(const Geo& g, int blk) {
+    Links L;
+    const int c[3] = {blk % g.blocks[0], (blk / g.blocks[0]) % g.blocks[1], blk / (g.blocks[0] * g.blocks[1])};
+    const int stride[3] = {1, g.blocks[0], g.blocks[0] * g.blocks[1]};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int B = g.blocks[ax];
+        const int wrap = (B - 1) * stride[ax];
+        L.lo[ax] = c[ax] > 0 ? -stride[ax] : (g.bc[ax][0] == BC_PERIODIC ? wrap : kNoLink);
+        L.hi[ax] = c[ax] < B - 1 ? stride[ax] : (g.bc[ax][1] == BC_PERIODIC ? -wrap : kNoLink);
+    }
+    return L;
+}
+
+// Ghost coordinate q (one block's extent N on kernel axis ax) -> the cell it
+// copies: in the linked block dblk (offset in blocks, 0 for the block
+// itself) at q -/+ N, or by the p-boundary rule of a mesh face, with the
+// treatment of the normal velocity (Sec. 3.1.1).
+__device__ __forceinline__ int resolve(const Geo& g, const Links& L, int ax, int q, int& vmode, int& dblk) {
+    const int N = g.n[ax];
+    vmode = VM_NONE;
+    dblk = 0;
+    if (q >= 0 && q < N) return q;
+    if (q < 0) {
+        if (L.lo[ax] != kNoLink) {
+            dblk = L.lo[ax];
+            return q + N;
+        }
+        switch (g.bc[ax][0]) {
+            case BC_FREE: return 0;
+            case BC_OUTFLOW: vmode = VM_CLIP_LO; return 0;
+            default: vmode = VM_NEG; return -1 - q;
+        }
+    }
+    if (L.hi[ax] != kNoLink) {
+        dblk = L.hi[ax];
+        return q - N;
+    }
+    switch (g.bc[ax][1]) {
+        case BC_FREE: return N - 1;
+        case BC_OUTFLOW: vmode = VM_CLIP_HI; return N - 1;
+        default: vmode = VM_NEG; return 2 * N - 1 - q;
+    }
+}
+
 __device__ __forceinline__ double apply_vmode(double v, int vmode) {
     switch (vmode) {
         case VM_NEG: return -v;
@@ -380,27 +434,30 @@ __device__ __forceinline__ double apply_vmode(double v, int vmode) {
     }
 }
 
-// Primitive state at kernel coordinates (x, y, z), at most one of which lies
-// outside the mesh (the axis-aligned stencil never needs corner ghosts).
+// Primitive state at kernel coordinates (x, y, z) of the whole mesh, at most
+// one of which lies outside it (the axis-aligned stencil never needs corner
+// ghosts); U in the block layout.
 template <int NDIM, typename R>
 __device__ __forceinline__ void load_w(const Geo& g, const double* __restrict__ U, int x, int y, int z,
                                        R (&W)[NDIM + 2], bool& bad) {
     constexpr int NC = NDIM + 2;
     int vm = VM_NONE, ax = -1;
-    if (x < 0 || x >= g.n[0]) {
-        x = resolve(g, 0, x, vm);
+    if (x < 0 || x >= g.n[0] * g.blocks[0]) {
+        x = resolve_mesh(g, 0, x, vm);
         ax = 0;
-    } else if (y < 0 || y >= g.n[1]) {
-        y = resolve(g, 1, y, vm);
+    } else if (y < 0 || y >= g.n[1] * g.blocks[1]) {
+        y = resolve_mesh(g, 1, y, vm);
         ax = 1;
-    } else if (z < 0 || z >= g.n[2]) {
-        z = resolve(g, 2, z, vm);
+    } else if (z < 0 || z >= g.n[2] * g.blocks[2]) {
+        z = resolve_mesh(g, 2, z, vm);
         ax = 2;
     }
-    const long long cell = ((long long)z * g.n[1] + y) * g.n[0] + x;
+    const int blk = x / g.n[0] + g.blocks[0] * (y / g.n[1] + g.blocks[1] * (z / g.n[2]));
+    const long long cell = ((long long)(z % g.n[2]) * g.n[1] + y % g.n[1]) * g.n[0] + x % g.n[0];
+    const double* Ub = U + (long long)blk * NC * g.ncells;
     double u[NC], w[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) u[c] = U[c * g.ncells + cell];
+    for (int c = 0; c < NC; ++c) u[c] = Ub[c * g.ncells + cell];
     bad |= !cons_to_prim<NDIM>(g.gamma - 1.0, u, w);
     if (ax >= 0) {
         const int vc = ax == 0 ? 1 : (ax == 1 ? 2 : NDIM);
@@ -613,7 +670,7 @@ struct StageOccupancy {
 };
 
 template <int NDIM, typename R, int MODE, int TX, int TY>
-__device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
+__device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
     constexpr int NC = NDIM + 2;
     constexpr bool HY = (NDIM == 3);
     constexpr bool HZ = (NDIM >= 2);
@@ -637,6 +694,9 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
     const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
     const long long N = g.ncells;
     const long long P = (long long)n0 * n1;  // plane stride
+    const long long BS = (long long)NC * N;  // elements of one block of a field
+    const long long boff = (long long)blk * BS;
+    const Links lk = block_links(g, blk);
     const double gm1 = g.gamma - 1.0;
 
     const int tix = b % a.tiles_x;
@@ -652,7 +712,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
     const bool act = lx < ax && ly < ay;
     const long long col = (long long)(y0 + ly) * n0 + (x0 + lx);
 
-    // this thread's halo cell (tile coordinates hx, hy), resolved once
+    // this thread's halo cell (tile coordinates hx, hy), resolved once to an
+    // element offset in the field (its block's offset + the in-plane index)
     bool hact = false;
     int hx = 0, hy = 0, hvax = -1, hvm = VM_NONE;
     long long hcol = 0;
@@ -671,15 +732,15 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
             hact = true;
         }
         if (hact) {
-            int X = x0 + hx, Y = y0 + hy;
+            int X = x0 + hx, Y = y0 + hy, db = 0;
             if (X < 0 || X >= n0) {
-                X = resolve(g, 0, X, hvm);
+                X = resolve(g, lk, 0, X, hvm, db);
                 hvax = 0;
             } else if (Y < 0 || Y >= n1) {
-                Y = resolve(g, 1, Y, hvm);
+                Y = resolve(g, lk, 1, Y, hvm, db);
                 hvax = 1;
             }
-            hcol = (long long)Y * n0 + X;
+            hcol = (long long)(blk + db) * BS + (long long)Y * n0 + X;
         }
     }
 
@@ -728,12 +789,25 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
             for (int c = 0; c < NC; ++c) u[c] = plane_load(a.in, c * N + poff, ext8, tc * 8u);
         }
     };
-    const uint32_t col32 = (uint32_t)col, hcol32 = (uint32_t)hcol;
+    // the halo cell at plane offset poff: it may lie in another block, so it
+    // is addressed from the field's base with a per-thread offset
+    auto load_halo = [&](long long poff, double (&u)[NC]) {
+        if constexpr (PRIM_IN) {
+            const R* F = reinterpret_cast<const R*>(a.in) + (hcol + poff);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) u[c] = (double)F[c * N];
+        } else {
+            const double* F = a.in + (hcol + poff);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) u[c] = F[c * N];
+        }
+    };
+    const uint32_t col32 = (uint32_t)col;
     auto load_interior = [&](int z, double (&u)[NC], int& vm) {
         vm = VM_NONE;
-        int zr = z;
-        if (z < 0 || z >= n2) zr = resolve(g, 2, z, vm);
-        load_in((long long)zr * P, col32, u);
+        int zr = z, db = 0;
+        if (z < 0 || z >= n2) zr = resolve(g, lk, 2, z, vm, db);
+        load_in((long long)(blk + db) * BS + (long long)zr * P, col32, u);
     };
 
     if (HZ && act) {
@@ -831,7 +905,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
                 }
             } else {
                 double u[NC];
-                load_in((long long)k * P, col32, u);
+                load_in(boff + (long long)k * P, col32, u);
                 in_to_w<NDIM, R, PRIM_IN>(gm1, u, -1, VM_NONE, wc, bad);
             }
 #pragma unroll
@@ -840,7 +914,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
         if (live && hact) {
             double uh[NC];
             R wh[NC];
-            load_in((long long)k * P, hcol32, uh);
+            load_halo((long long)k * P, uh);
             // not checked here: every cell is checked by the tile that owns it
             in_to_w<NDIM, R, PRIM_IN, false>(gm1, uh, hvax, hvm, wh, bad);
 #pragma unroll
@@ -919,7 +993,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b) {
         if (!ONE) __syncthreads();
 
         if (act && ku >= z0) {
-            const long long kuP = (long long)ku * P;  // plane offset of the updated cell
+            const long long kuP = boff + (long long)ku * P;  // plane offset of the updated cell
             const uint32_t colb = col32 * (uint32_t)sizeof(double);
             // z fluxes of faces ku-1/2 and ku+1/2
             const FT(&zlo)[NC] = ONE ? fza : fzb;
@@ -1011,7 +1085,16 @@ __global__ __launch_bounds__(TX * TY)
 __attribute__((amdgpu_waves_per_eu(StageOccupancy<NDIM, R, MODE>::kWaves, StageOccupancy<NDIM, R, MODE>::kWavesMax)))
 void stage_kernel(StageArgs a) {
     if (a.use_device_dt && a.ctrl->done) return;  // uniform over the grid
-    stage_body<NDIM, R, MODE, TX, TY>(a, xcd_remap(blockIdx.x, gridDim.x));
+    // work-group -> (block, work-group within the block)
+    int wg = xcd_remap(blockIdx.x, gridDim.x);
+    int blk = a.blk0;
+    if (a.nblk > 1) {
+        const int per = a.tiles_x * a.tiles_y * a.chunks_z;
+        const int q = wg / per;
+        blk += q;
+        wg -= q * per;
+    }
+    stage_body<NDIM, R, MODE, TX, TY>(a, wg, blk);
 }
 
 // Batched stage: work-group -> (member, work-group of the member) from a
@@ -1033,6 +1116,8 @@ void stage_kernel_batch(
     a.tiles_y = d.tiles_y;
     a.chunks_z = d.chunks_z;
     a.kz = d.kz;
+    a.blk0 = 0;
+    a.nblk = 1;
     if (MODE == MODE_STAGE1 || MODE == MODE_VL2_PRED) {
         a.in = d.U;
         a.base = d.U;
@@ -1044,14 +1129,16 @@ void stage_kernel_batch(
         a.out = d.U;
         a.want_dt = 1;
     }
-    stage_body<NDIM, R, MODE, TX, TY>(a, e.y);
+    stage_body<NDIM, R, MODE, TX, TY>(a, e.y, 0);
 }
 
 // ------------------------------------------------------------- small kernels
 
+// blockIdx.y: the block of the mesh (block layout)
 template <int NDIM>
 __global__ __launch_bounds__(256) void dt_kernel(Geo g, const double* __restrict__ U, Ctrl* ctrl) {
     constexpr int NC = NDIM + 2;
+    U += (long long)blockIdx.y * NC * g.ncells;
     double best = 0.0;
     bool bad = false;
     for (long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x; cell < g.ncells;
@@ -1139,10 +1226,13 @@ __device__ __forceinline__ Comp comp_merge(Comp a, Comp b) {
     return r;
 }
 
+// blockIdx.y: the block of the mesh (block layout); one partial per work-group
 template <int NC>
 __global__ __launch_bounds__(256) void totals_pass1(long long ncells, const double* __restrict__ U,
                                                     double* __restrict__ parts) {
     __shared__ double ss[NC][256], sc[NC][256];
+    U += (long long)blockIdx.y * NC * ncells;
+    parts += (long long)blockIdx.y * gridDim.x * NC * 2;
     const long long per = (ncells + gridDim.x - 1) / gridDim.x;
     const long long lo = (long long)blockIdx.x * per;
     const long long hi = lo + per < ncells ? lo + per : ncells;
@@ -1216,10 +1306,13 @@ __global__ __launch_bounds__(256) void totals_pass2(int nparts, const double* __
 }
 
 // m_d = rho v_d, E = p/(gamma - 1) + (1/2) sum_d m_d v_d
+// W and U may be the same array (each cell is read before it is written);
+// blockIdx.y: the block of the mesh (block layout).
 template <int NDIM>
-// W and U may be the same array (each cell is read before it is written).
 __global__ __launch_bounds__(256) void prim_to_cons_kernel(Geo g, const double* W, double* U) {
     constexpr int NC = NDIM + 2;
+    W += (long long)blockIdx.y * NC * g.ncells;
+    U += (long long)blockIdx.y * NC * g.ncells;
     for (long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x; cell < g.ncells;
          cell += (long long)gridDim.x * blockDim.x) {
         const double rho = W[cell];
@@ -1242,8 +1335,10 @@ template <int NDIM, typename R>
 __global__ __launch_bounds__(256) void padded_prim_kernel(Geo g, const double* __restrict__ U,
                                                           double* __restrict__ Wp, Ctrl* ctrl) {
     constexpr int NC = NDIM + 2;
-    // physical extents: axis p of NDIM -> kernel axis (3-D identity; 2-D y is kernel z)
-    int nph[3] = {g.n[0], NDIM == 3 ? g.n[1] : (NDIM == 2 ? g.n[2] : 1), NDIM == 3 ? g.n[2] : 1};
+    // physical extents of the mesh: axis p of NDIM -> kernel axis (3-D
+    // identity; 2-D y is kernel z)
+    const int m0 = g.n[0] * g.blocks[0], m1 = g.n[1] * g.blocks[1], m2 = g.n[2] * g.blocks[2];
+    int nph[3] = {m0, NDIM == 3 ? m1 : (NDIM == 2 ? m2 : 1), NDIM == 3 ? m2 : 1};
     int P[3];
     for (int d = 0; d < 3; ++d) P[d] = nph[d] + (d < NDIM ? 4 : 0);
     const long long total = (long long)P[0] * P[1] * P[2];
@@ -1268,6 +1363,28 @@ __global__ __launch_bounds__(256) void padded_prim_kernel(Geo g, const double* _
         for (int c = 0; c < NC; ++c) Wp[c * total + q] = out[c];
     }
     if (bad) atomicOr(&ctrl->flags, FLAG_NONPHYSICAL);
+}
+
+// Mesh layout [comp][k][j][i] <-> block layout; q runs over the mesh cells.
+__global__ __launch_bounds__(256) void relayout_kernel(Geo g, int nc, double* __restrict__ mesh,
+                                                       double* __restrict__ blk, int to_blocks) {
+    const long long m0 = (long long)g.n[0] * g.blocks[0], m1 = (long long)g.n[1] * g.blocks[1];
+    const long long total = m0 * m1 * ((long long)g.n[2] * g.blocks[2]);
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(q % m0);
+        const int y = (int)((q / m0) % m1);
+        const int z = (int)(q / (m0 * m1));
+        const int b = x / g.n[0] + g.blocks[0] * (y / g.n[1] + g.blocks[1] * (z / g.n[2]));
+        const long long cell = ((long long)(z % g.n[2]) * g.n[1] + y % g.n[1]) * g.n[0] + x % g.n[0];
+        const long long bo = (long long)b * nc * g.ncells + cell;
+        for (int c = 0; c < nc; ++c) {
+            if (to_blocks)
+                blk[bo + c * g.ncells] = mesh[c * total + q];
+            else
+                mesh[c * total + q] = blk[bo + c * g.ncells];
+        }
+    }
 }
 
 template <typename R, int NT>
@@ -1327,17 +1444,20 @@ hipError_t launch_stage_t(const LaunchCtx& L, hipStream_t s) {
         StageArgs a = *L.a;
         if (a.kz == 0) {
             // automatic chunk length: one round of resident work-groups
-            // covers the mesh, so no work-group waits for a second round
+            // covers the mesh (every block of it: blocks launched one by one
+            // on several streams run at once too), so no work-group waits
+            // for a second round
             const int slots = stage_slots<NDIM, R, MODE, TX, TY>();
-            const long long cols = (long long)a.tiles_x * a.tiles_y;
+            const long long cols = (long long)a.tiles_x * a.tiles_y * geo_nblk(a.geo);
             const int n2 = a.geo.n[2];
             long long kz = slots > 0 ? (n2 * cols + slots - 1) / slots : 32;
             kz = kz < kMinAutoKz ? kMinAutoKz : (kz > kMaxAutoKz ? kMaxAutoKz : kz);
             a.kz = kz > n2 ? n2 : (int)kz;
             a.chunks_z = (n2 + a.kz - 1) / a.kz;
         }
-        const int nb = a.tiles_x * a.tiles_y * a.chunks_z;
-        hipLaunchKernelGGL((stage_kernel<NDIM, R, MODE, TX, TY>), dim3(nb), dim3(TX * TY), 0, s, a);
+        const long long nb = (long long)a.tiles_x * a.tiles_y * a.chunks_z * a.nblk;
+        if (a.nblk < 1 || nb > 0x7fffffffll) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((stage_kernel<NDIM, R, MODE, TX, TY>), dim3((unsigned)nb), dim3(TX * TY), 0, s, a);
     } else {
         if (L.nblk <= 0) return hipSuccess;
         hipLaunchKernelGGL((stage_kernel_batch<NDIM, R, MODE, TX, TY>), dim3(L.nblk), dim3(TX * TY), 0, s,
@@ -1488,11 +1608,12 @@ hipError_t launch_ctrl_batch(const MeshDesc* d, int n, hipStream_t s) {
 }
 
 hipError_t launch_dt(const Geo& g, const double* U, Ctrl* ctrl, hipStream_t s) {
-    const int nb = grid_for(g.ncells, 256, 2048);
+    const int nblk = geo_nblk(g);
+    const dim3 grid(grid_for(g.ncells, 256, (2048 + nblk - 1) / nblk), nblk);
     switch (g.ndim) {
-        case 1: hipLaunchKernelGGL(dt_kernel<1>, dim3(nb), dim3(256), 0, s, g, U, ctrl); break;
-        case 2: hipLaunchKernelGGL(dt_kernel<2>, dim3(nb), dim3(256), 0, s, g, U, ctrl); break;
-        case 3: hipLaunchKernelGGL(dt_kernel<3>, dim3(nb), dim3(256), 0, s, g, U, ctrl); break;
+        case 1: hipLaunchKernelGGL(dt_kernel<1>, grid, dim3(256), 0, s, g, U, ctrl); break;
+        case 2: hipLaunchKernelGGL(dt_kernel<2>, grid, dim3(256), 0, s, g, U, ctrl); break;
+        case 3: hipLaunchKernelGGL(dt_kernel<3>, grid, dim3(256), 0, s, g, U, ctrl); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1505,20 +1626,25 @@ hipError_t launch_ctrl(Ctrl* c, int op, double a0, double a1, double cfl, hipStr
 
 hipError_t launch_totals(const Geo& g, const double* U, double* parts, int nparts, Ctrl* ctrl,
                          hipStream_t s) {
-    const int nb = grid_for(g.ncells, 256, nparts);
+    // nparts partials shared out over the blocks (at least one each)
+    const int nblk = geo_nblk(g);
+    if (nblk > nparts) return hipErrorInvalidValue;
+    const int nb = grid_for(g.ncells, 256, nparts / nblk);
+    const dim3 grid(nb, nblk);
+    const int np = nb * nblk;
     const int NC = g.ndim + 2;
     switch (NC) {
         case 3:
-            hipLaunchKernelGGL(totals_pass1<3>, dim3(nb), dim3(256), 0, s, g.ncells, U, parts);
-            hipLaunchKernelGGL(totals_pass2<3>, dim3(1), dim3(256), 0, s, nb, parts, ctrl);
+            hipLaunchKernelGGL(totals_pass1<3>, grid, dim3(256), 0, s, g.ncells, U, parts);
+            hipLaunchKernelGGL(totals_pass2<3>, dim3(1), dim3(256), 0, s, np, parts, ctrl);
             break;
         case 4:
-            hipLaunchKernelGGL(totals_pass1<4>, dim3(nb), dim3(256), 0, s, g.ncells, U, parts);
-            hipLaunchKernelGGL(totals_pass2<4>, dim3(1), dim3(256), 0, s, nb, parts, ctrl);
+            hipLaunchKernelGGL(totals_pass1<4>, grid, dim3(256), 0, s, g.ncells, U, parts);
+            hipLaunchKernelGGL(totals_pass2<4>, dim3(1), dim3(256), 0, s, np, parts, ctrl);
             break;
         case 5:
-            hipLaunchKernelGGL(totals_pass1<5>, dim3(nb), dim3(256), 0, s, g.ncells, U, parts);
-            hipLaunchKernelGGL(totals_pass2<5>, dim3(1), dim3(256), 0, s, nb, parts, ctrl);
+            hipLaunchKernelGGL(totals_pass1<5>, grid, dim3(256), 0, s, g.ncells, U, parts);
+            hipLaunchKernelGGL(totals_pass2<5>, dim3(1), dim3(256), 0, s, np, parts, ctrl);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -1526,19 +1652,26 @@ hipError_t launch_totals(const Geo& g, const double* U, double* parts, int npart
 }
 
 hipError_t launch_prim_to_cons(const Geo& g, const double* W, double* U, hipStream_t s) {
-    const int nb = grid_for(g.ncells, 256, 4096);
+    const int nblk = geo_nblk(g);
+    const dim3 grid(grid_for(g.ncells, 256, (4096 + nblk - 1) / nblk), nblk);
     switch (g.ndim) {
-        case 1: hipLaunchKernelGGL(prim_to_cons_kernel<1>, dim3(nb), dim3(256), 0, s, g, W, U); break;
-        case 2: hipLaunchKernelGGL(prim_to_cons_kernel<2>, dim3(nb), dim3(256), 0, s, g, W, U); break;
-        case 3: hipLaunchKernelGGL(prim_to_cons_kernel<3>, dim3(nb), dim3(256), 0, s, g, W, U); break;
+        case 1: hipLaunchKernelGGL(prim_to_cons_kernel<1>, grid, dim3(256), 0, s, g, W, U); break;
+        case 2: hipLaunchKernelGGL(prim_to_cons_kernel<2>, grid, dim3(256), 0, s, g, W, U); break;
+        case 3: hipLaunchKernelGGL(prim_to_cons_kernel<3>, grid, dim3(256), 0, s, g, W, U); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+hipError_t launch_relayout(const Geo& g, double* mesh, double* blk, int to_blocks, hipStream_t s) {
+    const int nb = grid_for(g.ncells * geo_nblk(g), 256, 4096);
+    hipLaunchKernelGGL(relayout_kernel, dim3(nb), dim3(256), 0, s, g, g.ndim + 2, mesh, blk, to_blocks);
+    return hipGetLastError();
+}
+
 hipError_t launch_padded_prim(const Geo& g, int precision, const double* U, double* Wp, Ctrl* ctrl,
                               hipStream_t s) {
-    const int nb = grid_for(g.ncells * 2 + 4096, 256, 4096);
+    const int nb = grid_for(g.ncells * geo_nblk(g) * 2 + 4096, 256, 4096);
 #define PP(ND, RT) hipLaunchKernelGGL((padded_prim_kernel<ND, RT>), dim3(nb), dim3(256), 0, s, g, U, Wp, ctrl)
     if (precision == 0) {
         switch (g.ndim) {

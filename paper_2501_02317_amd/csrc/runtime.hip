@@ -14,9 +14,22 @@
 
 using namespace hydro;
 
+// Streams the blocks of a split mesh are spread over when launched one by
+// one (the hardware offers four queues per process by default).
+constexpr int kBlockStreams = 4;
+
 struct hydro_ctx {
     hydro_config cfg;
     Geo geo;
+    int nblk;         // blocks of the mesh (geo holds one block's extents)
+    // per-block launches on their own streams (Sec. 3: one stream per block)
+    bool block_streams;
+    int nbs;                       // streams created (0: none yet)
+    hipStream_t bs[kBlockStreams];
+    hipEvent_t ev_fork;
+    hipEvent_t ev_join[kBlockStreams];
+    hipEvent_t* ev_s1;             // per block: its stage 1 has finished
+    int* nbr;                      // per block: up to 6 distinct face neighbours, -1 padded
     Tile tile[2];  // stage 1 (and the rhs), stage 2
     hipStream_t stream;
     int ncomp;
@@ -39,6 +52,8 @@ namespace {
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int blocks_of(const hydro_config* c, int d) { return c->blocks[d] == 0 ? 1 : c->blocks[d]; }
 
 bool config_ok(const hydro_config* c) {
     if (!c) return false;
@@ -63,12 +78,17 @@ bool config_ok(const hydro_config* c) {
         } else if (c->n[d] != 1) {
             return false;
         }
+        // blocks of equal extents; a neighbour supplies both ghost layers of
+        // a shared face, so a split axis gives every block two cells at least
+        const int B = blocks_of(c, d);
+        if (B < 1 || (d >= c->ndim && B != 1) || c->n[d] % B != 0 || (B > 1 && c->n[d] / B < 2)) return false;
         cells *= c->n[d];
         if (cells > (1ll << 40)) return false;
     }
+    if ((long long)blocks_of(c, 0) * blocks_of(c, 1) * blocks_of(c, 2) > kMaxBlocks) return false;
     // the stage kernels address one plane of the marching axis (x-y in 3-D,
-    // a row in 1-D and 2-D) with 32-bit byte offsets
-    const long long plane = (long long)c->n[0] * (c->ndim == 3 ? c->n[1] : 1);
+    // a row in 1-D and 2-D) of a block with 32-bit byte offsets
+    const long long plane = (long long)(c->n[0] / blocks_of(c, 0)) * (c->ndim == 3 ? c->n[1] / blocks_of(c, 1) : 1);
     if (plane * 8 >= (1ll << 32)) return false;
     return true;
 }
@@ -90,14 +110,14 @@ size_t second_bytes(const hydro_config* c) {
 int stage1_mode(const hydro_config* c) { return c->integrator == HYDRO_VL2 ? MODE_VL2_PRED : MODE_STAGE1; }
 int stage2_mode(const hydro_config* c) { return c->integrator == HYDRO_VL2 ? MODE_VL2_CORR : MODE_STAGE2; }
 
-// Kernel-axis geometry (see hydro_internal.h).
+// Kernel-axis geometry of one block (see hydro_internal.h).
 Geo make_geo(const hydro_config* c) {
     Geo g;
     std::memset(&g, 0, sizeof(g));
     g.ndim = c->ndim;
     g.gamma = c->gamma;
     g.cfl = c->cfl;
-    g.ncells = ncells_of(c);
+    g.ncells = ncells_of(c) / ((long long)blocks_of(c, 0) * blocks_of(c, 1) * blocks_of(c, 2));
     double dx[3];
     for (int d = 0; d < 3; ++d) dx[d] = d < c->ndim ? (c->hi[d] - c->lo[d]) / c->n[d] : 1.0;
     int map[3];  // kernel axis -> physical axis (-1: inactive)
@@ -110,13 +130,15 @@ Geo make_geo(const hydro_config* c) {
     }
     for (int k = 0; k < 3; ++k) {
         if (map[k] >= 0) {
-            g.n[k] = c->n[map[k]];
+            g.blocks[k] = blocks_of(c, map[k]);
+            g.n[k] = c->n[map[k]] / g.blocks[k];
             g.dx[k] = dx[map[k]];
             g.inv_dx[k] = 1.0 / dx[map[k]];
             g.bc[k][0] = c->bc[map[k]][0];
             g.bc[k][1] = c->bc[map[k]][1];
         } else {
             g.n[k] = 1;
+            g.blocks[k] = 1;
             g.dx[k] = 1.0;
             g.inv_dx[k] = 1.0;
             g.bc[k][0] = g.bc[k][1] = HYDRO_BC_PERIODIC;
@@ -145,12 +167,155 @@ int usable(hydro_t h) {
     return HYDRO_OK;
 }
 
+// Arguments of a launch over every block of the mesh.
 StageArgs stage_args(hydro_t h) {
     StageArgs a;
     std::memset(&a, 0, sizeof(a));
     a.ctrl = h->ctrl;
     a.geo = h->geo;
+    a.blk0 = 0;
+    a.nblk = h->nblk;
     return a;
+}
+
+// Distinct face neighbours of every block (the blocks whose stage-1 output
+// a block's stage 2 reads, and which read the state its stage 2 overwrites).
+void block_neighbours(hydro_t h) {
+    const Geo& g = h->geo;
+    for (int b = 0; b < h->nblk; ++b) {
+        int* out = h->nbr + 6 * b;
+        int k = 0;
+        for (int q = 0; q < 6; ++q) out[q] = -1;
+        const int c[3] = {b % g.blocks[0], (b / g.blocks[0]) % g.blocks[1], b / (g.blocks[0] * g.blocks[1])};
+        for (int ax = 0; ax < 3; ++ax)
+            for (int side = 0; side < 2; ++side) {
+                int cc[3] = {c[0], c[1], c[2]};
+                int q = cc[ax] + (side ? 1 : -1);
+                if (q < 0 || q >= g.blocks[ax]) {
+                    if (g.bc[ax][side] != HYDRO_BC_PERIODIC) continue;
+                    q = (q + g.blocks[ax]) % g.blocks[ax];
+                }
+                cc[ax] = q;
+                const int nb = cc[0] + g.blocks[0] * (cc[1] + g.blocks[1] * cc[2]);
+                bool seen = nb == b;
+                for (int i = 0; i < k; ++i) seen = seen || out[i] == nb;
+                if (!seen) out[k++] = nb;
+            }
+    }
+}
+
+void block_streams_free(hydro_t h) {
+    for (int i = 0; i < h->nbs; ++i) {
+        (void)hipStreamDestroy(h->bs[i]);
+        (void)hipEventDestroy(h->ev_join[i]);
+    }
+    if (h->nbs > 0) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_s1)
+        for (int b = 0; b < h->nblk; ++b) (void)hipEventDestroy(h->ev_s1[b]);
+    delete[] h->ev_s1;
+    delete[] h->nbr;
+    h->ev_s1 = nullptr;
+    h->nbr = nullptr;
+    h->nbs = 0;
+}
+
+// Streams and events of the per-block launches, made on first use.
+hipError_t block_streams_make(hydro_t h) {
+    if (h->nbs > 0) return hipSuccess;
+    h->nbr = new (std::nothrow) int[6 * (size_t)h->nblk];
+    h->ev_s1 = new (std::nothrow) hipEvent_t[h->nblk];
+    if (!h->nbr || !h->ev_s1) {
+        delete[] h->nbr;
+        delete[] h->ev_s1;
+        h->nbr = nullptr;
+        h->ev_s1 = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    block_neighbours(h);
+    int made = 0;
+    hipError_t e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+    for (; made < h->nblk && e == hipSuccess; ++made) e = hipEventCreateWithFlags(&h->ev_s1[made], hipEventDisableTiming);
+    if (e != hipSuccess) --made;
+    const int ns = std::min(h->nblk, kBlockStreams);
+    int nstreams = 0;
+    for (; nstreams < ns && e == hipSuccess; ++nstreams) {
+        // default priority, not synchronising with the legacy default stream
+        e = hipStreamCreateWithFlags(&h->bs[nstreams], hipStreamNonBlocking);
+        if (e == hipSuccess) {
+            e = hipEventCreateWithFlags(&h->ev_join[nstreams], hipEventDisableTiming);
+            if (e != hipSuccess) (void)hipStreamDestroy(h->bs[nstreams]);
+        }
+    }
+    if (e != hipSuccess) {
+        --nstreams;
+        for (int i = 0; i < nstreams; ++i) {
+            (void)hipStreamDestroy(h->bs[i]);
+            (void)hipEventDestroy(h->ev_join[i]);
+        }
+        for (int b = 0; b < made; ++b) (void)hipEventDestroy(h->ev_s1[b]);
+        if (made >= 0) (void)hipEventDestroy(h->ev_fork);
+        delete[] h->ev_s1;
+        delete[] h->nbr;
+        h->ev_s1 = nullptr;
+        h->nbr = nullptr;
+        return e;
+    }
+    h->nbs = ns;
+    return hipSuccess;
+}
+
+// One step with each block's stages launched on its own stream: stage 1 of
+// every block, then stage 2 of a block once its face neighbours' stage 1 has
+// finished (no wait on the other blocks), then the step's finalisation on
+// the handle's stream after every block.
+hipError_t enqueue_step_streams(hydro_t h, bool device_dt, double dt) {
+    StageArgs a = stage_args(h);
+    a.use_device_dt = device_dt ? 1 : 0;
+    a.dt_host = dt;
+    a.nblk = 1;
+    hipError_t e = hipEventRecord(h->ev_fork, h->stream);
+    for (int i = 0; i < h->nbs && e == hipSuccess; ++i) e = hipStreamWaitEvent(h->bs[i], h->ev_fork, 0);
+    for (int b = 0; b < h->nblk && e == hipSuccess; ++b) {
+        hipStream_t s = h->bs[b % h->nbs];
+        a.blk0 = b;
+        a.in = h->U;
+        a.base = h->U;
+        a.out = h->U1;
+        a.want_dt = 0;
+        e = launch_stage(h->cfg.precision, stage1_mode(&h->cfg), h->tile[0], a, s);
+        if (e == hipSuccess) e = hipEventRecord(h->ev_s1[b], s);
+    }
+    for (int b = 0; b < h->nblk && e == hipSuccess; ++b) {
+        hipStream_t s = h->bs[b % h->nbs];
+        for (int q = 0; q < 6 && e == hipSuccess; ++q) {
+            const int nb = h->nbr[6 * b + q];
+            if (nb >= 0 && nb % h->nbs != b % h->nbs) e = hipStreamWaitEvent(s, h->ev_s1[nb], 0);
+        }
+        a.blk0 = b;
+        a.in = h->U1;
+        a.base = h->U;
+        a.out = h->U;
+        a.want_dt = device_dt ? 1 : 0;
+        if (e == hipSuccess) e = launch_stage(h->cfg.precision, stage2_mode(&h->cfg), h->tile[1], a, s);
+    }
+    for (int i = 0; i < h->nbs && e == hipSuccess; ++i) {
+        e = hipEventRecord(h->ev_join[i], h->bs[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->ev_join[i], 0);
+    }
+    if (e != hipSuccess) return e;
+    if (device_dt) return launch_ctrl(h->ctrl, CTRL_FINALIZE_STEP, 0.0, 0.0, h->cfg.cfl, h->stream);
+    return launch_ctrl(h->ctrl, CTRL_ADVANCE_T, dt, 0.0, h->cfg.cfl, h->stream);
+}
+
+// Mesh-layout buffer on the handle's stream for a split mesh's transfers.
+hipError_t mesh_tmp(hydro_t h, double** d) {
+    return hipMallocAsync((void**)d, (size_t)h->ncomp * h->geo.ncells * h->nblk * sizeof(double), h->stream);
+}
+
+hipError_t free_tmp(hydro_t h, double* d, hipError_t e) {
+    if (!d) return e;
+    const hipError_t e2 = hipFreeAsync(d, h->stream);
+    return e == hipSuccess ? e2 : e;
 }
 
 // Launch one stage, bracketed by events when profiling is on.
@@ -171,6 +336,7 @@ hipError_t timed_stage(hydro_t h, int mode, const StageArgs& a) {
 // primitive state) then stage 2 in place over U^n, dt either from the host or
 // from the device control block (clamped to the run limit kept there).
 hipError_t enqueue_step(hydro_t h, bool device_dt, double dt) {
+    if (h->block_streams && h->nblk > 1) return enqueue_step_streams(h, device_dt, dt);
     StageArgs a = stage_args(h);
     a.use_device_dt = device_dt ? 1 : 0;
     a.dt_host = dt;
@@ -217,6 +383,7 @@ int hydro_create(const hydro_config* cfg, void* d_workspace, size_t nbytes, void
     std::memset(h, 0, sizeof(*h));
     h->cfg = *cfg;
     h->geo = make_geo(cfg);
+    h->nblk = geo_nblk(h->geo);
     h->tile[0] = default_tile(h->geo, cfg->precision, stage1_mode(cfg));
     h->tile[1] = default_tile(h->geo, cfg->precision, stage2_mode(cfg));
     h->stream = (hipStream_t)hip_stream;
@@ -252,8 +419,17 @@ int hydro_set_state(hydro_t h, const double* U_host) {
     int rc = usable(h);
     if (rc) return rc;
     if (!U_host) return HYDRO_E_INVAL;
-    const size_t bytes = (size_t)h->ncomp * h->geo.ncells * sizeof(double);
-    hipError_t e = hipMemcpyAsync(h->U, U_host, bytes, hipMemcpyHostToDevice, h->stream);
+    const size_t bytes = (size_t)h->ncomp * h->geo.ncells * h->nblk * sizeof(double);
+    hipError_t e = hipSuccess;
+    if (h->nblk == 1) {
+        e = hipMemcpyAsync(h->U, U_host, bytes, hipMemcpyHostToDevice, h->stream);
+    } else {
+        double* tmp = nullptr;
+        e = mesh_tmp(h, &tmp);
+        if (e == hipSuccess) e = hipMemcpyAsync(tmp, U_host, bytes, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = launch_relayout(h->geo, tmp, h->U, 1, h->stream);
+        e = free_tmp(h, tmp, e);
+    }
     if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_INIT, 0.0, 0.0, h->cfg.cfl, h->stream);
     h->dt_valid = false;
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -264,9 +440,19 @@ int hydro_set_primitive(hydro_t h, const double* W_host) {
     int rc = usable(h);
     if (rc) return rc;
     if (!W_host) return HYDRO_E_INVAL;
-    const size_t bytes = (size_t)h->ncomp * h->geo.ncells * sizeof(double);
-    // staged in U itself and converted in place
-    hipError_t e = hipMemcpyAsync(h->U, W_host, bytes, hipMemcpyHostToDevice, h->stream);
+    const size_t bytes = (size_t)h->ncomp * h->geo.ncells * h->nblk * sizeof(double);
+    // staged in U itself (through a mesh-layout buffer for a split mesh) and
+    // converted in place
+    hipError_t e = hipSuccess;
+    if (h->nblk == 1) {
+        e = hipMemcpyAsync(h->U, W_host, bytes, hipMemcpyHostToDevice, h->stream);
+    } else {
+        double* tmp = nullptr;
+        e = mesh_tmp(h, &tmp);
+        if (e == hipSuccess) e = hipMemcpyAsync(tmp, W_host, bytes, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = launch_relayout(h->geo, tmp, h->U, 1, h->stream);
+        e = free_tmp(h, tmp, e);
+    }
     if (e == hipSuccess) e = launch_prim_to_cons(h->geo, h->U, h->U, h->stream);
     if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_INIT, 0.0, 0.0, h->cfg.cfl, h->stream);
     h->dt_valid = false;
@@ -278,7 +464,14 @@ int hydro_set_primitive_device(hydro_t h, const double* d_W) {
     int rc = usable(h);
     if (rc) return rc;
     if (!d_W) return HYDRO_E_INVAL;
-    hipError_t e = launch_prim_to_cons(h->geo, d_W, h->U, h->stream);
+    hipError_t e = hipSuccess;
+    if (h->nblk == 1) {
+        e = launch_prim_to_cons(h->geo, d_W, h->U, h->stream);
+    } else {
+        // only read: the relayout writes the block layout into U
+        e = launch_relayout(h->geo, const_cast<double*>(d_W), h->U, 1, h->stream);
+        if (e == hipSuccess) e = launch_prim_to_cons(h->geo, h->U, h->U, h->stream);
+    }
     if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_INIT, 0.0, 0.0, h->cfg.cfl, h->stream);
     h->dt_valid = false;
     return fail(h, e);
@@ -289,6 +482,7 @@ int hydro_get_state_device(hydro_t h, double* d_U) {
     if (rc) return rc;
     if (!d_U) return HYDRO_E_INVAL;
     const size_t bytes = (size_t)h->ncomp * h->geo.ncells * sizeof(double);
+    if (h->nblk > 1) return fail(h, launch_relayout(h->geo, d_U, h->U, 0, h->stream));
     return fail(h, hipMemcpyAsync(d_U, h->U, bytes, hipMemcpyDeviceToDevice, h->stream));
 }
 
@@ -296,8 +490,17 @@ int hydro_get_state(hydro_t h, double* U_host) {
     int rc = usable(h);
     if (rc) return rc;
     if (!U_host) return HYDRO_E_INVAL;
-    const size_t bytes = (size_t)h->ncomp * h->geo.ncells * sizeof(double);
-    hipError_t e = hipMemcpyAsync(U_host, h->U, bytes, hipMemcpyDeviceToHost, h->stream);
+    const size_t bytes = (size_t)h->ncomp * h->geo.ncells * h->nblk * sizeof(double);
+    hipError_t e = hipSuccess;
+    if (h->nblk == 1) {
+        e = hipMemcpyAsync(U_host, h->U, bytes, hipMemcpyDeviceToHost, h->stream);
+    } else {
+        double* tmp = nullptr;
+        e = mesh_tmp(h, &tmp);
+        if (e == hipSuccess) e = launch_relayout(h->geo, tmp, h->U, 0, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(U_host, tmp, bytes, hipMemcpyDeviceToHost, h->stream);
+        e = free_tmp(h, tmp, e);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     return fail(h, e);
 }
@@ -401,19 +604,25 @@ int hydro_stage_rhs(hydro_t h, double dt, double* dU_host) {
     StageArgs a = stage_args(h);
     a.dt_host = dt;
     a.in = h->U;
-    const size_t bytes = (size_t)h->ncomp * h->geo.ncells * sizeof(double);
+    const size_t bytes = (size_t)h->ncomp * h->geo.ncells * h->nblk * sizeof(double);
     // the Heun predictor buffer holds FP64 values of this size; the van Leer
-    // one may not, so a temporary buffer takes the result then
-    double* d_buf = h->U1;
+    // one may not, so a temporary buffer takes the result then; a split
+    // mesh's result is copied out through a mesh-layout buffer
+    double* d_buf = nullptr;
+    double* d_mesh = nullptr;
     hipError_t e = hipSuccess;
     if (h->cfg.integrator != HYDRO_HEUN) e = hipMallocAsync((void**)&d_buf, bytes, h->stream);
-    a.out = d_buf;
+    double* out = h->cfg.integrator != HYDRO_HEUN ? d_buf : h->U1;
+    a.out = out;
     if (e == hipSuccess) e = launch_stage(h->cfg.precision, MODE_RHS, h->tile[0], a, h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(dU_host, d_buf, bytes, hipMemcpyDeviceToHost, h->stream);
-    if (h->cfg.integrator != HYDRO_HEUN && d_buf && d_buf != h->U1) {
-        hipError_t e2 = hipFreeAsync(d_buf, h->stream);
-        if (e == hipSuccess) e = e2;
+    if (e == hipSuccess && h->nblk > 1) {
+        e = mesh_tmp(h, &d_mesh);
+        if (e == hipSuccess) e = launch_relayout(h->geo, d_mesh, out, 0, h->stream);
     }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dU_host, d_mesh ? d_mesh : out, bytes, hipMemcpyDeviceToHost, h->stream);
+    e = free_tmp(h, d_mesh, e);
+    e = free_tmp(h, d_buf, e);
     if (e != hipSuccess) return fail(h, e);
     return read_ctrl(h);
 }
@@ -619,9 +828,25 @@ int hydro_profile_read(hydro_t h, double* ms_stage1, double* ms_stage2, int64_t*
     return HYDRO_OK;
 }
 
+int hydro_set_block_streams(hydro_t h, int on) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (on != 0 && on != 1) return HYDRO_E_INVAL;
+    if (on && h->nblk > 1) {
+        // streams made while no work of this handle is in flight
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e == hipSuccess) e = block_streams_make(h);
+        if (e == hipErrorOutOfMemory) return HYDRO_E_NOMEM;
+        if (e != hipSuccess) return fail(h, e);
+    }
+    h->block_streams = on != 0;
+    return HYDRO_OK;
+}
+
 int hydro_destroy(hydro_t h) {
     if (!h) return HYDRO_E_INVAL;
     if (!h->broken) (void)hipStreamSynchronize(h->stream);
+    block_streams_free(h);
     profile_free(h);
     (void)hipHostFree(h->host_ctrl);
     delete h;
@@ -753,7 +978,8 @@ size_t batch_bytes(const BatchPlan& P) {
 bool members_ok(int n, const hydro_t* members) {
     if (n < 1 || !members) return false;
     for (int i = 0; i < n; ++i) {
-        if (!members[i] || members[i]->broken) return false;
+        // a batch member is one block (the batch is the level that splits work)
+        if (!members[i] || members[i]->broken || members[i]->nblk != 1) return false;
         if (members[i]->stream != members[0]->stream) return false;
         for (int j = 0; j < i; ++j)
             if (members[j] == members[i]) return false;

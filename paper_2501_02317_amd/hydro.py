@@ -31,7 +31,8 @@ HEUN, VL2 = 0, 1
 class Config(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 3), ("lo", C.c_double * 3),
                 ("hi", C.c_double * 3), ("gamma", C.c_double), ("cfl", C.c_double),
-                ("precision", C.c_int32), ("bc", (C.c_int32 * 2) * 3), ("integrator", C.c_int32)]
+                ("precision", C.c_int32), ("bc", (C.c_int32 * 2) * 3), ("integrator", C.c_int32),
+                ("blocks", C.c_int32 * 3)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -46,6 +47,7 @@ _SIG = {
     "hydro_set_primitive_device": (C.c_int, [_h, _vp]),
     "hydro_get_state_device": (C.c_int, [_h, _vp]),
     "hydro_state_device": (C.c_int, [_h, C.POINTER(_vp)]),
+    "hydro_set_block_streams": (C.c_int, [_h, C.c_int]),
     "hydro_cfl_dt": (C.c_int, [_h, _dp]),
     "hydro_step": (C.c_int, [_h, C.c_double]),
     "hydro_step_auto": (C.c_int, [_h, C.c_int, C.c_double]),
@@ -97,8 +99,9 @@ def strerror(status):
     return _lib.hydro_strerror(int(status)).decode()
 
 
-def make_config(n, gamma, cfl, precision=FP64, lo=None, hi=None, bc=None, integrator=HEUN):
-    """Config for the active axes' cell counts n (x first)."""
+def make_config(n, gamma, cfl, precision=FP64, lo=None, hi=None, bc=None, integrator=HEUN, blocks=None):
+    """Config for the active axes' cell counts n (x first); blocks: blocks
+    per active axis of a split mesh (None: one block)."""
     nd = len(n)
     cfg = Config()
     cfg.ndim = nd
@@ -116,6 +119,9 @@ def make_config(n, gamma, cfl, precision=FP64, lo=None, hi=None, bc=None, integr
     cfg.cfl = float(cfl)
     cfg.precision = int(precision)
     cfg.integrator = int(integrator)
+    blocks = tuple(blocks) if blocks else (1,) * nd
+    for d in range(3):
+        cfg.blocks[d] = int(blocks[d]) if d < len(blocks) else 1
     return cfg
 
 
@@ -134,11 +140,12 @@ class Hydro:
     """
 
     def __init__(self, n, gamma, cfl, precision=FP64, lo=None, hi=None, bc=None, device=None,
-                 stream=None, workspace=None, integrator=HEUN):
+                 stream=None, workspace=None, integrator=HEUN, blocks=None):
         import torch
 
-        self.cfg = make_config(n, gamma, cfl, precision, lo, hi, bc, integrator)
+        self.cfg = make_config(n, gamma, cfl, precision, lo, hi, bc, integrator, blocks)
         self.integrator = int(integrator)
+        self.blocks = tuple(self.cfg.blocks[d] for d in range(len(n)))
         self.ndim = len(n)
         self.n = tuple(int(v) for v in n)
         self.precision = int(precision)
@@ -192,13 +199,25 @@ class Hydro:
         return U
 
     def state_view(self):
-        """Zero-copy torch view of the device state (valid until the next step)."""
+        """Zero-copy torch view of the device state (valid until the next
+        step): shape (ncomp, nz, ny, nx), or for a split mesh the block
+        layout (nblocks, ncomp, bz, by, bx)."""
         import torch
         p = _vp()
         _check(_lib.hydro_state_device(self._h, C.byref(p)), "hydro_state_device")
         off = p.value - self.workspace.data_ptr()
         n = int(np.prod(self.shape))
-        return self.workspace[off: off + 8 * n].view(torch.float64).view(self.shape)
+        v = self.workspace[off: off + 8 * n].view(torch.float64)
+        nb = int(np.prod(self.blocks))
+        if nb == 1:
+            return v.view(self.shape)
+        b = list(self.blocks) + [1] * (3 - len(self.blocks))
+        return v.view(nb, self.ncomp, self.shape[1] // b[2], self.shape[2] // b[1], self.shape[3] // b[0])
+
+    def set_block_streams(self, on):
+        """Launch each block's stages on their own streams (True) or one
+        launch per stage over every block (False, the default)."""
+        _check(_lib.hydro_set_block_streams(self._h, 1 if on else 0), "hydro_set_block_streams")
 
     # ---- stepping
     def cfl_dt(self):

@@ -96,3 +96,29 @@ def test_tile_candidates(H):
     assert H.tile_candidates(1, (256,)) == [(64, 1, 1), (128, 1, 1), (256, 1, 1)]
     bad = H.make_config((0, 4), 1.4, 0.4)
     assert H._lib.hydro_tile_candidates(C.byref(bad), None, 0) == H.E_INVAL
+
+
+def test_block_split_validation(H):
+    """A split mesh: equal blocks dividing the mesh, two cells per block on a
+    split axis, one block on inactive axes, at most 1024 blocks; the
+    workspace is that of the unsplit mesh."""
+    base = H.workspace_bytes(H.make_config((64, 32, 16), 1.4, 0.3))
+    for blocks in [(2, 2, 2), (4, 1, 8), (32, 16, 2), (1, 1, 1), (0, 0, 0)]:
+        assert H.workspace_bytes(H.make_config((64, 32, 16), 1.4, 0.3, blocks=blocks)) == base
+    bad = [
+        ((64, 32, 16), (3, 1, 1)),     # does not divide
+        ((64, 32, 16), (64, 1, 1)),    # one cell per block
+        ((64, 32, 16), (32, 32, 2)),   # 2048 blocks
+        ((64, 48), (2, 2, 2)),         # inactive axis split
+        ((64,), (-1,)),                # negative
+    ]
+    for n, blocks in bad:
+        cfg = H.make_config(n, 1.4, 0.3, blocks=blocks)
+        if len(blocks) > len(n):
+            for d in range(3):
+                cfg.blocks[d] = blocks[d]
+        assert H.workspace_bytes(cfg) == 0, (n, blocks)
+    # a reflecting axis split into blocks of two cells is valid
+    cfg = H.make_config((8, 4), 1.4, 0.3, bc=((3, 3), (2, 1)), blocks=(4, 2))
+    assert H.workspace_bytes(cfg) > 0
+    assert H._lib.hydro_set_block_streams(None, 1) == H.E_INVAL

@@ -1,0 +1,209 @@
+"""A mesh split into blocks on one GPU: each stage reads a block's ghosts
+straight from the neighbouring blocks (c-boundaries), the faces of the
+whole mesh follow the boundary rules (Sec. 3.1.1), and the blocks' stages
+run either in one launch or one block at a time on several streams.
+
+The split mesh advances bit for bit like the unsplit one (a c-boundary
+copies exact values and every cell's arithmetic is the same), and matches
+the oracle's multi-block run (ghost exchange between blocks) to the
+precision's tolerance."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2501_02317_amd import workloads as wl
+from gpu_util import bitwise_equal, oracle_mesh, rel_l1, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2501_02317_amd import hydro
+    return hydro
+
+
+def mesh(H, c, precision, integrator=0, blocks=None, streams=False):
+    h = H.Hydro(c.n, c.gamma, c.cfl, precision=precision, lo=c.lo, hi=c.hi, bc=c.bc,
+                integrator=integrator, blocks=blocks)
+    if streams:
+        h.set_block_streams(True)
+    h.set_primitive(c.W)
+    return h
+
+
+def run(H, c, precision, integrator, blocks, steps, streams=False):
+    h = mesh(H, c, precision, integrator, blocks, streams)
+    h.step_auto(steps)
+    out = h.get_state(), h.time(), h.steps_done()
+    h.close()
+    return out
+
+
+CASES_3D = [((2, 2, 2), False), ((3, 2, 4), False), ((3, 2, 4), True), ((1, 5, 1), True)]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("integrator", [0, 1])
+def test_3d_periodic_split_bitwise_and_oracle(H, precision, integrator):
+    c = wl.turbulence_3d(n=(48, 40, 32), mach=1.2, seed=41)
+    steps = 5
+    say("blocks 3d unsplit", precision, integrator)
+    U1, t1, s1 = run(H, c, precision, integrator, None, steps)
+    m = oracle_mesh(c, integrator)
+    U_o, t_o, s_o, _ = O.run_blocks(m, (2, 2, 2), O.prim_to_cons(m, c.W), c.cfl, max_steps=steps)
+    err = rel_l1(U1, U_o)
+    assert s1 == s_o == steps and np.all(err <= TOL[precision]), err
+    assert abs(t1 - t_o) <= (1e-14 if precision == 0 else 1e-6) * t_o
+    for blocks, streams in CASES_3D:
+        say("blocks 3d", blocks, "streams" if streams else "fused", precision, integrator)
+        U, t, s = run(H, c, precision, integrator, blocks, steps, streams)
+        assert s == steps and t == t1
+        assert bitwise_equal(U, U1), (blocks, streams)
+
+
+@pytest.mark.parametrize("integrator", [0, 1])
+def test_2d_reflecting_box_split(H, integrator):
+    """The diagonal implosion in a reflecting box: blocks on the walls use
+    the reflecting rule, inner faces read the neighbour."""
+    c = wl.implosion_2d(N=96)
+    steps = 20
+    m = oracle_mesh(c, integrator)
+    U_o, *_ = O.run_blocks(m, (4, 3), O.prim_to_cons(m, c.W), c.cfl, max_steps=steps)
+    for precision in (0, 1):
+        say("blocks 2d unsplit", precision, integrator)
+        U1, t1, _ = run(H, c, precision, integrator, None, steps)
+        assert np.all(rel_l1(U1, U_o) <= (1e-12 if precision == 0 else 1e-4))
+        for blocks, streams in [((4, 3), False), ((2, 8), True), ((48, 1), False), ((3, 48), True)]:
+            say("blocks 2d", blocks, streams, precision, integrator)
+            U, t, _ = run(H, c, precision, integrator, blocks, steps, streams)
+            assert t == t1 and bitwise_equal(U, U1), (blocks, streams)
+
+
+def test_1d_split(H):
+    c = wl.sod_1d(256)
+    for integrator in (0, 1):
+        for precision in (0, 1):
+            say("blocks 1d", precision, integrator)
+            U1, t1, _ = run(H, c, precision, integrator, None, 30)
+            for blocks, streams in [((2,), False), ((16,), True), ((128,), False)]:
+                U, t, _ = run(H, c, precision, integrator, blocks, 30, streams)
+                assert t == t1 and bitwise_equal(U, U1), (blocks, streams)
+
+
+def test_mixed_boundaries_many_small_blocks(H):
+    """Every boundary rule on some face, blocks of two cells, 240 blocks."""
+    c = wl.turbulence_3d(n=(16, 12, 20), mach=0.8, seed=42)
+    bc = ((H.BC_REFLECT, H.BC_OUTFLOW), (H.BC_FREE, H.BC_REFLECT), (H.BC_PERIODIC, H.BC_PERIODIC))
+    c.bc = bc
+    m = oracle_mesh(c, 0)
+    steps = 4
+    U_o, *_ = O.run_blocks(m, (8, 6, 5), O.prim_to_cons(m, c.W), c.cfl, max_steps=steps)
+    U_u, *_ = O.run(m, O.prim_to_cons(m, c.W), c.cfl, max_steps=steps)
+    assert np.array_equal(U_o, U_u)
+    say("blocks mixed bc unsplit")
+    U1, t1, _ = run(H, c, 0, 0, None, steps)
+    assert np.all(rel_l1(U1, U_o) <= 1e-12)
+    for blocks, streams in [((8, 6, 5), False), ((8, 6, 5), True), ((2, 1, 10), True)]:
+        say("blocks mixed bc", blocks, streams)
+        U, t, _ = run(H, c, 0, 0, blocks, steps, streams)
+        assert t == t1 and bitwise_equal(U, U1), (blocks, streams)
+
+
+def test_transfers_and_views(H):
+    """Host and device transfers use the mesh layout; the device view is
+    the block layout; the diagnostics match the unsplit mesh."""
+    import torch
+    c = wl.turbulence_3d(n=(24, 16, 20), mach=1.0, seed=43)
+    blocks = (3, 2, 4)
+    say("blocks transfers")
+    a = mesh(H, c, 0)
+    b = mesh(H, c, 0, blocks=blocks)
+    Ua, Ub = a.get_state(), b.get_state()
+    assert bitwise_equal(Ua, Ub)
+    # block layout of the device view
+    v = b.state_view().cpu().numpy()
+    nc, nz, ny, nx = Ua.shape
+    bz, by, bx = nz // 4, ny // 2, nx // 3
+    ref = Ua.reshape(nc, 4, bz, 2, by, 3, bx).transpose(1, 3, 5, 0, 2, 4, 6).reshape(24, nc, bz, by, bx)
+    assert bitwise_equal(v, ref)
+    # device copies in and out
+    out = torch.empty(Ua.shape, dtype=torch.float64, device=b.device)
+    b.get_state_device(out)
+    torch.cuda.synchronize()
+    assert bitwise_equal(out.cpu().numpy(), Ua)
+    Wd = torch.from_numpy(np.ascontiguousarray(c.W)).to(b.device)
+    b.set_state(np.zeros_like(Ua))
+    b.set_primitive_device(Wd)
+    torch.cuda.synchronize()
+    assert bitwise_equal(b.get_state(), Ua)
+    b.set_state(Ua)
+    assert bitwise_equal(b.get_state(), Ua)
+    # diagnostics
+    assert a.cfl_dt() == b.cfl_dt()
+    assert bitwise_equal(a.stage_rhs(1e-3), b.stage_rhs(1e-3))
+    assert bitwise_equal(a.padded_primitive(), b.padded_primitive())
+    Ta, Tb = a.totals(), b.totals()
+    assert np.allclose(Ta, Tb, rtol=1e-14, atol=1e-14 * np.abs(Ta).max())
+    for h in (a, b):
+        h.close()
+
+
+def test_vl2_rhs_and_padded_split(H):
+    c = wl.implosion_2d(N=64)
+    say("blocks vl2 diagnostics")
+    a = mesh(H, c, 1, 1)
+    b = mesh(H, c, 1, 1, blocks=(4, 2))
+    assert bitwise_equal(a.stage_rhs(1e-3), b.stage_rhs(1e-3))
+    assert bitwise_equal(a.padded_primitive(), b.padded_primitive())
+    for h in (a, b):
+        h.close()
+
+
+def test_tiles_and_autotune_on_split_mesh(H, tmp_path):
+    c = wl.turbulence_3d(n=(64, 48, 40), mach=1.0, seed=44)
+    blocks = (2, 3, 2)
+    say("blocks tiles")
+    U1, _, _ = run(H, c, 1, 0, None, 6)
+    for t in H.tile_candidates(3, (32, 16, 20), 1)[::3]:
+        h = mesh(H, c, 1, blocks=blocks)
+        h.set_tile(*t)
+        h.step_auto(6)
+        assert bitwise_equal(h.get_state(), U1), t
+        h.close()
+    # the autotuner's steps are steps of the run
+    h = mesh(H, c, 1, blocks=blocks)
+    tiles, k = h.autotune(1)
+    assert k == len(H.tile_candidates(3, (32, 16, 20), 1)) + 1
+    Uk, _, _ = run(H, c, 1, 0, None, k)
+    assert h.steps_done() == k and bitwise_equal(h.get_state(), Uk)
+    h.close()
+
+
+def test_run_limit_and_streams_toggle(H):
+    c = wl.turbulence_3d(n=(32, 32, 32), mach=1.0, seed=45)
+    say("blocks run limit")
+    ref = mesh(H, c, 0)
+    ref.step_auto(100, t_end=0.05)
+    h = mesh(H, c, 0, blocks=(2, 2, 2))
+    h.step_auto(3)
+    h.set_block_streams(True)
+    h.step_auto(3)
+    h.set_block_streams(False)
+    h.step_auto(100, t_end=0.05)
+    assert h.time() == ref.time() == 0.05 and h.steps_done() == ref.steps_done() > 6
+    assert bitwise_equal(h.get_state(), ref.get_state())
+    for x in (h, ref):
+        x.close()
+
+
+def test_batch_rejects_split_members(H):
+    c = wl.turbulence_3d(n=(16, 16, 16), mach=1.0, seed=46)
+    h = mesh(H, c, 0, blocks=(2, 1, 1))
+    with pytest.raises(H.HydroError):
+        H.Batch([h])
+    h.close()

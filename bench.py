@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 2-D workload")
     ap.add_argument("--no-vl2", action="store_true", help="skip the van Leer integrator leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--no-blocks", action="store_true", help="skip the multi-block leg")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--serve-calib", type=int, default=300,
@@ -87,10 +88,11 @@ def bytes_per_update(ndim, precision=0, integrator=0):
     return sum(stage_bytes(ndim, precision, integrator))
 
 
-def run_precision(H, case, precision, steps, warmup, tile=None, tune=True, integrator=0):
+def run_precision(H, case, precision, steps, warmup, tile=None, tune=True, integrator=0, blocks=None,
+                  streams=False):
     import torch
     h = H.Hydro(case.n, case.gamma, case.cfl, precision=precision, lo=case.lo, hi=case.hi, bc=case.bc,
-                integrator=integrator)
+                integrator=integrator, blocks=blocks)
     h.set_primitive(case.W)
     if tile or not tune:
         if tile:
@@ -98,6 +100,8 @@ def run_precision(H, case, precision, steps, warmup, tile=None, tune=True, integ
         tiles = h.get_tile()
     else:
         tiles, _ = h.autotune(3)   # tuning steps are warm-up steps of the run
+    if streams:
+        h.set_block_streams(True)  # per-block launches (stage timing records none)
     h.step_auto(warmup)
     torch.cuda.synchronize()
     h.set_primitive(case.W)        # timed run starts from the seeded state
@@ -124,11 +128,11 @@ def run_precision(H, case, precision, steps, warmup, tile=None, tune=True, integ
     b1, b2 = stage_bytes(case.ndim, precision, integrator)
     alg_bytes = (b1 * n1 + b2 * n2) * cells                  # stage-1 and stage-2 launches
     kern_ms = ms1 + ms2
-    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
     return {
         "rate": rate, "ms_per_step": ms / steps, "wall_s": wall, "t_sim": t_sim,
         "stage_ms": [ms1 / max(n1, 1), ms2 / max(n2, 1)], "launches": [n1, n2],
-        "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS, "totals": T.tolist(),
+        "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS if achieved else None, "totals": T.tolist(),
         "step_frac": rate * bytes_per_update(case.ndim, precision, integrator) / 1e9 / HBM_PEAK_GBS,
         "tiles": [list(t) for t in tiles],
     }
@@ -328,6 +332,21 @@ def main():
             print(f"[bench] vl2 {name}: {r['rate']:.3e} cell-updates/s, {r['ms_per_step']:.3f} ms/step, "
                   f"stage kernels {r['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
         out["vl2"] = vl
+    if not args.no_blocks and "mixed" in res:
+        # the same mesh split into blocks that read their ghosts from each
+        # other: one launch per stage over every block, or each block's
+        # stages on their own streams
+        bl = {"unsplit": res["mixed"]["rate"]}
+        for blocks in ((2, 2, 2), (4, 4, 4)):
+            key = "x".join(map(str, blocks))
+            bl[key] = {}
+            for mode in ("fused", "streams"):
+                r = run_precision(H, case, H.MIXED, args.steps, args.warmup, None, not args.no_tune,
+                                  blocks=blocks, streams=mode == "streams")
+                bl[key][mode] = {"value": r["rate"], "ms_per_step": r["ms_per_step"], "tiles": r["tiles"]}
+                print(f"[bench] blocks {key} {mode}: {r['rate']:.3e} cell-updates/s, "
+                      f"{r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        out["blocks"] = {"precision": "mixed", "integrator": "heun", **bl}
     if not args.no_batch:
         print("[bench] batched 2-D workload ...", file=sys.stderr, flush=True)
         out["batch"] = run_batch(H, wl, args.batch_count, 300, H.MIXED)

@@ -78,6 +78,7 @@ struct StageArgs {
     int want_dt;         // stage 2: accumulate the next CFL candidate
     int tiles_x, tiles_y, chunks_z, kz;  // per block
     int blk0, nblk;      // the launch covers blocks blk0 .. blk0 + nblk - 1
+    int conc;            // blocks whose stage work runs at once (automatic chunk length)
 };
 
 // One member of a batch: the stage kernels build StageArgs from it.
@@ -132,6 +133,6 @@ constexpr int kTotalsParts = 1024;
 // Blocks of one mesh: each needs one totals partial at least.
 constexpr int kMaxBlocks = kTotalsParts;
 
-inline int geo_nblk(const Geo& g) { return g.blocks[0] * g.blocks[1] * g.blocks[2]; }
+__host__ __device__ inline int geo_nblk(const Geo& g) { return g.blocks[0] * g.blocks[1] * g.blocks[2]; }
 
 }  // namespace hydro

@@ -1085,7 +1085,9 @@ __global__ __launch_bounds__(TX * TY)
 __attribute__((amdgpu_waves_per_eu(StageOccupancy<NDIM, R, MODE>::kWaves, StageOccupancy<NDIM, R, MODE>::kWavesMax)))
 void stage_kernel(StageArgs a) {
     if (a.use_device_dt && a.ctrl->done) return;  // uniform over the grid
-    // work-group -> (block, work-group within the block)
+    // work-group -> (block, work-group within the block), block after block:
+    // each XCD's contiguous range of work-groups covers whole blocks (measured
+    // faster than taking them in the order of the whole mesh's tile grid)
     int wg = xcd_remap(blockIdx.x, gridDim.x);
     int blk = a.blk0;
     if (a.nblk > 1) {
@@ -1444,11 +1446,11 @@ hipError_t launch_stage_t(const LaunchCtx& L, hipStream_t s) {
         StageArgs a = *L.a;
         if (a.kz == 0) {
             // automatic chunk length: one round of resident work-groups
-            // covers the mesh (every block of it: blocks launched one by one
-            // on several streams run at once too), so no work-group waits
-            // for a second round
+            // covers the blocks whose work runs at once (this launch's, or
+            // those of the launches on the other streams as well), so no
+            // work-group waits for a second round
             const int slots = stage_slots<NDIM, R, MODE, TX, TY>();
-            const long long cols = (long long)a.tiles_x * a.tiles_y * geo_nblk(a.geo);
+            const long long cols = (long long)a.tiles_x * a.tiles_y * (a.conc > a.nblk ? a.conc : a.nblk);
             const int n2 = a.geo.n[2];
             long long kz = slots > 0 ? (n2 * cols + slots - 1) / slots : 32;
             kz = kz < kMinAutoKz ? kMinAutoKz : (kz > kMaxAutoKz ? kMaxAutoKz : kz);

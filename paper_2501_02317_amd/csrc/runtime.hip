@@ -175,6 +175,7 @@ StageArgs stage_args(hydro_t h) {
     a.geo = h->geo;
     a.blk0 = 0;
     a.nblk = h->nblk;
+    a.conc = h->nblk;
     return a;
 }
 
@@ -273,6 +274,7 @@ hipError_t enqueue_step_streams(hydro_t h, bool device_dt, double dt) {
     a.use_device_dt = device_dt ? 1 : 0;
     a.dt_host = dt;
     a.nblk = 1;
+    a.conc = h->nbs;  // one block per stream at a time
     hipError_t e = hipEventRecord(h->ev_fork, h->stream);
     for (int i = 0; i < h->nbs && e == hipSuccess; ++i) e = hipStreamWaitEvent(h->bs[i], h->ev_fork, 0);
     for (int b = 0; b < h->nblk && e == hipSuccess; ++b) {

@@ -110,6 +110,12 @@ def lib():
                                   C.POINTER(C.c_int), _dp]),
             "orc_run_blocks": (C.c_int, [mp, C.POINTER(C.c_int32), _dp, C.c_double, C.c_int, C.c_double,
                                          _dp, C.POINTER(C.c_int), _dp]),
+            "orc_smr_leaves": (C.c_int, [mp, C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int32), C.c_int]),
+            "orc_smr_ghosts": (C.c_int, [mp, C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int32), _dp, _dp]),
+            "orc_run_smr": (C.c_int, [mp, C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int32), _dp, C.c_double,
+                                      C.c_int, C.c_double, _dp, C.POINTER(C.c_int), _dp]),
+            "orc_smr_totals": (None, [mp, C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int32), _dp, _dp]),
             "orc_totals": (None, [mp, _dp, _dp]),
             "orc_rhs_cells": (C.c_int, [mp, _dp, C.c_double, C.c_int, _i64p, _dp]),
             "orc_step_cells": (C.c_int, [mp, _dp, C.c_double, C.c_int, _i64p, _dp]),
@@ -259,6 +265,100 @@ def run_blocks(mesh, blocks, U, cfl, max_steps=0, t_end=0.0, t0=0.0):
                               C.byref(t), C.byref(steps), _p(dts) if max_steps > 0 else C.cast(None, _dp))
     _check(rc, "run_blocks")
     return U, t.value, steps.value, dts[: steps.value] if max_steps > 0 else None
+
+
+def _blocks3(blocks):
+    return (C.c_int32 * 3)(*(list(blocks) + [1] * (3 - len(blocks))))
+
+
+def _refined(refined):
+    r = np.ascontiguousarray(list(refined) if len(refined) else [0], dtype=np.int32)
+    return len(refined), r.ctypes.data_as(C.POINTER(C.c_int32)), r
+
+
+class SMR:
+    """Two-level static refinement of a block mesh: the root blocks listed
+    in refined are split into 2^ndim blocks of half the size.  Fields are
+    block-layout arrays of shape (nleaf, ncomp, bz, by, bx)."""
+
+    def __init__(self, mesh, blocks, refined):
+        self.mesh = mesh
+        self.blocks = tuple(blocks) + (1,) * (3 - len(blocks))
+        self.refined = [int(r) for r in refined]
+        B = _blocks3(self.blocks)
+        nr, rp, keep = _refined(self.refined)
+        cap = 1 << 16
+        out = np.zeros((cap, 4), dtype=np.int32)
+        n = lib().orc_smr_leaves(C.byref(mesh.to_c()), B, nr, rp, out.ctypes.data_as(C.POINTER(C.c_int32)), cap)
+        if n < 0:
+            raise OracleError("smr: invalid refinement")
+        self.leaves = out[:n].copy()
+        nn = list(mesh.n) + [1] * (3 - mesh.ndim)
+        self.bn = tuple(nn[d] // self.blocks[d] for d in range(3))
+        self.shape = (n, mesh.ncomp, self.bn[2], self.bn[1], self.bn[0])
+
+    def _args(self):
+        nr, rp, keep = _refined(self.refined)
+        self._keep = keep
+        return C.byref(self.mesh.to_c()), _blocks3(self.blocks), nr, rp
+
+    def centres(self):
+        """Cell-centre coordinates per leaf: a list of ndim arrays of shape
+        (nleaf, bz, by, bx)."""
+        m = self.mesh
+        out = []
+        for d in range(m.ndim):
+            dx0 = (m.hi[d] - m.lo[d]) / m.n[d]
+            lev = self.leaves[:, 0].astype(np.float64)
+            dxl = dx0 / 2.0 ** lev
+            org = m.lo[d] + self.leaves[:, 1 + d] * self.bn[d] * dxl
+            idx = np.arange(self.bn[d], dtype=np.float64)
+            shp = [1, 1, 1]
+            shp[2 - d] = self.bn[d]
+            x = org[:, None, None, None] + (idx.reshape(shp)[None] + 0.5) * dxl[:, None, None, None]
+            out.append(np.broadcast_to(x, (len(self.leaves), self.bn[2], self.bn[1], self.bn[0])).copy())
+        return out
+
+    def ghosts(self, W):
+        W = np.ascontiguousarray(W, dtype=np.float64).reshape(self.shape)
+        pad = [s + (4 if (2 - a) < self.mesh.ndim else 0) for a, s in enumerate(self.shape[2:])]
+        out = np.zeros((self.shape[0], self.shape[1], *pad))
+        rc = lib().orc_smr_ghosts(*self._args(), _p(W), _p(out))
+        _check(rc, "smr_ghosts")
+        return out
+
+    def run(self, U, cfl, max_steps=0, t_end=0.0, t0=0.0):
+        U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.shape).copy()
+        t = C.c_double(t0)
+        steps = C.c_int(0)
+        cap = max_steps if max_steps > 0 else 1_000_000
+        dts = np.zeros(cap)
+        rc = lib().orc_run_smr(*self._args(), _p(U), float(cfl), int(max_steps), float(t_end), C.byref(t),
+                               C.byref(steps), _p(dts) if max_steps > 0 else C.cast(None, _dp))
+        _check(rc, "run_smr")
+        return U, t.value, steps.value, dts[: steps.value] if max_steps > 0 else None
+
+    def totals(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.shape)
+        T = np.empty(self.mesh.ncomp)
+        lib().orc_smr_totals(*self._args(), _p(U), _p(T))
+        return T
+
+    def _pointwise(self, F, fn):
+        # the conversions are cell by cell: apply them to all cells as one row
+        F = np.ascontiguousarray(F, dtype=np.float64).reshape(self.shape)
+        nc, n = self.mesh.ncomp, self.shape[0]
+        cells = n * int(np.prod(self.bn))
+        nd = self.mesh.ndim
+        row = Mesh((cells,) + (1,) * (nd - 1), self.mesh.gamma, bc=((BC_FREE, BC_FREE),) * nd)
+        G = fn(row, np.moveaxis(F, 1, 0).reshape(row.shape))
+        return np.moveaxis(G.reshape(nc, n, *self.shape[2:]), 0, 1).copy()
+
+    def prim_to_cons(self, W):
+        return self._pointwise(W, prim_to_cons)
+
+    def cons_to_prim(self, U):
+        return self._pointwise(U, cons_to_prim)
 
 
 def totals(mesh, U):

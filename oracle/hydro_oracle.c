@@ -432,34 +432,43 @@ int orc_rhs_prim(const orc_mesh* m, const double* W, double dt, int order, doubl
     return rc;
 }
 
-/* Stage right-hand side from the padded primitive array Wp (interior filled;
- * the ghosts of sides not marked in cside are filled here by the boundary
- * rules), with piecewise-constant (order 1) or PLM (order 2) face states.
- * dx: cell widths (NULL: those of m). */
-static int rhs_core(const orc_mesh* m, const double* dx, const int (*cside)[2], double* Wp, double dt,
-                    int order, double* dU) {
+/* Face fluxes of one block from its padded primitive array Wp (ghosts
+ * filled): axis d has n_d + 1 faces per line, face f separating cells f-1 and
+ * f, stored [comp][face] with extents fext[d].  Piecewise-constant (order 1)
+ * or PLM (order 2) face states. */
+typedef struct {
+    double* F[3];
+    int64_t fext[3][3];
+    int64_t nf[3];
+} faceflux;
+
+static void faceflux_free(faceflux* ff) {
+    for (int d = 0; d < 3; ++d) {
+        free(ff->F[d]);
+        ff->F[d] = NULL;
+    }
+}
+
+static int block_fluxes(const orc_mesh* m, const double* Wp, int order, faceflux* ff) {
     int ndim = m->ndim, nc = ndim + 2;
     double g = m->gamma;
-    int64_t N = ncells(m);
-    int n0 = m->n[0], n1 = m->n[1], n2 = m->n[2];
     padgeo pg = pad_geometry(m);
-    fill_ghosts_masked(m, Wp, cside);
-
-    /* face fluxes: axis d has n_d + 1 faces per line; face f separates cells f-1 and f */
-    double* Fd[3] = {NULL, NULL, NULL};
-    int64_t fext[3][3];
+    for (int d = 0; d < 3; ++d) ff->F[d] = NULL;
     for (int d = 0; d < ndim; ++d) {
-        for (int e = 0; e < 3; ++e) fext[d][e] = m->n[e] + (e == d ? 1 : 0);
-        int64_t nf = fext[d][0] * fext[d][1] * fext[d][2];
-        Fd[d] = (double*)malloc((size_t)(nc * nf) * sizeof(double));
-        if (!Fd[d]) {
-            for (int e = 0; e < d; ++e) free(Fd[e]);
+        for (int e = 0; e < 3; ++e) ff->fext[d][e] = m->n[e] + (e == d ? 1 : 0);
+        int64_t nf = ff->fext[d][0] * ff->fext[d][1] * ff->fext[d][2];
+        ff->nf[d] = nf;
+        ff->F[d] = (double*)malloc((size_t)(nc * nf) * sizeof(double));
+        if (!ff->F[d]) {
+            faceflux_free(ff);
             return -1;
         }
+        double* Fd = ff->F[d];
+        const int64_t* fext = ff->fext[d];
 #pragma omp parallel for schedule(static)
-        for (int fk = 0; fk < (int)fext[d][2]; ++fk)
-            for (int fj = 0; fj < (int)fext[d][1]; ++fj)
-                for (int fi = 0; fi < (int)fext[d][0]; ++fi) {
+        for (int fk = 0; fk < (int)fext[2]; ++fk)
+            for (int fj = 0; fj < (int)fext[1]; ++fj)
+                for (int fi = 0; fi < (int)fext[0]; ++fi) {
                     int f[3] = {fi, fj, fk};
                     double w4[4][MAXC];
                     for (int s = 0; s < 4; ++s) {
@@ -470,12 +479,18 @@ static int rhs_core(const orc_mesh* m, const double* dx, const int (*cside)[2], 
                     }
                     double F[MAXC];
                     face_flux(ndim, g, d, order, w4, F);
-                    int64_t fo = ((int64_t)fk * fext[d][1] + fj) * fext[d][0] + fi;
-                    for (int c = 0; c < nc; ++c) Fd[d][c * (nf) + fo] = F[c];
+                    int64_t fo = ((int64_t)fk * fext[1] + fj) * fext[0] + fi;
+                    for (int c = 0; c < nc; ++c) Fd[c * nf + fo] = F[c];
                 }
     }
+    return 0;
+}
 
-    /* dU_i = sum over d (in order) of dt/dx_d (F_{d,i-1/2} - F_{d,i+1/2}) */
+/* dU_i = sum over d (in order) of dt/dx_d (F_{d,i-1/2} - F_{d,i+1/2}) */
+static void flux_update(const orc_mesh* m, const double* dx, const faceflux* ff, double dt, double* dU) {
+    int ndim = m->ndim, nc = ndim + 2;
+    int64_t N = ncells(m);
+    int n0 = m->n[0], n1 = m->n[1], n2 = m->n[2];
     double lam[3];
     for (int d = 0; d < ndim; ++d) lam[d] = dt / (dx ? dx[d] : cell_width(m, d));
 #pragma omp parallel for schedule(static)
@@ -487,18 +502,31 @@ static int rhs_core(const orc_mesh* m, const double* dx, const int (*cside)[2], 
                 for (int c = 0; c < nc; ++c) {
                     double acc = 0.0;
                     for (int d = 0; d < ndim; ++d) {
-                        int64_t nf = fext[d][0] * fext[d][1] * fext[d][2];
+                        const int64_t* fext = ff->fext[d];
+                        int64_t nf = ff->nf[d];
                         int lo3[3] = {c3[0], c3[1], c3[2]};
                         int hi3[3] = {c3[0], c3[1], c3[2]};
                         hi3[d] += 1;
-                        int64_t flo = ((int64_t)lo3[2] * fext[d][1] + lo3[1]) * fext[d][0] + lo3[0];
-                        int64_t fhi = ((int64_t)hi3[2] * fext[d][1] + hi3[1]) * fext[d][0] + hi3[0];
-                        acc = acc + lam[d] * (Fd[d][c * nf + flo] - Fd[d][c * nf + fhi]);
+                        int64_t flo = ((int64_t)lo3[2] * fext[1] + lo3[1]) * fext[0] + lo3[0];
+                        int64_t fhi = ((int64_t)hi3[2] * fext[1] + hi3[1]) * fext[0] + hi3[0];
+                        acc = acc + lam[d] * (ff->F[d][c * nf + flo] - ff->F[d][c * nf + fhi]);
                     }
                     dU[c * N + cell] = acc;
                 }
             }
-    for (int d = 0; d < ndim; ++d) free(Fd[d]);
+}
+
+/* Stage right-hand side from the padded primitive array Wp (interior filled;
+ * the ghosts of sides not marked in cside are filled here by the boundary
+ * rules), with piecewise-constant (order 1) or PLM (order 2) face states.
+ * dx: cell widths (NULL: those of m). */
+static int rhs_core(const orc_mesh* m, const double* dx, const int (*cside)[2], double* Wp, double dt,
+                    int order, double* dU) {
+    fill_ghosts_masked(m, Wp, cside);
+    faceflux ff;
+    if (block_fluxes(m, Wp, order, &ff)) return -1;
+    flux_update(m, dx, &ff, dt, dU);
+    faceflux_free(&ff);
     return 0;
 }
 
@@ -865,6 +893,503 @@ int orc_run_blocks(const orc_mesh* m, const int32_t blocks[3], double* U, double
     free(Ub);
     if (steps_done) *steps_done = s;
     return rc;
+}
+
+/* ------------------------------------------------- static mesh refinement */
+
+/* Two-level static refinement of the block mesh above (the 2^d-tree of
+ * Sec. 2.3 one level deep): each listed root block is replaced by 2^d blocks
+ * of half its size, every block keeping the same number of cells.  The
+ * leaves are ordered level 0 first (ascending root index, x fastest), then
+ * level 1 (ascending index on the level-1 block grid of 2 B blocks per axis).
+ *
+ * A stage follows the cross-level sequence of Sec. 3 (c-boundaries):
+ *   (a) ghosts that involve no prolongation: same-level neighbours, the
+ *       p-boundary rules at the mesh faces, and on a coarse block facing
+ *       finer ones, the volume average (restriction) of the fine cells that
+ *       cover each ghost;
+ *   (b) prolongation on the coarse side, now that its ghost zone is
+ *       complete: each fine ghost is its coarse cell's value plus, per axis,
+ *       a quarter of the minmod-limited (eq. minmod) difference, signed by
+ *       the side of the coarse centre the fine centre lies on;
+ *   (c) fluxes on every block;
+ *   (d) on a coarse face shared with finer blocks the flux is the average of
+ *       the fine fluxes through it, so the mass, momentum and energy that
+ *       leave one level enter the other.
+ * All of this on primitive variables, as the paper's figure of the interface
+ * shows; averages are taken pairwise along x, then y, then z. */
+enum { NB_PHYS = 0, NB_SAME = 1, NB_COARSE = 2, NB_FINE = 3 };
+
+typedef struct {
+    orc_mesh mb;        /* one block: its extents, the mesh's boundary codes */
+    int B[3];           /* root blocks per axis */
+    int nleaf;
+    int (*leaf)[4];     /* level, c0, c1, c2 */
+    int* look[2];       /* per level: block coordinates -> leaf index, or -1 */
+    double dx[2][3];    /* cell widths per level */
+    int64_t nb;         /* cells per block */
+} smrgeo;
+
+static void smr_free(smrgeo* g) {
+    free(g->leaf);
+    free(g->look[0]);
+    free(g->look[1]);
+}
+
+static int64_t smr_key(const smrgeo* g, int L, const int* c) {
+    int64_t e0 = (int64_t)g->B[0] << L, e1 = (int64_t)g->B[1] << L;
+    return ((int64_t)c[2] * e1 + c[1]) * e0 + c[0];
+}
+
+static int smr_geometry(const orc_mesh* m, const int32_t* blocks, int nref, const int32_t* refined, smrgeo* g) {
+    memset(g, 0, sizeof(*g));
+    blockgeo bg;
+    if (!block_geometry(m, blocks, &bg) || nref < 0 || (nref > 0 && !refined)) return 0;
+    g->mb = bg.mb;
+    for (int d = 0; d < 3; ++d) {
+        g->B[d] = bg.B[d];
+        g->dx[0][d] = bg.dx[d];
+        g->dx[1][d] = d < m->ndim ? 0.5 * bg.dx[d] : 1.0;
+        /* a refined block's children align with its cells: restriction of
+         * n_gh coarse ghost layers needs 2 n_gh fine layers in one block */
+        if (nref > 0 && d < m->ndim && (bg.mb.n[d] % 2 != 0 || bg.mb.n[d] < 2 * NGH)) return 0;
+    }
+    g->nb = bg.nb;
+    int nroot = bg.nblk, kids = 1 << m->ndim;
+    char* ref = (char*)calloc((size_t)nroot, 1);
+    if (!ref) return 0;
+    for (int r = 0; r < nref; ++r) {
+        if (refined[r] < 0 || refined[r] >= nroot || ref[refined[r]]) {
+            free(ref);
+            return 0;
+        }
+        ref[refined[r]] = 1;
+    }
+    int64_t n1 = (int64_t)nroot * kids;
+    g->nleaf = nroot - nref + nref * kids;
+    g->leaf = (int(*)[4])malloc((size_t)g->nleaf * sizeof(*g->leaf));
+    g->look[0] = (int*)malloc((size_t)nroot * sizeof(int));
+    g->look[1] = (int*)malloc((size_t)n1 * sizeof(int));
+    if (!g->leaf || !g->look[0] || !g->look[1]) {
+        free(ref);
+        smr_free(g);
+        return 0;
+    }
+    int q = 0;
+    for (int r = 0; r < nroot; ++r) {
+        g->look[0][r] = -1;
+        if (ref[r]) continue;
+        g->leaf[q][0] = 0;
+        g->leaf[q][1] = r % g->B[0];
+        g->leaf[q][2] = (r / g->B[0]) % g->B[1];
+        g->leaf[q][3] = r / (g->B[0] * g->B[1]);
+        g->look[0][r] = q++;
+    }
+    int E[3];
+    for (int d = 0; d < 3; ++d) E[d] = d < m->ndim ? 2 * g->B[d] : 1;
+    for (int64_t f = 0; f < n1; ++f) {
+        int c[3] = {(int)(f % E[0]), (int)((f / E[0]) % E[1]), (int)(f / ((int64_t)E[0] * E[1]))};
+        int pc[3] = {c[0] / (m->ndim > 0 ? 2 : 1), c[1] / (m->ndim > 1 ? 2 : 1), c[2] / (m->ndim > 2 ? 2 : 1)};
+        int r = pc[0] + g->B[0] * (pc[1] + g->B[1] * pc[2]);
+        g->look[1][f] = -1;
+        if (!ref[r]) continue;
+        g->leaf[q][0] = 1;
+        g->leaf[q][1] = c[0];
+        g->leaf[q][2] = c[1];
+        g->leaf[q][3] = c[2];
+        g->look[1][f] = q++;
+    }
+    free(ref);
+    return q == g->nleaf;
+}
+
+/* Extent of the level-L block grid on axis d. */
+static int smr_extent(const smrgeo* g, int L, int d) { return d < g->mb.ndim ? g->B[d] << L : 1; }
+
+/* What lies across side s of axis d of leaf b: NB_PHYS, or the leaf index
+ * (NB_SAME, NB_COARSE) or the refined root's level-0 coordinates (NB_FINE). */
+static int smr_nbr(const smrgeo* g, int b, int d, int s, int* idx, int* root) {
+    int L = g->leaf[b][0];
+    int c[3] = {g->leaf[b][1], g->leaf[b][2], g->leaf[b][3]};
+    int E = smr_extent(g, L, d);
+    int q = c[d] + (s ? 1 : -1);
+    if (q < 0 || q >= E) {
+        if (g->mb.bc[d][s] != ORC_BC_PERIODIC) return NB_PHYS;
+        q = (q + E) % E;
+    }
+    c[d] = q;
+    int same = g->look[L][smr_key(g, L, c)];
+    if (same >= 0) {
+        *idx = same;
+        return NB_SAME;
+    }
+    if (L == 1) {
+        int pc[3];
+        for (int e = 0; e < 3; ++e) pc[e] = e < g->mb.ndim ? c[e] / 2 : 0;
+        *idx = g->look[0][smr_key(g, 0, pc)];
+        return NB_COARSE;
+    }
+    for (int e = 0; e < 3; ++e) root[e] = c[e];
+    return NB_FINE;
+}
+
+/* the level-1 leaf holding fine cell (x, y, z) of the level-1 grid, and the
+ * cell's block-local coordinates */
+static int smr_fine_cell(const smrgeo* g, const int* x, int* local) {
+    int c[3];
+    for (int e = 0; e < 3; ++e) {
+        c[e] = x[e] / g->mb.n[e];
+        local[e] = x[e] % g->mb.n[e];
+    }
+    return g->look[1][smr_key(g, 1, c)];
+}
+
+/* Pairwise means of 2^k values along x, then y, then z (bit 0 of the index
+ * is the x offset): equal values give the value back exactly. */
+static double tree_mean(double* v, int k) {
+    int n = 1 << k;
+    for (int a = 0; a < k; ++a) {
+        n >>= 1;
+        for (int i = 0; i < n; ++i) v[i] = 0.5 * (v[2 * i] + v[2 * i + 1]);
+    }
+    return v[0];
+}
+
+/* Fill every ghost of every leaf's padded primitive array (interiors set). */
+static void smr_fill_ghosts(const smrgeo* g, double* Wp) {
+    const orc_mesh* mb = &g->mb;
+    int ndim = mb->ndim, nc = ndim + 2;
+    padgeo pg = pad_geometry(mb);
+    const int* n = mb->n;
+    /* (a) same-level copies, restriction onto coarse ghosts, p-boundaries */
+    for (int b = 0; b < g->nleaf; ++b) {
+        double* Wd = Wp + (int64_t)b * nc * pg.total;
+        int cside[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+        for (int d = 0; d < ndim; ++d) {
+            int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
+            for (int s = 0; s < 2; ++s) {
+                int idx = -1, root[3] = {0, 0, 0};
+                int kind = smr_nbr(g, b, d, s, &idx, root);
+                cside[d][s] = kind != NB_PHYS;
+                if (kind == NB_SAME) {
+                    const double* Ws = Wp + (int64_t)idx * nc * pg.total;
+                    for (int a = 0; a < n[e1]; ++a)
+                        for (int bb = 0; bb < n[e2]; ++bb)
+                            for (int l = 0; l < NGH; ++l) {
+                                int gi[3], si[3];
+                                gi[d] = s ? n[d] + l : -1 - l;
+                                si[d] = s ? l : n[d] - 1 - l;
+                                gi[e1] = si[e1] = a;
+                                gi[e2] = si[e2] = bb;
+                                int64_t go = pidx(&pg, gi[0], gi[1], gi[2]), so = pidx(&pg, si[0], si[1], si[2]);
+                                for (int c = 0; c < nc; ++c) Wd[c * pg.total + go] = Ws[c * pg.total + so];
+                            }
+                } else if (kind == NB_FINE) {
+                    /* coarse ghost layer l covers fine layers 2l, 2l+1 away
+                     * from the face; transverse coarse index t covers fine
+                     * 2t, 2t+1 from the refined root's origin */
+                    for (int a = 0; a < n[e1]; ++a)
+                        for (int bb = 0; bb < n[e2]; ++bb)
+                            for (int l = 0; l < NGH; ++l) {
+                                int gi[3];
+                                gi[d] = s ? n[d] + l : -1 - l;
+                                gi[e1] = a;
+                                gi[e2] = bb;
+                                int64_t go = pidx(&pg, gi[0], gi[1], gi[2]);
+                                for (int c = 0; c < nc; ++c) {
+                                    double v[8];
+                                    for (int o = 0; o < (1 << ndim); ++o) {
+                                        int x[3];
+                                        for (int e = 0; e < 3; ++e) {
+                                            int off = e < ndim ? (o >> e) & 1 : 0;
+                                            int fe;
+                                            if (e == d) {
+                                                /* fine cells 2l, 2l+1 in from the refined
+                                                 * root's face (off 0: the lower one) */
+                                                fe = s ? 2 * root[d] * n[d] + 2 * l + off
+                                                       : 2 * (root[d] + 1) * n[d] - 2 - 2 * l + off;
+                                            } else {
+                                                fe = e < ndim ? 2 * root[e] * n[e] + 2 * gi[e] + off : 0;
+                                            }
+                                            x[e] = fe;
+                                        }
+                                        int loc[3];
+                                        int fb = smr_fine_cell(g, x, loc);
+                                        const double* Wf = Wp + (int64_t)fb * nc * pg.total;
+                                        v[o] = Wf[c * pg.total + pidx(&pg, loc[0], loc[1], loc[2])];
+                                    }
+                                    Wd[c * pg.total + go] = tree_mean(v, ndim);
+                                }
+                            }
+                }
+            }
+        }
+        fill_ghosts_masked(mb, Wd, (const int(*)[2])cside);
+    }
+    /* (b) prolongation from the coarse side's complete padded array */
+    for (int b = 0; b < g->nleaf; ++b) {
+        if (g->leaf[b][0] != 1) continue;
+        double* Wd = Wp + (int64_t)b * nc * pg.total;
+        const int fc[3] = {g->leaf[b][1], g->leaf[b][2], g->leaf[b][3]};
+        for (int d = 0; d < ndim; ++d) {
+            int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
+            for (int s = 0; s < 2; ++s) {
+                int idx = -1, root[3];
+                if (smr_nbr(g, b, d, s, &idx, root) != NB_COARSE) continue;
+                const double* Wc = Wp + (int64_t)idx * nc * pg.total;
+                for (int a = 0; a < n[e1]; ++a)
+                    for (int bb = 0; bb < n[e2]; ++bb)
+                        for (int l = 0; l < NGH; ++l) {
+                            int gi[3], ci[3];
+                            double sg[3] = {0.0, 0.0, 0.0};
+                            gi[d] = s ? n[d] + l : -1 - l;
+                            gi[e1] = a;
+                            gi[e2] = bb;
+                            /* the coarse cell: next to the face along d */
+                            ci[d] = s ? 0 : n[d] - 1;
+                            sg[d] = s ? (l == 0 ? -1.0 : 1.0) : (l == 0 ? 1.0 : -1.0);
+                            for (int e = 0; e < 3; ++e) {
+                                if (e == d) continue;
+                                if (e >= ndim) {
+                                    ci[e] = 0;
+                                    continue;
+                                }
+                                int p = (fc[e] % 2) * n[e] + gi[e]; /* fine index from the parent's origin */
+                                ci[e] = p / 2;
+                                sg[e] = (p % 2) ? 1.0 : -1.0;
+                            }
+                            int64_t go = pidx(&pg, gi[0], gi[1], gi[2]);
+                            int64_t co = pidx(&pg, ci[0], ci[1], ci[2]);
+                            for (int c = 0; c < nc; ++c) {
+                                double wc = Wc[c * pg.total + co];
+                                double acc = wc;
+                                for (int e = 0; e < ndim; ++e) {
+                                    int lo[3] = {ci[0], ci[1], ci[2]}, hi[3] = {ci[0], ci[1], ci[2]};
+                                    lo[e] -= 1;
+                                    hi[e] += 1;
+                                    double wl = Wc[c * pg.total + pidx(&pg, lo[0], lo[1], lo[2])];
+                                    double wh = Wc[c * pg.total + pidx(&pg, hi[0], hi[1], hi[2])];
+                                    acc = acc + (0.25 * sg[e]) * orc_minmod(wc - wl, wh - wc);
+                                }
+                                Wd[c * pg.total + go] = acc;
+                            }
+                        }
+            }
+        }
+    }
+}
+
+/* Stage right-hand side of every leaf from X (conserved, block layout). */
+static int smr_rhs(const smrgeo* g, const double* X, double dt, double* dU) {
+    const orc_mesh* mb = &g->mb;
+    int ndim = mb->ndim, nc = ndim + 2;
+    int n0 = mb->n[0], n1 = mb->n[1], n2 = mb->n[2];
+    int64_t nb = g->nb;
+    padgeo pg = pad_geometry(mb);
+    double* Wp = (double*)calloc((size_t)g->nleaf * nc * pg.total, sizeof(double));
+    faceflux* ff = (faceflux*)calloc((size_t)g->nleaf, sizeof(faceflux));
+    if (!Wp || !ff) {
+        free(Wp);
+        free(ff);
+        return -1;
+    }
+    int bad = 0;
+    for (int b = 0; b < g->nleaf; ++b) {
+        const double* Xb = X + (int64_t)b * nc * nb;
+        double* Wb = Wp + (int64_t)b * nc * pg.total;
+        for (int k = 0; k < n2; ++k)
+            for (int j = 0; j < n1; ++j)
+                for (int i = 0; i < n0; ++i) {
+                    int64_t cell = ((int64_t)k * n1 + j) * n0 + i;
+                    double u[MAXC], w[MAXC];
+                    for (int c = 0; c < nc; ++c) u[c] = Xb[c * nb + cell];
+                    if (!cons_to_prim_cell(ndim, mb->gamma, u, w)) ++bad;
+                    int64_t o = pidx(&pg, i, j, k);
+                    for (int c = 0; c < nc; ++c) Wb[c * pg.total + o] = w[c];
+                }
+    }
+    int rc = bad;
+    if (rc == 0) smr_fill_ghosts(g, Wp);
+    for (int b = 0; b < g->nleaf && rc == 0; ++b)
+        rc = block_fluxes(mb, Wp + (int64_t)b * nc * pg.total, 2, &ff[b]);
+    /* (d) coarse faces shared with finer blocks take the fine fluxes' average */
+    for (int b = 0; b < g->nleaf && rc == 0; ++b) {
+        for (int d = 0; d < ndim; ++d) {
+            int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
+            for (int s = 0; s < 2; ++s) {
+                int idx = -1, root[3] = {0, 0, 0};
+                if (smr_nbr(g, b, d, s, &idx, root) != NB_FINE) continue;
+                const int64_t* fext = ff[b].fext[d];
+                for (int a = 0; a < mb->n[e1]; ++a)
+                    for (int bb = 0; bb < mb->n[e2]; ++bb) {
+                        int fi[3];
+                        fi[d] = s ? mb->n[d] : 0;
+                        fi[e1] = a;
+                        fi[e2] = bb;
+                        int64_t fo = ((int64_t)fi[2] * fext[1] + fi[1]) * fext[0] + fi[0];
+                        for (int c = 0; c < nc; ++c) {
+                            double v[4];
+                            int k = 0;
+                            /* transverse offsets in axis order (x, y, z without d) */
+                            int tax[2], nt = 0;
+                            for (int e = 0; e < ndim; ++e)
+                                if (e != d) tax[nt++] = e;
+                            for (int o = 0; o < (1 << nt); ++o) {
+                                int x[3];
+                                x[d] = s ? 2 * root[d] * mb->n[d] : 2 * (root[d] + 1) * mb->n[d] - 1;
+                                for (int e = 0; e < 3; ++e) {
+                                    if (e == d) continue;
+                                    x[e] = e < ndim ? 2 * root[e] * mb->n[e] + 2 * fi[e] : 0;
+                                }
+                                for (int t = 0; t < nt; ++t) x[tax[t]] += (o >> t) & 1;
+                                int loc[3];
+                                int fb = smr_fine_cell(g, x, loc);
+                                /* the fine face on the shared plane: low face of a
+                                 * fine cell for s = 1, its high face for s = 0 */
+                                int ffi[3] = {loc[0], loc[1], loc[2]};
+                                if (!s) ffi[d] += 1;
+                                const int64_t* fx = ff[fb].fext[d];
+                                int64_t ffo = ((int64_t)ffi[2] * fx[1] + ffi[1]) * fx[0] + ffi[0];
+                                v[k++] = ff[fb].F[d][c * ff[fb].nf[d] + ffo];
+                            }
+                            ff[b].F[d][c * ff[b].nf[d] + fo] = tree_mean(v, nt);
+                        }
+                    }
+            }
+        }
+    }
+    for (int b = 0; b < g->nleaf && rc == 0; ++b)
+        flux_update(mb, g->dx[g->leaf[b][0]], &ff[b], dt, dU + (int64_t)b * nc * nb);
+    for (int b = 0; b < g->nleaf; ++b) faceflux_free(&ff[b]);
+    free(ff);
+    free(Wp);
+    return rc;
+}
+
+static double smr_cfl_dt(const smrgeo* g, const double* U, double cfl) {
+    int ndim = g->mb.ndim, nc = ndim + 2;
+    double gm = g->mb.gamma, best = INFINITY;
+    for (int b = 0; b < g->nleaf; ++b) {
+        const double* dx = g->dx[g->leaf[b][0]];
+        for (int64_t i = 0; i < g->nb; ++i) {
+            double u[MAXC], w[MAXC];
+            for (int c = 0; c < nc; ++c) u[c] = U[(int64_t)b * nc * g->nb + c * g->nb + i];
+            if (!cons_to_prim_cell(ndim, gm, u, w)) return -1.0;
+            double cs = sqrt(gm * w[nc - 1] / w[0]);
+            for (int d = 0; d < ndim; ++d) {
+                double cand = dx[d] / (fabs(w[1 + d]) + cs);
+                if (cand < best) best = cand;
+            }
+        }
+    }
+    return cfl * best;
+}
+
+int orc_smr_leaves(const orc_mesh* m, const int32_t blocks[3], int nref, const int32_t* refined,
+                   int32_t* leaves, int max) {
+    smrgeo g;
+    if (!smr_geometry(m, blocks, nref, refined, &g)) {
+        smr_free(&g);
+        return -1;
+    }
+    for (int b = 0; b < g.nleaf && b < max; ++b)
+        for (int q = 0; q < 4; ++q) leaves[4 * b + q] = g.leaf[b][q];
+    int n = g.nleaf;
+    smr_free(&g);
+    return n;
+}
+
+int orc_smr_ghosts(const orc_mesh* m, const int32_t blocks[3], int nref, const int32_t* refined,
+                   const double* W, double* Wpad) {
+    smrgeo g;
+    if (!smr_geometry(m, blocks, nref, refined, &g)) {
+        smr_free(&g);
+        return -1;
+    }
+    int nc = m->ndim + 2;
+    padgeo pg = pad_geometry(&g.mb);
+    memset(Wpad, 0, (size_t)g.nleaf * nc * pg.total * sizeof(double));
+    for (int b = 0; b < g.nleaf; ++b)
+        for (int k = 0; k < g.mb.n[2]; ++k)
+            for (int j = 0; j < g.mb.n[1]; ++j)
+                for (int i = 0; i < g.mb.n[0]; ++i) {
+                    int64_t cell = ((int64_t)k * g.mb.n[1] + j) * g.mb.n[0] + i;
+                    for (int c = 0; c < nc; ++c)
+                        Wpad[((int64_t)b * nc + c) * pg.total + pidx(&pg, i, j, k)] =
+                            W[((int64_t)b * nc + c) * g.nb + cell];
+                }
+    smr_fill_ghosts(&g, Wpad);
+    smr_free(&g);
+    return 0;
+}
+
+int orc_run_smr(const orc_mesh* m, const int32_t blocks[3], int nref, const int32_t* refined, double* U,
+                double cfl, int max_steps, double t_end, double* t, int* steps_done, double* dts) {
+    smrgeo g;
+    if (!smr_geometry(m, blocks, nref, refined, &g) || !t || !(cfl > 0.0) ||
+        (max_steps <= 0 && !(t_end > 0.0)) || m->integrator != ORC_HEUN) {
+        smr_free(&g);
+        return -1;
+    }
+    int64_t tot = (int64_t)g.nleaf * (m->ndim + 2) * g.nb;
+    double* U1 = (double*)malloc((size_t)tot * sizeof(double));
+    double* dU = (double*)malloc((size_t)tot * sizeof(double));
+    int s = 0, rc = (U1 && dU) ? 0 : -1;
+    while (rc == 0 && (max_steps <= 0 || s < max_steps)) {
+        if (t_end > 0.0 && !(*t < t_end)) break;
+        double dt = smr_cfl_dt(&g, U, cfl);
+        if (!(dt > 0.0)) {
+            rc = 1;
+            break;
+        }
+        int last = 0;
+        if (t_end > 0.0 && dt >= t_end - *t) {
+            dt = t_end - *t;
+            last = 1;
+        }
+        rc = smr_rhs(&g, U, dt, dU);
+        if (rc) break;
+        for (int64_t q = 0; q < tot; ++q) U1[q] = U[q] + dU[q];
+        rc = smr_rhs(&g, U1, dt, dU);
+        if (rc) break;
+        for (int64_t q = 0; q < tot; ++q) U[q] = 0.5 * U[q] + 0.5 * (U1[q] + dU[q]);
+        if (dts) dts[s] = dt;
+        *t = last ? t_end : *t + dt;
+        ++s;
+    }
+    free(U1);
+    free(dU);
+    smr_free(&g);
+    if (steps_done) *steps_done = s;
+    return rc;
+}
+
+void orc_smr_totals(const orc_mesh* m, const int32_t blocks[3], int nref, const int32_t* refined,
+                    const double* U, double* totals) {
+    smrgeo g;
+    if (!smr_geometry(m, blocks, nref, refined, &g)) {
+        smr_free(&g);
+        return;
+    }
+    int nc = m->ndim + 2;
+    for (int c = 0; c < nc; ++c) {
+        double sum = 0.0, comp = 0.0;
+        for (int b = 0; b < g.nleaf; ++b) {
+            double dV = 1.0;
+            for (int d = 0; d < m->ndim; ++d) dV *= g.dx[g.leaf[b][0]][d];
+            for (int64_t i = 0; i < g.nb; ++i) {
+                double x = dV * U[((int64_t)b * nc + c) * g.nb + i];
+                double tt = sum + x;
+                if (fabs(sum) >= fabs(x))
+                    comp += (sum - tt) + x;
+                else
+                    comp += (x - tt) + sum;
+                sum = tt;
+            }
+        }
+        totals[c] = sum + comp;
+    }
+    smr_free(&g);
 }
 
 void orc_totals(const orc_mesh* m, const double* U, double* totals) {

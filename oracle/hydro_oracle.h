@@ -118,6 +118,34 @@ int orc_run(const orc_mesh* m, double* U, double cfl, int max_steps, double t_en
 int orc_run_blocks(const orc_mesh* m, const int32_t blocks[3], double* U, double cfl, int max_steps,
                    double t_end, double* t, int* steps_done, double* dts);
 
+/*
+ * Two-level static mesh refinement of the block mesh of orc_run_blocks: the
+ * nref root blocks listed in refined[] (root index b0 + B0 (b1 + B1 b2)) are
+ * each replaced by 2^ndim blocks of half their size with the same cell
+ * count.  Refinement needs an even block extent of at least 4 cells on every
+ * active axis.  Leaves are ordered level 0 first (ascending root index), then
+ * level 1 (ascending index on the level-1 block grid, x fastest); fields are
+ * in the block layout [leaf][comp][k][j][i] of one block's extents.
+ * Cross-level c-boundaries: restriction (pairwise volume averages) onto
+ * coarse ghosts, then minmod-limited prolongation onto fine ghosts, fluxes,
+ * and the average of the fine fluxes on the coarse side of each level jump;
+ * all on primitive variables; one global time step; Heun only.
+ *
+ * orc_smr_leaves writes (level, c0, c1, c2) per leaf (at most max) and
+ * returns the leaf count, or -1 for an invalid refinement.
+ * orc_smr_ghosts fills every leaf's padded primitive array (n_gh = 2, the
+ * orc_fill_ghosts layout per leaf) from the primitive block-layout field W.
+ * orc_smr_totals: the conserved totals, sum over leaves of dV_level U.
+ */
+int orc_smr_leaves(const orc_mesh* m, const int32_t blocks[3], int nref, const int32_t* refined,
+                   int32_t* leaves, int max);
+int orc_smr_ghosts(const orc_mesh* m, const int32_t blocks[3], int nref, const int32_t* refined,
+                   const double* W, double* Wpad);
+int orc_run_smr(const orc_mesh* m, const int32_t blocks[3], int nref, const int32_t* refined, double* U,
+                double cfl, int max_steps, double t_end, double* t, int* steps_done, double* dts);
+void orc_smr_totals(const orc_mesh* m, const int32_t blocks[3], int nref, const int32_t* refined,
+                    const double* U, double* totals);
+
 /* dV-weighted conserved totals, compensated (Neumaier) sums in storage order. */
 void orc_totals(const orc_mesh* m, const double* U, double* totals);
 

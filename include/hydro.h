@@ -235,6 +235,40 @@ int hydro_profile(hydro_t h, int cap);
 int hydro_profile_read(hydro_t h, double* ms_stage1, double* ms_stage2, int64_t* launches);
 
 /*
+ * Static mesh refinement, two levels (Sec. 2.3: the 2^d-tree of blocks, one
+ * level deep; Sec. 3: c-boundaries across levels).  The blocks of cfg (see
+ * "Blocks") are the root blocks; the nref root indices in refined[] (b0 +
+ * blocks[0] (b1 + blocks[1] b2), distinct) are each replaced by 2^ndim blocks
+ * of half the size and the same extents in cells.  Refinement needs even
+ * block extents of at least 4 cells on the active axes, the Heun integrator,
+ * and at most 1024 leaves.
+ *   - Leaves are ordered: level 0 in root order, then level 1 in the order of
+ *     the level-1 block grid (2 blocks[d] per active axis, x fastest).
+ *     hydro_smr_leaves writes (level, c0, c1, c2) per leaf (at most max
+ *     entries, block coordinates on the leaf's level, physical axes) and
+ *     returns the number of leaves, or HYDRO_E_INVAL; it needs no device.
+ *   - A refined handle's host and device state transfers use the block
+ *     layout [leaf][comp][k][j][i] of one block's extents (the mesh has no
+ *     single uniform layout); its totals weight each level by its cell volume.
+ *   - Each stage: the ghost layers at level jumps are filled first, the
+ *     coarse side's by volume averages (restriction) of the fine cells, then
+ *     the fine side's by minmod-limited prolongation (eq. minmod) of the
+ *     coarse cells, on primitive variables, into ghost slots in the
+ *     workspace; then the stage kernel runs per level (same-level faces read
+ *     the neighbour's cells in place); then each coarse cell next to a level
+ *     jump is corrected so that its update uses the mean of the fine fluxes
+ *     through its face, which keeps the totals conserved.  One global time
+ *     step (the paper's default), taken from a reduction after the step.
+ *   - Not available on a refined handle (HYDRO_E_INVAL): hydro_stage_rhs,
+ *     hydro_padded_primitive, hydro_autotune, hydro_set_block_streams(h, 1),
+ *     batch membership.
+ */
+size_t hydro_smr_workspace_bytes(const hydro_config* cfg, int nref, const int32_t* refined);
+int hydro_smr_create(const hydro_config* cfg, int nref, const int32_t* refined, void* d_workspace, size_t nbytes,
+                     void* hip_stream, hydro_t* out);
+int hydro_smr_leaves(const hydro_config* cfg, int nref, const int32_t* refined, int32_t* leaves, int max);
+
+/*
  * How the stages of a split mesh are launched (Sec. 3, Fig. hydro_proc: each
  * block's work on a stream of its own).  on = 0 (the default): one launch per
  * stage covers every block.  on = 1: each block's stages are launched on

@@ -79,6 +79,31 @@ struct StageArgs {
     int tiles_x, tiles_y, chunks_z, kz;  // per block
     int blk0, nblk;      // the launch covers blocks blk0 .. blk0 + nblk - 1
     int conc;            // blocks whose stage work runs at once (automatic chunk length)
+    // static refinement: per block 6 side codes (else null: the uniform
+    // block grid of geo), and the ghost slots of the sides at level jumps
+    const int* side;
+    const double* gbuf;
+    long long gcs;       // component stride within a ghost slot (slot = ncomp * gcs)
+};
+
+// Side codes of a refined mesh's blocks, [block][kernel axis][low, high]:
+// >= 0 the block of the same level across the side; kSidePhys a face of the
+// mesh (its boundary rule); kSideSlot0 - q the ghost slot q, which holds the
+// two ghost layers of the side, [comp][layer][t_hi][t_lo] over the side's two
+// transverse kernel axes (t_lo the lower), layer 0 next to the face.
+constexpr int kSidePhys = -1;
+constexpr int kSideSlot0 = -2;
+
+// One ghost slot: the side (ax, s) of block `leaf` at a level jump.
+// kind 0 (restriction; leaf is coarse): src[o] is the fine block on the face
+// at transverse child offsets o (bit 0: t_lo, bit 1: t_hi).  kind 1
+// (prolongation; leaf is fine): src[0] is the coarse block, child[] the
+// leaf's offsets (0/1) per kernel axis within its parent.
+struct GhostTask {
+    int leaf, ax, s, kind;
+    int src[4];
+    int child[3];
+    int slot;
 };
 
 // One member of a batch: the stage kernels build StageArgs from it.
@@ -116,6 +141,24 @@ hipError_t launch_padded_prim(const Geo& g, int precision, const double* U, doub
                               hipStream_t s);
 hipError_t launch_riemann(int precision, int ntan, double gamma, long long n, const double* WL,
                           const double* WR, double* F, hipStream_t s);
+
+// Static refinement passes over the ghost slots tasks[0, n) (all of one
+// kind): restriction or prolongation of the stage input U into gbuf (conserved
+// FP64 values), and the fine-flux correction of the coarse cells next to the
+// level jumps of kernel axis ax: out += factor * lam (difference of the coarse
+// flux and the mean of the fine fluxes), from the stage input in.  g0 and g1
+// are the coarse and fine levels' geometries.
+hipError_t launch_smr_restrict(const Geo& g, const double* U, const int* side, double* gbuf, long long gcs,
+                               const GhostTask* tasks, int n, Ctrl* ctrl, hipStream_t s);
+hipError_t launch_smr_prolong(const Geo& g, const double* U, const int* side, double* gbuf, long long gcs,
+                              const GhostTask* tasks, int n, Ctrl* ctrl, hipStream_t s);
+hipError_t launch_smr_reflux(int precision, int ax, const Geo& g0, const Geo& g1, const double* in, double* out,
+                             double factor, int use_device_dt, double dt_host, const int* side,
+                             const double* gbuf, long long gcs, const GhostTask* tasks, int n, Ctrl* ctrl,
+                             hipStream_t s);
+// dt reduction over the blocks [0, blocks[0]) of U (geo of one level); with
+// skip_done, nothing once the run limit is reached.
+hipError_t launch_dt_blocks(const Geo& g, const double* U, Ctrl* ctrl, int skip_done, hipStream_t s);
 
 // Default tile for a mesh (kernel axes) and precision.
 Tile default_tile(const Geo& g, int precision, int mode);

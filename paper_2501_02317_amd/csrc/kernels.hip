@@ -375,13 +375,18 @@ __device__ __forceinline__ int resolve_mesh(const Geo& g, int ax, int q, int& vm
 // The sides of one block: the block-index offset of the neighbour a side
 // reads its ghosts from (a c-boundary: inside the mesh, or across a periodic
 // axis), or kNoLink at a face of the mesh with a p-boundary rule.
+// On a refined mesh a side may instead read a ghost slot (slo/shi: the slot
+// index, else -1).
 constexpr int kNoLink = 0x7fffffff;
 struct Links {
     int lo[3], hi[3];
+    int slo[3], shi[3];
 };
 
 __device__ __forceinline__ Links block_links(const Geo& g, int blk) {
     Links L;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) L.slo[ax] = L.shi[ax] = -1;
     const int c[3] = {blk % g.blocks[0], (blk / g.blocks[0]) % g.blocks[1], blk / (g.blocks[0] * g.blocks[1])};
     const int stride[3] = {1, g.blocks[0], g.blocks[0] * g.blocks[1]};
 #pragma unroll
@@ -394,16 +399,56 @@ __device__ __forceinline__ Links block_links(const Geo& g, int blk) {
     return L;
 }
 
+// The sides of a block of a refined mesh, from its side codes.
+__device__ __forceinline__ Links table_links(const int* __restrict__ side, int blk) {
+    Links L;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int lo = side[6 * blk + 2 * ax], hi = side[6 * blk + 2 * ax + 1];
+        L.lo[ax] = lo >= 0 ? lo - blk : kNoLink;
+        L.hi[ax] = hi >= 0 ? hi - blk : kNoLink;
+        L.slo[ax] = lo <= kSideSlot0 ? kSideSlot0 - lo : -1;
+        L.shi[ax] = hi <= kSideSlot0 ? kSideSlot0 - hi : -1;
+    }
+    return L;
+}
+
+// The sides of a launch's block: from the side codes of a refined mesh, else
+// from the uniform block grid (selected field by field, so the structure
+// stays in registers).
+__device__ __forceinline__ Links stage_links(const StageArgs& a, int blk) {
+    const Geo& g = a.geo;
+    const bool tab = a.side != nullptr;
+    const Links G = block_links(g, blk);
+    Links L;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int lo = tab ? a.side[6 * blk + 2 * ax] : 0, hi = tab ? a.side[6 * blk + 2 * ax + 1] : 0;
+        L.lo[ax] = tab ? (lo >= 0 ? lo - blk : kNoLink) : G.lo[ax];
+        L.hi[ax] = tab ? (hi >= 0 ? hi - blk : kNoLink) : G.hi[ax];
+        L.slo[ax] = tab && lo <= kSideSlot0 ? kSideSlot0 - lo : -1;
+        L.shi[ax] = tab && hi <= kSideSlot0 ? kSideSlot0 - hi : -1;
+    }
+    return L;
+}
+
 // Ghost coordinate q (one block's extent N on kernel axis ax) -> the cell it
 // copies: in the linked block dblk (offset in blocks, 0 for the block
 // itself) at q -/+ N, or by the p-boundary rule of a mesh face, with the
-// treatment of the normal velocity (Sec. 3.1.1).
-__device__ __forceinline__ int resolve(const Geo& g, const Links& L, int ax, int q, int& vmode, int& dblk) {
+// treatment of the normal velocity (Sec. 3.1.1); or, at a level jump, the
+// ghost slot `slot` (else -1) and the layer returned (0 next to the face).
+__device__ __forceinline__ int resolve(const Geo& g, const Links& L, int ax, int q, int& vmode, int& dblk,
+                                       int& slot) {
     const int N = g.n[ax];
     vmode = VM_NONE;
     dblk = 0;
+    slot = -1;
     if (q >= 0 && q < N) return q;
     if (q < 0) {
+        if (L.slo[ax] >= 0) {
+            slot = L.slo[ax];
+            return -1 - q;
+        }
         if (L.lo[ax] != kNoLink) {
             dblk = L.lo[ax];
             return q + N;
@@ -413,6 +458,10 @@ __device__ __forceinline__ int resolve(const Geo& g, const Links& L, int ax, int
             case BC_OUTFLOW: vmode = VM_CLIP_LO; return 0;
             default: vmode = VM_NEG; return -1 - q;
         }
+    }
+    if (L.shi[ax] >= 0) {
+        slot = L.shi[ax];
+        return q - N;
     }
     if (L.hi[ax] != kNoLink) {
         dblk = L.hi[ax];
@@ -696,7 +745,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
     const long long P = (long long)n0 * n1;  // plane stride
     const long long BS = (long long)NC * N;  // elements of one block of a field
     const long long boff = (long long)blk * BS;
-    const Links lk = block_links(g, blk);
+    const Links lk = stage_links(a, blk);
     const double gm1 = g.gamma - 1.0;
 
     const int tix = b % a.tiles_x;
@@ -713,10 +762,12 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
     const long long col = (long long)(y0 + ly) * n0 + (x0 + lx);
 
     // this thread's halo cell (tile coordinates hx, hy), resolved once to an
-    // element offset in the field (its block's offset + the in-plane index)
-    bool hact = false;
-    int hx = 0, hy = 0, hvax = -1, hvm = VM_NONE;
-    long long hcol = 0;
+    // element offset hcol in the field (its block's offset + the in-plane
+    // index) or in the ghost buffer (hslot), with its plane and component
+    // strides
+    bool hact = false, hslot = false;
+    int hx = 0, hy = 0, hvax = -1, hvm = VM_NONE, hk = 0;
+    long long hcol = 0, hc = 0;
     {
         const int nhx = 4 * ay;
         const int nhy = HY ? 4 * ax : 0;
@@ -732,15 +783,26 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
             hact = true;
         }
         if (hact) {
-            int X = x0 + hx, Y = y0 + hy, db = 0;
+            int X = x0 + hx, Y = y0 + hy, db = 0, sl = -1;
             if (X < 0 || X >= n0) {
-                X = resolve(g, lk, 0, X, hvm, db);
+                X = resolve(g, lk, 0, X, hvm, db, sl);
                 hvax = 0;
             } else if (Y < 0 || Y >= n1) {
-                Y = resolve(g, lk, 1, Y, hvm, db);
+                Y = resolve(g, lk, 1, Y, hvm, db, sl);
                 hvax = 1;
             }
-            hcol = (long long)(blk + db) * BS + (long long)Y * n0 + X;
+            if (sl >= 0) {
+                // a ghost slot: [comp][layer][z][y] of an x side, [comp][layer][z][x] of a y side
+                hslot = true;
+                const long long sb = (long long)sl * NC * a.gcs;
+                hcol = hvax == 0 ? sb + ((long long)X * n2) * n1 + Y : sb + ((long long)Y * n2) * n0 + X;
+                hk = hvax == 0 ? n1 : n0;
+                hc = a.gcs;
+            } else {
+                hcol = (long long)(blk + db) * BS + (long long)Y * n0 + X;
+                hk = (int)P;
+                hc = N;
+            }
         }
     }
 
@@ -789,25 +851,38 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
             for (int c = 0; c < NC; ++c) u[c] = plane_load(a.in, c * N + poff, ext8, tc * 8u);
         }
     };
-    // the halo cell at plane offset poff: it may lie in another block, so it
-    // is addressed from the field's base with a per-thread offset
-    auto load_halo = [&](long long poff, double (&u)[NC]) {
+    // the halo cell of plane k: it may lie in another block or in a ghost
+    // slot, so it is addressed from the base with a per-thread offset
+    auto load_halo = [&](int k, double (&u)[NC]) {
+        const long long o = hcol + (long long)k * hk;
         if constexpr (PRIM_IN) {
-            const R* F = reinterpret_cast<const R*>(a.in) + (hcol + poff);
+            // (refined meshes, whose ghost slots hold conserved values, run Heun only)
+            const R* F = reinterpret_cast<const R*>(a.in) + o;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) u[c] = (double)F[c * N];
+            for (int c = 0; c < NC; ++c) u[c] = (double)F[c * hc];
         } else {
-            const double* F = a.in + (hcol + poff);
+            // (the base is selected as an integer: selecting between the two
+            // argument fields themselves makes the compiler copy the
+            // arguments to private memory)
+            const uintptr_t bi = reinterpret_cast<uintptr_t>(a.in), bg = reinterpret_cast<uintptr_t>(a.gbuf);
+            const double* F = reinterpret_cast<const double*>(hslot ? bg : bi) + o;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) u[c] = F[c * N];
+            for (int c = 0; c < NC; ++c) u[c] = F[c * hc];
         }
     };
     const uint32_t col32 = (uint32_t)col;
     auto load_interior = [&](int z, double (&u)[NC], int& vm) {
         vm = VM_NONE;
-        int zr = z, db = 0;
-        if (z < 0 || z >= n2) zr = resolve(g, lk, 2, z, vm, db);
-        load_in((long long)(blk + db) * BS + (long long)zr * P, col32, u);
+        int zr = z, db = 0, sl = -1;
+        if (z < 0 || z >= n2) zr = resolve(g, lk, 2, z, vm, db, sl);
+        if (!PRIM_IN && sl >= 0) {
+            // a ghost slot of a z side: [comp][layer][y][x], one plane per layer
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                u[c] = plane_load(a.gbuf, ((long long)sl * NC + c) * a.gcs + (long long)zr * P, ext8, col32 * 8u);
+        } else {
+            load_in((long long)(blk + db) * BS + (long long)zr * P, col32, u);
+        }
     };
 
     if (HZ && act) {
@@ -914,7 +989,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
         if (live && hact) {
             double uh[NC];
             R wh[NC];
-            load_halo((long long)k * P, uh);
+            load_halo(k, uh);
             // not checked here: every cell is checked by the tile that owns it
             in_to_w<NDIM, R, PRIM_IN, false>(gm1, uh, hvax, hvm, wh, bad);
 #pragma unroll
@@ -1109,7 +1184,7 @@ void stage_kernel_batch(
     const int2 e = blk[xcd_remap(blockIdx.x, gridDim.x)];
     const MeshDesc& d = descs[e.x];
     if (d.ctrl->done) return;  // uniform over the work-group
-    StageArgs a;
+    StageArgs a{};  // every field set: a batch member is one unrefined block
     a.ctrl = d.ctrl;
     a.geo = d.geo;
     a.dt_host = 0.0;
@@ -1120,6 +1195,10 @@ void stage_kernel_batch(
     a.kz = d.kz;
     a.blk0 = 0;
     a.nblk = 1;
+    a.conc = 1;
+    a.side = nullptr;
+    a.gbuf = nullptr;
+    a.gcs = 0;
     if (MODE == MODE_STAGE1 || MODE == MODE_VL2_PRED) {
         a.in = d.U;
         a.base = d.U;
@@ -1138,8 +1217,9 @@ void stage_kernel_batch(
 
 // blockIdx.y: the block of the mesh (block layout)
 template <int NDIM>
-__global__ __launch_bounds__(256) void dt_kernel(Geo g, const double* __restrict__ U, Ctrl* ctrl) {
+__global__ __launch_bounds__(256) void dt_kernel(Geo g, const double* __restrict__ U, Ctrl* ctrl, int skip_done) {
     constexpr int NC = NDIM + 2;
+    if (skip_done && ctrl->done) return;  // uniform over the grid
     U += (long long)blockIdx.y * NC * g.ncells;
     double best = 0.0;
     bool bad = false;
@@ -1363,6 +1443,297 @@ __global__ __launch_bounds__(256) void padded_prim_kernel(Geo g, const double* _
             for (int c = 0; c < NC; ++c) out[c] = (double)w[c];
         }
         for (int c = 0; c < NC; ++c) Wp[c * total + q] = out[c];
+    }
+    if (bad) atomicOr(&ctrl->flags, FLAG_NONPHYSICAL);
+}
+
+// ------------------------------------------------------- static refinement
+
+// The two transverse kernel axes of a side of kernel axis ax (lower first).
+__device__ __forceinline__ void transverse(int ax, int& lo, int& hi) {
+    lo = ax == 0 ? 1 : 0;
+    hi = ax == 2 ? 1 : 2;
+}
+
+// Raw conserved values of cell (x, y, z) of block blk of a refined mesh, at
+// most one coordinate outside the block (by up to two cells): through the
+// block's side codes, from a neighbouring block, by a mesh face's boundary
+// rule (vax, vm: the velocity treatment), or from a ghost slot.
+template <int NC>
+__device__ __forceinline__ void smr_cell(const Geo& g, const Links& L, const double* __restrict__ U,
+                                         const double* __restrict__ gbuf, long long gcs, int blk, int x, int y,
+                                         int z, double (&u)[NC], int& vax, int& vm) {
+    int c3[3] = {x, y, z};
+    int b = blk;
+    vax = -1;
+    vm = VM_NONE;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        if (c3[ax] >= 0 && c3[ax] < g.n[ax]) continue;
+        int db = 0, sl = -1;
+        const int q = resolve(g, L, ax, c3[ax], vm, db, sl);
+        if (sl >= 0) {
+            int lo, hi;
+            transverse(ax, lo, hi);
+            const long long o = (long long)sl * NC * gcs + ((long long)q * g.n[hi] + c3[hi]) * g.n[lo] + c3[lo];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) u[c] = gbuf[o + c * gcs];
+            vm = VM_NONE;
+            return;
+        }
+        c3[ax] = q;
+        b = blk + db;
+        if (vm != VM_NONE) vax = ax;
+        break;
+    }
+    const long long N = g.ncells;
+    const long long o = (long long)b * NC * N + ((long long)c3[2] * g.n[1] + c3[1]) * g.n[0] + c3[0];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) u[c] = U[o + c * N];
+}
+
+// Primitive FP64 state of a refined mesh's cell (see smr_cell).
+template <int NDIM>
+__device__ __forceinline__ void smr_prim(const Geo& g, const Links& L, const double* __restrict__ U,
+                                         const double* __restrict__ gbuf, long long gcs, int blk, int x, int y,
+                                         int z, double (&w)[NDIM + 2], bool& bad) {
+    double u[NDIM + 2];
+    int vax, vm;
+    smr_cell<NDIM + 2>(g, L, U, gbuf, gcs, blk, x, y, z, u, vax, vm);
+    to_prim<NDIM, double>(g.gamma - 1.0, u, vax, vm, w, bad);
+}
+
+// m_d = rho v_d, E = p/(gamma - 1) + (1/2) sum_d m_d v_d
+template <int NDIM>
+__device__ __forceinline__ void prim_to_cons_cell(double gamma, const double (&w)[NDIM + 2], double (&u)[NDIM + 2]) {
+    double ke2 = 0.0;
+    u[0] = w[0];
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+        const double mom = w[0] * w[1 + d];
+        u[1 + d] = mom;
+        ke2 = ke2 + mom * w[1 + d];
+    }
+    u[NDIM + 1] = w[NDIM + 1] / (gamma - 1.0) + 0.5 * ke2;
+}
+
+// Kernel axis of the k-th active axis (physical order: x, y, z).
+template <int NDIM>
+__device__ __forceinline__ constexpr int active_axis(int k) {
+    return NDIM == 2 ? (k == 0 ? 0 : 2) : k;
+}
+
+// Restriction onto the two ghost layers of a coarse block's side that faces
+// finer blocks: each ghost is the volume average of the 2^NDIM fine cells it
+// covers (pairwise means along x, then y, then z), on primitive variables;
+// stored as conserved values.  One work-group per ghost slot.
+template <int NDIM>
+__global__ __launch_bounds__(256) void smr_restrict_kernel(Geo g, const double* __restrict__ U,
+                                                           const int* __restrict__ side, double* __restrict__ gbuf,
+                                                           long long gcs, const GhostTask* __restrict__ tasks,
+                                                           Ctrl* ctrl) {
+    constexpr int NC = NDIM + 2;
+    constexpr int K = 1 << NDIM;
+    const GhostTask t = tasks[blockIdx.x];
+    int lo, hi;
+    transverse(t.ax, lo, hi);
+    const int nlo = g.n[lo], nhi = g.n[hi], face = nlo * nhi;
+    bool bad = false;
+    for (int q = threadIdx.x; q < 2 * face; q += blockDim.x) {
+        const int layer = q / face, r = q - layer * face;
+        const int tl = r % nlo, th = r / nlo;
+        double v[NC][K];
+#pragma unroll
+        for (int o = 0; o < K; ++o) {
+            int x3[3] = {0, 0, 0};
+            int cb[3] = {0, 0, 0};  // child offsets on the transverse axes
+#pragma unroll
+            for (int k = 0; k < NDIM; ++k) {
+                const int ax = active_axis<NDIM>(k);
+                const int off = (o >> k) & 1;
+                if (ax == t.ax) {
+                    // fine cells 2 layer, 2 layer + 1 in from the face (off 0: the lower)
+                    x3[ax] = t.s ? 2 * layer + off : g.n[ax] - 2 - 2 * layer + off;
+                } else {
+                    const int p = 2 * (ax == lo ? tl : th) + off;  // from the refined root's origin
+                    cb[ax] = p / g.n[ax];
+                    x3[ax] = p - cb[ax] * g.n[ax];
+                }
+            }
+            const int fb = t.src[cb[lo] + 2 * cb[hi]];
+            const Links L = table_links(side, fb);
+            double w[NC];
+            smr_prim<NDIM>(g, L, U, gbuf, gcs, fb, x3[0], x3[1], x3[2], w, bad);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) v[c][o] = w[c];
+        }
+        double w[NC], u[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            // pairwise means: along x first (bit 0), then y, then z
+#pragma unroll
+            for (int k = 0; k < NDIM; ++k)
+#pragma unroll
+                for (int i = 0; i < (K >> (k + 1)); ++i) v[c][i] = 0.5 * (v[c][2 * i] + v[c][2 * i + 1]);
+            w[c] = v[c][0];
+        }
+        prim_to_cons_cell<NDIM>(g.gamma, w, u);
+        const long long o = (long long)t.slot * NC * gcs + (long long)layer * face + r;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) gbuf[o + c * gcs] = u[c];
+    }
+    if (bad) atomicOr(&ctrl->flags, FLAG_NONPHYSICAL);
+}
+
+// Prolongation onto the two ghost layers of a fine block's side that faces a
+// coarser block: the coarse cell's value plus, per axis, a quarter of its
+// minmod-limited difference (eq. minmod), signed by the side of the coarse
+// centre the ghost's centre lies on; the coarse block's own ghosts (same
+// level, boundary rule, restricted slots) complete its stencil.  Primitive
+// variables; stored as conserved values.  One work-group per ghost slot.
+template <int NDIM>
+__global__ __launch_bounds__(256) void smr_prolong_kernel(Geo g, const double* __restrict__ U,
+                                                          const int* __restrict__ side, double* __restrict__ gbuf,
+                                                          long long gcs, const GhostTask* __restrict__ tasks,
+                                                          Ctrl* ctrl) {
+    constexpr int NC = NDIM + 2;
+    const GhostTask t = tasks[blockIdx.x];
+    int lo, hi;
+    transverse(t.ax, lo, hi);
+    const int nlo = g.n[lo], nhi = g.n[hi], face = nlo * nhi;
+    const int cblk = t.src[0];
+    const Links L = table_links(side, cblk);
+    bool bad = false;
+    for (int q = threadIdx.x; q < 2 * face; q += blockDim.x) {
+        const int layer = q / face, r = q - layer * face;
+        int ci[3] = {0, 0, 0};
+        double sg[3] = {0.0, 0.0, 0.0};
+        ci[t.ax] = t.s ? 0 : g.n[t.ax] - 1;
+        sg[t.ax] = t.s ? (layer == 0 ? -1.0 : 1.0) : (layer == 0 ? 1.0 : -1.0);
+        const int tl = r % nlo, th = r / nlo;
+#pragma unroll
+        for (int k = 0; k < NDIM; ++k) {
+            const int ax = active_axis<NDIM>(k);
+            if (ax == t.ax) continue;
+            const int p = t.child[ax] * g.n[ax] + (ax == lo ? tl : th);  // fine index from the parent's origin
+            ci[ax] = p >> 1;
+            sg[ax] = (p & 1) ? 1.0 : -1.0;
+        }
+        double wc[NC], acc[NC];
+        smr_prim<NDIM>(g, L, U, gbuf, gcs, cblk, ci[0], ci[1], ci[2], wc, bad);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = wc[c];
+#pragma unroll
+        for (int k = 0; k < NDIM; ++k) {
+            const int ax = active_axis<NDIM>(k);
+            int a3[3] = {ci[0], ci[1], ci[2]}, b3[3] = {ci[0], ci[1], ci[2]};
+            a3[ax] -= 1;
+            b3[ax] += 1;
+            double wl[NC], wh[NC];
+            smr_prim<NDIM>(g, L, U, gbuf, gcs, cblk, a3[0], a3[1], a3[2], wl, bad);
+            smr_prim<NDIM>(g, L, U, gbuf, gcs, cblk, b3[0], b3[1], b3[2], wh, bad);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[c] = acc[c] + (0.25 * sg[ax]) * minmod(wc[c] - wl[c], wh[c] - wc[c]);
+        }
+        double u[NC];
+        prim_to_cons_cell<NDIM>(g.gamma, acc, u);
+        const long long o = (long long)t.slot * NC * gcs + (long long)layer * face + r;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) gbuf[o + c * gcs] = u[c];
+    }
+    if (bad) atomicOr(&ctrl->flags, FLAG_NONPHYSICAL);
+}
+
+// Flux correction at the level jumps of kernel axis AX: each coarse cell next
+// to a face shared with finer blocks gets out += factor * lam * (F_coarse -
+// mean of the fine fluxes) (sign by side), so that its update uses the fine
+// fluxes' mean in place of its own.  The fluxes are recomputed from the same
+// stage input, ghosts and operations as in the stage kernel, so F_coarse
+// cancels exactly.  One work-group per coarse ghost slot of that axis.
+template <int NDIM, typename R, int AX>
+__global__ __launch_bounds__(256) void smr_reflux_kernel(Geo g0, Geo g1, const double* __restrict__ in,
+                                                         double* out, double factor, int use_device_dt,
+                                                         double dt_host, const int* __restrict__ side,
+                                                         const double* __restrict__ gbuf, long long gcs,
+                                                         const GhostTask* __restrict__ tasks, Ctrl* ctrl) {
+    constexpr int NC = NDIM + 2;
+    constexpr int NT = NDIM - 1;
+    if (use_device_dt && ctrl->done) return;  // uniform over the grid
+    const double dt = use_device_dt ? device_dt(ctrl) : dt_host;
+    const double lam = dt / g0.dx[AX];
+    const Gas<R> gr = make_gas<R>(g0.gamma);
+    const double gm1 = g0.gamma - 1.0;
+    const GhostTask t = tasks[blockIdx.x];
+    int lo, hi;
+    transverse(AX, lo, hi);
+    const int nlo = g0.n[lo], nhi = g0.n[hi], face = nlo * nhi;
+    const int n = g0.n[AX];
+    const Links Lc = table_links(side, t.leaf);
+    bool bad = false;
+    for (int r = threadIdx.x; r < face; r += blockDim.x) {
+        const int tl = r % nlo, th = r / nlo;
+        int x3[3] = {0, 0, 0};
+        x3[lo] = tl;
+        x3[hi] = th;
+        // the coarse face flux from the four coarse cells across it
+        R w[4][NC];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int c3[3] = {x3[0], x3[1], x3[2]};
+            c3[AX] = t.s ? n - 2 + j : -2 + j;
+            double u[NC];
+            int vax, vm;
+            smr_cell<NC>(g0, Lc, in, gbuf, gcs, t.leaf, c3[0], c3[1], c3[2], u, vax, vm);
+            in_to_w<NDIM, R, false>(gm1, u, vax, vm, w[j], bad);
+        }
+        R Fc[NC];
+        face_flux<NDIM, AX, R>(gr, w[0], w[1], w[2], w[3], Fc);
+        // the fine fluxes through it, by transverse child offsets
+        double Ff[NC][4];
+#pragma unroll
+        for (int o = 0; o < (1 << NT); ++o) {
+            int f3[3] = {0, 0, 0};
+            int cb[3] = {0, 0, 0};
+            int bit = 0;
+#pragma unroll
+            for (int k = 0; k < NDIM; ++k) {
+                const int ax = active_axis<NDIM>(k);
+                if (ax == AX) continue;
+                const int p = 2 * x3[ax] + ((o >> bit) & 1);
+                ++bit;
+                cb[ax] = p / g1.n[ax];
+                f3[ax] = p - cb[ax] * g1.n[ax];
+            }
+            const int fb = t.src[cb[lo] + 2 * cb[hi]];
+            const Links Lf = table_links(side, fb);
+            R v[4][NC];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                int c3[3] = {f3[0], f3[1], f3[2]};
+                c3[AX] = t.s ? -2 + j : g1.n[AX] - 2 + j;
+                double u[NC];
+                int vax, vm;
+                smr_cell<NC>(g1, Lf, in, gbuf, gcs, fb, c3[0], c3[1], c3[2], u, vax, vm);
+                in_to_w<NDIM, R, false>(gm1, u, vax, vm, v[j], bad);
+            }
+            R F[NC];
+            face_flux<NDIM, AX, R>(gr, v[0], v[1], v[2], v[3], F);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) Ff[c][o] = (double)F[c];
+        }
+        const long long N = g0.ncells;
+        int c3[3] = {x3[0], x3[1], x3[2]};
+        c3[AX] = t.s ? n - 1 : 0;
+        const long long cell = (long long)t.leaf * NC * N + ((long long)c3[2] * g0.n[1] + c3[1]) * g0.n[0] + c3[0];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+#pragma unroll
+            for (int k = 0; k < NT; ++k)
+#pragma unroll
+                for (int i = 0; i < ((1 << NT) >> (k + 1)); ++i) Ff[c][i] = 0.5 * (Ff[c][2 * i] + Ff[c][2 * i + 1]);
+            const double d = t.s ? ((double)Fc[c] - Ff[c][0]) : (Ff[c][0] - (double)Fc[c]);
+            out[cell + c * N] = out[cell + c * N] + factor * (lam * d);
+        }
     }
     if (bad) atomicOr(&ctrl->flags, FLAG_NONPHYSICAL);
 }
@@ -1609,16 +1980,21 @@ hipError_t launch_ctrl_batch(const MeshDesc* d, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_dt(const Geo& g, const double* U, Ctrl* ctrl, hipStream_t s) {
+hipError_t launch_dt_blocks(const Geo& g, const double* U, Ctrl* ctrl, int skip_done, hipStream_t s) {
     const int nblk = geo_nblk(g);
+    if (nblk < 1) return hipSuccess;
     const dim3 grid(grid_for(g.ncells, 256, (2048 + nblk - 1) / nblk), nblk);
     switch (g.ndim) {
-        case 1: hipLaunchKernelGGL(dt_kernel<1>, grid, dim3(256), 0, s, g, U, ctrl); break;
-        case 2: hipLaunchKernelGGL(dt_kernel<2>, grid, dim3(256), 0, s, g, U, ctrl); break;
-        case 3: hipLaunchKernelGGL(dt_kernel<3>, grid, dim3(256), 0, s, g, U, ctrl); break;
+        case 1: hipLaunchKernelGGL(dt_kernel<1>, grid, dim3(256), 0, s, g, U, ctrl, skip_done); break;
+        case 2: hipLaunchKernelGGL(dt_kernel<2>, grid, dim3(256), 0, s, g, U, ctrl, skip_done); break;
+        case 3: hipLaunchKernelGGL(dt_kernel<3>, grid, dim3(256), 0, s, g, U, ctrl, skip_done); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_dt(const Geo& g, const double* U, Ctrl* ctrl, hipStream_t s) {
+    return launch_dt_blocks(g, U, ctrl, 0, s);
 }
 
 hipError_t launch_ctrl(Ctrl* c, int op, double a0, double a1, double cfl, hipStream_t s) {
@@ -1692,6 +2068,67 @@ hipError_t launch_padded_prim(const Geo& g, int precision, const double* U, doub
     }
 #undef PP
     return hipGetLastError();
+}
+
+hipError_t launch_smr_restrict(const Geo& g, const double* U, const int* side, double* gbuf, long long gcs,
+                               const GhostTask* tasks, int n, Ctrl* ctrl, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    switch (g.ndim) {
+        case 1: hipLaunchKernelGGL(smr_restrict_kernel<1>, dim3(n), dim3(256), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
+        case 2: hipLaunchKernelGGL(smr_restrict_kernel<2>, dim3(n), dim3(256), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
+        case 3: hipLaunchKernelGGL(smr_restrict_kernel<3>, dim3(n), dim3(256), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_smr_prolong(const Geo& g, const double* U, const int* side, double* gbuf, long long gcs,
+                              const GhostTask* tasks, int n, Ctrl* ctrl, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    switch (g.ndim) {
+        case 1: hipLaunchKernelGGL(smr_prolong_kernel<1>, dim3(n), dim3(256), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
+        case 2: hipLaunchKernelGGL(smr_prolong_kernel<2>, dim3(n), dim3(256), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
+        case 3: hipLaunchKernelGGL(smr_prolong_kernel<3>, dim3(n), dim3(256), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int NDIM, typename R>
+hipError_t reflux_t(int ax, const Geo& g0, const Geo& g1, const double* in, double* out, double factor, int ud,
+                    double dth, const int* side, const double* gbuf, long long gcs, const GhostTask* tasks, int n,
+                    Ctrl* ctrl, hipStream_t s) {
+#define RF(AXV) hipLaunchKernelGGL((smr_reflux_kernel<NDIM, R, AXV>), dim3(n), dim3(256), 0, s, g0, g1, in, out, \
+                                   factor, ud, dth, side, gbuf, gcs, tasks, ctrl)
+    if (ax == 0) {
+        RF(0);
+    } else if (NDIM == 3 && ax == 1) {
+        RF(1);
+    } else if (NDIM >= 2 && ax == 2) {
+        RF(2);
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef RF
+    return hipGetLastError();
+}
+
+hipError_t launch_smr_reflux(int precision, int ax, const Geo& g0, const Geo& g1, const double* in, double* out,
+                             double factor, int use_device_dt, double dt_host, const int* side,
+                             const double* gbuf, long long gcs, const GhostTask* tasks, int n, Ctrl* ctrl,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+#define RFD(ND) (precision == 0 ? reflux_t<ND, double>(ax, g0, g1, in, out, factor, use_device_dt, dt_host, side, \
+                                                       gbuf, gcs, tasks, n, ctrl, s)                              \
+                                : reflux_t<ND, float>(ax, g0, g1, in, out, factor, use_device_dt, dt_host, side,  \
+                                                      gbuf, gcs, tasks, n, ctrl, s))
+    switch (g0.ndim) {
+        case 1: return RFD(1);
+        case 2: return RFD(2);
+        case 3: return RFD(3);
+        default: return hipErrorInvalidValue;
+    }
+#undef RFD
 }
 
 hipError_t launch_riemann(int precision, int ntan, double gamma, long long n, const double* WL,

@@ -30,6 +30,16 @@ struct hydro_ctx {
     hipEvent_t ev_join[kBlockStreams];
     hipEvent_t* ev_s1;             // per block: its stage 1 has finished
     int* nbr;                      // per block: up to 6 distinct face neighbours, -1 padded
+    // static refinement (two levels; leaves of level 0, then of level 1)
+    bool smr;
+    int lev_start[2], lev_count[2];
+    Geo lgeo[2];                   // per level: one block's extents and the level's cell widths
+    int* d_side;                   // 6 side codes per leaf
+    GhostTask* d_tasks;            // restriction slots by kernel axis, then prolongation slots
+    int nres, npro, res_off[4];
+    double* gbuf;
+    long long gcs;
+    int32_t* leaves;               // host: (level, c0, c1, c2) per leaf
     Tile tile[2];  // stage 1 (and the rhs), stage 2
     hipStream_t stream;
     int ncomp;
@@ -176,6 +186,9 @@ StageArgs stage_args(hydro_t h) {
     a.blk0 = 0;
     a.nblk = h->nblk;
     a.conc = h->nblk;
+    a.side = h->smr ? h->d_side : nullptr;
+    a.gbuf = h->gbuf;
+    a.gcs = h->gcs;
     return a;
 }
 
@@ -309,6 +322,10 @@ hipError_t enqueue_step_streams(hydro_t h, bool device_dt, double dt) {
     return launch_ctrl(h->ctrl, CTRL_ADVANCE_T, dt, 0.0, h->cfg.cfl, h->stream);
 }
 
+// Whether host transfers convert between the mesh layout and the block
+// layout: a split mesh; a refined mesh's transfers use the block layout.
+bool mesh_relayout(hydro_t h) { return h->nblk > 1 && !h->smr; }
+
 // Mesh-layout buffer on the handle's stream for a split mesh's transfers.
 hipError_t mesh_tmp(hydro_t h, double** d) {
     return hipMallocAsync((void**)d, (size_t)h->ncomp * h->geo.ncells * h->nblk * sizeof(double), h->stream);
@@ -337,7 +354,52 @@ hipError_t timed_stage(hydro_t h, int mode, const StageArgs& a) {
 // One step: stage 1 (Heun: U1 = U^n + dt L(U^n); van Leer: the predicted
 // primitive state) then stage 2 in place over U^n, dt either from the host or
 // from the device control block (clamped to the run limit kept there).
+// One step of a refined mesh (Heun).  Each stage: the ghost slots of the
+// level jumps from the stage input (restriction, then prolongation, which
+// reads the restricted slots), the stage kernel per level, then the flux
+// correction of the coarse cells at the level jumps, axis by axis (a cell
+// next to two jumps is corrected once per axis, in order).  The CFL rate of
+// the corrected state is a reduction of its own.
+hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
+    hipError_t e = hipSuccess;
+    const long long BS = (long long)h->ncomp * h->geo.ncells;
+    for (int st = 0; st < 2 && e == hipSuccess; ++st) {
+        const double* in = st == 0 ? h->U : h->U1;
+        double* out = st == 0 ? h->U1 : h->U;
+        e = launch_smr_restrict(h->lgeo[0], in, h->d_side, h->gbuf, h->gcs, h->d_tasks, h->nres, h->ctrl, h->stream);
+        if (e == hipSuccess)
+            e = launch_smr_prolong(h->lgeo[0], in, h->d_side, h->gbuf, h->gcs, h->d_tasks + h->nres, h->npro,
+                                   h->ctrl, h->stream);
+        for (int lev = 0; lev < 2 && e == hipSuccess; ++lev) {
+            if (h->lev_count[lev] == 0) continue;
+            StageArgs a = stage_args(h);
+            a.geo = h->lgeo[lev];
+            a.blk0 = h->lev_start[lev];
+            a.nblk = a.conc = h->lev_count[lev];
+            a.use_device_dt = device_dt ? 1 : 0;
+            a.dt_host = dt;
+            a.in = in;
+            a.base = h->U;
+            a.out = out;
+            a.want_dt = 0;
+            e = timed_stage(h, st == 0 ? MODE_STAGE1 : MODE_STAGE2, a);
+        }
+        for (int ax = 0; ax < 3 && e == hipSuccess; ++ax)
+            e = launch_smr_reflux(h->cfg.precision, ax, h->lgeo[0], h->lgeo[1], in, out, st == 0 ? 1.0 : 0.5,
+                                  device_dt ? 1 : 0, dt, h->d_side, h->gbuf, h->gcs, h->d_tasks + h->res_off[ax],
+                                  h->res_off[ax + 1] - h->res_off[ax], h->ctrl, h->stream);
+    }
+    if (e != hipSuccess) return e;
+    if (!device_dt) return launch_ctrl(h->ctrl, CTRL_ADVANCE_T, dt, 0.0, h->cfg.cfl, h->stream);
+    for (int lev = 0; lev < 2 && e == hipSuccess; ++lev)
+        if (h->lev_count[lev] > 0)
+            e = launch_dt_blocks(h->lgeo[lev], h->U + h->lev_start[lev] * BS, h->ctrl, 1, h->stream);
+    if (e != hipSuccess) return e;
+    return launch_ctrl(h->ctrl, CTRL_FINALIZE_STEP, 0.0, 0.0, h->cfg.cfl, h->stream);
+}
+
 hipError_t enqueue_step(hydro_t h, bool device_dt, double dt) {
+    if (h->smr) return enqueue_step_smr(h, device_dt, dt);
     if (h->block_streams && h->nblk > 1) return enqueue_step_streams(h, device_dt, dt);
     StageArgs a = stage_args(h);
     a.use_device_dt = device_dt ? 1 : 0;
@@ -359,10 +421,190 @@ hipError_t enqueue_step(hydro_t h, bool device_dt, double dt) {
 
 hipError_t enqueue_dt(hydro_t h) {
     hipError_t e = launch_ctrl(h->ctrl, CTRL_RESET_MIN, 0.0, 0.0, h->cfg.cfl, h->stream);
-    if (e == hipSuccess) e = launch_dt(h->geo, h->U, h->ctrl, h->stream);
+    if (h->smr) {
+        const long long BS = (long long)h->ncomp * h->geo.ncells;
+        for (int lev = 0; lev < 2 && e == hipSuccess; ++lev)
+            if (h->lev_count[lev] > 0)
+                e = launch_dt_blocks(h->lgeo[lev], h->U + h->lev_start[lev] * BS, h->ctrl, 0, h->stream);
+    } else if (e == hipSuccess) {
+        e = launch_dt(h->geo, h->U, h->ctrl, h->stream);
+    }
     if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_FINALIZE_DT, 0.0, 0.0, h->cfg.cfl, h->stream);
     if (e == hipSuccess) h->dt_valid = true;
     return e;
+}
+
+// ------------------------------------------------------- static refinement
+
+// Leaves, side codes and ghost slots of a two-level refinement of the block
+// grid of cfg: the listed root blocks are each replaced by 2^ndim blocks of
+// half their size and the same extents in cells.  Leaves: level 0 in root
+// order, then level 1 in the order of the level-1 block grid (x fastest).
+struct SmrPlan {
+    int nleaf = 0;
+    std::vector<int32_t> leaves;  // (level, c0, c1, c2), physical axes
+    std::vector<int> side;        // 6 per leaf, kernel axes
+    std::vector<GhostTask> tasks;
+    int nres = 0, npro = 0, res_off[4] = {0, 0, 0, 0};
+    int lev_start[2] = {0, 0}, lev_count[2] = {0, 0};
+    long long gcs = 0;
+};
+
+bool smr_plan(const hydro_config* c, int nref, const int32_t* refined, SmrPlan& P) {
+    if (!config_ok(c) || c->integrator != HYDRO_HEUN || nref < 0 || (nref > 0 && !refined)) return false;
+    const int nd = c->ndim;
+    int B[3], nb[3];
+    for (int d = 0; d < 3; ++d) {
+        B[d] = blocks_of(c, d);
+        nb[d] = c->n[d] / B[d];
+        // a refined block's children align with its cells, and the two
+        // restricted ghost layers of a coarse side cover four fine layers
+        if (nref > 0 && d < nd && (nb[d] % 2 != 0 || nb[d] < 4)) return false;
+    }
+    const int nroot = B[0] * B[1] * B[2];
+    std::vector<char> ref(nroot, 0);
+    for (int r = 0; r < nref; ++r) {
+        if (refined[r] < 0 || refined[r] >= nroot || ref[refined[r]]) return false;
+        ref[refined[r]] = 1;
+    }
+    int E[3];  // level-1 block grid
+    for (int d = 0; d < 3; ++d) E[d] = d < nd ? 2 * B[d] : 1;
+    const long long n1 = (long long)E[0] * E[1] * E[2];
+    std::vector<int> look0(nroot, -1), look1(n1, -1);
+    for (int r = 0; r < nroot; ++r) {
+        if (ref[r]) continue;
+        look0[r] = (int)(P.leaves.size() / 4);
+        P.leaves.insert(P.leaves.end(), {0, r % B[0], (r / B[0]) % B[1], r / (B[0] * B[1])});
+    }
+    P.lev_count[0] = (int)(P.leaves.size() / 4);
+    for (long long f = 0; f < n1; ++f) {
+        const int x = (int)(f % E[0]), y = (int)((f / E[0]) % E[1]), z = (int)(f / ((long long)E[0] * E[1]));
+        auto half = [&](int v, int d) { return d < nd ? v / 2 : 0; };
+        const int r = half(x, 0) + B[0] * (half(y, 1) + B[1] * half(z, 2));
+        if (!ref[r]) continue;
+        look1[f] = (int)(P.leaves.size() / 4);
+        P.leaves.insert(P.leaves.end(), {1, x, y, z});
+    }
+    P.nleaf = (int)(P.leaves.size() / 4);
+    P.lev_start[1] = P.lev_count[0];
+    P.lev_count[1] = P.nleaf - P.lev_count[0];
+    if (P.nleaf > kMaxBlocks) return false;
+    const int kmap[3] = {0, nd == 3 ? 1 : -1, nd == 3 ? 2 : (nd == 2 ? 1 : -1)};  // kernel -> physical axis
+    auto leaf_at = [&](int L, const int* c3) -> int {
+        if (L == 0) return look0[c3[0] + B[0] * (c3[1] + B[1] * c3[2])];
+        return look1[c3[0] + (long long)E[0] * (c3[1] + (long long)E[1] * c3[2])];
+    };
+    // sides: what lies across (physical axis d, side s) of leaf b
+    enum { PHYS, SAME, COARSE, FINE };
+    auto across = [&](int b, int d, int s, int& idx, int* root) -> int {
+        const int L = P.leaves[4 * b];
+        int c3[3] = {P.leaves[4 * b + 1], P.leaves[4 * b + 2], P.leaves[4 * b + 3]};
+        const int ext = (d < nd ? B[d] : 1) << L;
+        int q = c3[d] + (s ? 1 : -1);
+        if (q < 0 || q >= ext) {
+            if (c->bc[d][s] != HYDRO_BC_PERIODIC) return PHYS;
+            q = (q + ext) % ext;
+        }
+        c3[d] = q;
+        idx = leaf_at(L, c3);
+        if (idx >= 0) return SAME;
+        if (L == 1) {
+            int p3[3];
+            for (int e = 0; e < 3; ++e) p3[e] = e < nd ? c3[e] / 2 : 0;
+            idx = leaf_at(0, p3);
+            return COARSE;
+        }
+        for (int e = 0; e < 3; ++e) root[e] = c3[e];
+        return FINE;
+    };
+    P.side.assign(6 * (size_t)P.nleaf, 0);
+    std::vector<GhostTask> res[3], pro;
+    std::vector<std::pair<int, int>> res_at[3], pro_at;  // (leaf, side index) owning each task
+    for (int b = 0; b < P.nleaf; ++b) {
+        for (int k = 0; k < 3; ++k) {
+            for (int s = 0; s < 2; ++s) {
+                int& code = P.side[6 * b + 2 * k + s];
+                const int d = kmap[k];
+                if (d < 0) {
+                    code = b;  // inactive axis: never read
+                    continue;
+                }
+                int idx = -1, root[3] = {0, 0, 0};
+                const int kind = across(b, d, s, idx, root);
+                if (kind == PHYS) {
+                    code = kSidePhys;
+                } else if (kind == SAME) {
+                    code = idx;
+                } else {
+                    GhostTask t;
+                    std::memset(&t, 0, sizeof(t));
+                    t.leaf = b;
+                    t.ax = k;
+                    t.s = s;
+                    const int lo = k == 0 ? 1 : 0, hi = k == 2 ? 1 : 2;
+                    if (kind == FINE) {
+                        t.kind = 0;
+                        for (int o = 0; o < 4; ++o) {
+                            int f3[3];
+                            for (int e = 0; e < 3; ++e) f3[e] = 0;
+                            f3[d] = s ? 2 * root[d] : 2 * root[d] + 1;
+                            const int bits[2] = {o & 1, (o >> 1) & 1};
+                            const int tax[2] = {lo, hi};
+                            for (int q = 0; q < 2; ++q) {
+                                const int e = kmap[tax[q]];
+                                if (e >= 0) f3[e] = 2 * root[e] + bits[q];
+                            }
+                            t.src[o] = leaf_at(1, f3);
+                            if (t.src[o] < 0) return false;
+                        }
+                        res[k].push_back(t);
+                        res_at[k].push_back({b, 2 * k + s});
+                    } else {
+                        t.kind = 1;
+                        t.src[0] = idx;
+                        for (int q = 0; q < 3; ++q) t.child[q] = kmap[q] >= 0 ? P.leaves[4 * b + 1 + kmap[q]] % 2 : 0;
+                        if (idx < 0) return false;
+                        pro.push_back(t);
+                        pro_at.push_back({b, 2 * k + s});
+                    }
+                }
+            }
+        }
+    }
+    for (int k = 0; k < 3; ++k) {
+        P.res_off[k] = (int)P.tasks.size();
+        for (size_t i = 0; i < res[k].size(); ++i) {
+            res[k][i].slot = (int)P.tasks.size();
+            P.side[6 * res_at[k][i].first + res_at[k][i].second] = kSideSlot0 - res[k][i].slot;
+            P.tasks.push_back(res[k][i]);
+        }
+    }
+    P.res_off[3] = P.nres = (int)P.tasks.size();
+    for (size_t i = 0; i < pro.size(); ++i) {
+        pro[i].slot = (int)P.tasks.size();
+        P.side[6 * pro_at[i].first + pro_at[i].second] = kSideSlot0 - pro[i].slot;
+        P.tasks.push_back(pro[i]);
+    }
+    P.npro = (int)pro.size();
+    // slot component stride: both layers of the largest side
+    long long face = 1;
+    const int nk[3] = {nb[kmap[0]], kmap[1] >= 0 ? nb[kmap[1]] : 1, kmap[2] >= 0 ? nb[kmap[2]] : 1};
+    for (int k = 0; k < 3; ++k)
+        if (kmap[k] >= 0) {
+            const int lo = k == 0 ? 1 : 0, hi = k == 2 ? 1 : 2;
+            face = std::max(face, (long long)nk[lo] * nk[hi]);
+        }
+    P.gcs = 2 * face;
+    return true;
+}
+
+size_t smr_bytes(const hydro_config* c, const SmrPlan& P) {
+    const size_t nc = (size_t)c->ndim + 2;
+    const size_t cells = (size_t)ncells_of(c) / ((size_t)blocks_of(c, 0) * blocks_of(c, 1) * blocks_of(c, 2));
+    const size_t field = align_up(nc * cells * (size_t)P.nleaf * sizeof(double));
+    return 2 * field + align_up(sizeof(Ctrl)) + align_up((size_t)kTotalsParts * kMaxComp * 2 * sizeof(double)) +
+           align_up(P.side.size() * sizeof(int)) + align_up(P.tasks.size() * sizeof(GhostTask)) +
+           align_up(P.tasks.size() * nc * (size_t)P.gcs * sizeof(double));
 }
 
 }  // namespace
@@ -417,13 +659,109 @@ int hydro_create(const hydro_config* cfg, void* d_workspace, size_t nbytes, void
     return HYDRO_OK;
 }
 
+size_t hydro_smr_workspace_bytes(const hydro_config* cfg, int nref, const int32_t* refined) {
+    SmrPlan P;
+    if (!smr_plan(cfg, nref, refined, P)) return 0;
+    return smr_bytes(cfg, P);
+}
+
+int hydro_smr_create(const hydro_config* cfg, int nref, const int32_t* refined, void* d_workspace, size_t nbytes,
+                     void* hip_stream, hydro_t* out) {
+    SmrPlan P;
+    if (!out || !d_workspace || !smr_plan(cfg, nref, refined, P)) return HYDRO_E_INVAL;
+    if (((uintptr_t)d_workspace) % kAlign != 0 || nbytes < smr_bytes(cfg, P)) return HYDRO_E_INVAL;
+    hydro_ctx* h = new (std::nothrow) hydro_ctx;
+    if (!h) return HYDRO_E_NOMEM;
+    std::memset(h, 0, sizeof(*h));
+    h->leaves = new (std::nothrow) int32_t[P.leaves.size()];
+    if (!h->leaves) {
+        delete h;
+        return HYDRO_E_NOMEM;
+    }
+    std::memcpy(h->leaves, P.leaves.data(), P.leaves.size() * sizeof(int32_t));
+    h->cfg = *cfg;
+    h->smr = true;
+    h->geo = make_geo(cfg);
+    h->nblk = P.nleaf;
+    h->geo.blocks[0] = P.nleaf;  // the leaves as a row of blocks (per-cell passes)
+    h->geo.blocks[1] = h->geo.blocks[2] = 1;
+    for (int lev = 0; lev < 2; ++lev) {
+        Geo g = h->geo;
+        for (int k = 0; k < 3; ++k) {
+            const bool active = k == 0 || (k == 1 && cfg->ndim == 3) || (k == 2 && cfg->ndim >= 2);
+            if (!active) continue;
+            g.dx[k] = lev ? 0.5 * h->geo.dx[k] : h->geo.dx[k];
+            g.inv_dx[k] = 1.0 / g.dx[k];
+        }
+        g.blocks[0] = P.lev_count[lev];
+        h->lgeo[lev] = g;
+        h->lev_start[lev] = P.lev_start[lev];
+        h->lev_count[lev] = P.lev_count[lev];
+    }
+    h->tile[0] = default_tile(h->geo, cfg->precision, MODE_STAGE1);
+    h->tile[1] = default_tile(h->geo, cfg->precision, MODE_STAGE2);
+    h->stream = (hipStream_t)hip_stream;
+    h->ncomp = cfg->ndim + 2;
+    h->dV = 1.0;
+    for (int d = 0; d < cfg->ndim; ++d) h->dV *= (cfg->hi[d] - cfg->lo[d]) / cfg->n[d];
+    h->nres = P.nres;
+    h->npro = P.npro;
+    for (int k = 0; k < 4; ++k) h->res_off[k] = P.res_off[k];
+    h->gcs = P.gcs;
+    const size_t nc = (size_t)h->ncomp;
+    const size_t field = align_up(nc * (size_t)h->geo.ncells * P.nleaf * sizeof(double));
+    char* p = (char*)d_workspace;
+    h->U = (double*)p;
+    p += field;
+    h->U1 = (double*)p;
+    p += field;
+    h->ctrl = (Ctrl*)p;
+    p += align_up(sizeof(Ctrl));
+    h->parts = (double*)p;
+    p += align_up((size_t)kTotalsParts * kMaxComp * 2 * sizeof(double));
+    h->d_side = (int*)p;
+    p += align_up(P.side.size() * sizeof(int));
+    h->d_tasks = (GhostTask*)p;
+    p += align_up(P.tasks.size() * sizeof(GhostTask));
+    h->gbuf = (double*)p;
+    if (hipHostMalloc((void**)&h->host_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+        delete[] h->leaves;
+        delete h;
+        return HYDRO_E_NOMEM;
+    }
+    hipError_t e = hipMemsetAsync(h->U, 0, 2 * field, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->d_side, P.side.data(), P.side.size() * sizeof(int), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && !P.tasks.empty())
+        e = hipMemcpyAsync(h->d_tasks, P.tasks.data(), P.tasks.size() * sizeof(GhostTask), hipMemcpyHostToDevice,
+                           h->stream);
+    if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_INIT, 0.0, 0.0, cfg->cfl, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // the plan's host vectors end here
+    if (e != hipSuccess) {
+        (void)hipHostFree(h->host_ctrl);
+        delete[] h->leaves;
+        delete h;
+        return HYDRO_E_DEVICE;
+    }
+    *out = h;
+    return HYDRO_OK;
+}
+
+int hydro_smr_leaves(const hydro_config* cfg, int nref, const int32_t* refined, int32_t* leaves, int max) {
+    SmrPlan P;
+    if (max < 0 || (max > 0 && !leaves) || !smr_plan(cfg, nref, refined, P)) return HYDRO_E_INVAL;
+    for (int b = 0; b < P.nleaf && b < max; ++b)
+        for (int q = 0; q < 4; ++q) leaves[4 * b + q] = P.leaves[4 * b + q];
+    return P.nleaf;
+}
+
 int hydro_set_state(hydro_t h, const double* U_host) {
     int rc = usable(h);
     if (rc) return rc;
     if (!U_host) return HYDRO_E_INVAL;
     const size_t bytes = (size_t)h->ncomp * h->geo.ncells * h->nblk * sizeof(double);
     hipError_t e = hipSuccess;
-    if (h->nblk == 1) {
+    if (!mesh_relayout(h)) {
         e = hipMemcpyAsync(h->U, U_host, bytes, hipMemcpyHostToDevice, h->stream);
     } else {
         double* tmp = nullptr;
@@ -446,7 +784,7 @@ int hydro_set_primitive(hydro_t h, const double* W_host) {
     // staged in U itself (through a mesh-layout buffer for a split mesh) and
     // converted in place
     hipError_t e = hipSuccess;
-    if (h->nblk == 1) {
+    if (!mesh_relayout(h)) {
         e = hipMemcpyAsync(h->U, W_host, bytes, hipMemcpyHostToDevice, h->stream);
     } else {
         double* tmp = nullptr;
@@ -467,7 +805,7 @@ int hydro_set_primitive_device(hydro_t h, const double* d_W) {
     if (rc) return rc;
     if (!d_W) return HYDRO_E_INVAL;
     hipError_t e = hipSuccess;
-    if (h->nblk == 1) {
+    if (!mesh_relayout(h)) {
         e = launch_prim_to_cons(h->geo, d_W, h->U, h->stream);
     } else {
         // only read: the relayout writes the block layout into U
@@ -483,8 +821,8 @@ int hydro_get_state_device(hydro_t h, double* d_U) {
     int rc = usable(h);
     if (rc) return rc;
     if (!d_U) return HYDRO_E_INVAL;
-    const size_t bytes = (size_t)h->ncomp * h->geo.ncells * sizeof(double);
-    if (h->nblk > 1) return fail(h, launch_relayout(h->geo, d_U, h->U, 0, h->stream));
+    const size_t bytes = (size_t)h->ncomp * h->geo.ncells * h->nblk * sizeof(double);
+    if (mesh_relayout(h)) return fail(h, launch_relayout(h->geo, d_U, h->U, 0, h->stream));
     return fail(h, hipMemcpyAsync(d_U, h->U, bytes, hipMemcpyDeviceToDevice, h->stream));
 }
 
@@ -494,7 +832,7 @@ int hydro_get_state(hydro_t h, double* U_host) {
     if (!U_host) return HYDRO_E_INVAL;
     const size_t bytes = (size_t)h->ncomp * h->geo.ncells * h->nblk * sizeof(double);
     hipError_t e = hipSuccess;
-    if (h->nblk == 1) {
+    if (!mesh_relayout(h)) {
         e = hipMemcpyAsync(U_host, h->U, bytes, hipMemcpyDeviceToHost, h->stream);
     } else {
         double* tmp = nullptr;
@@ -570,6 +908,23 @@ int hydro_conserved_totals(hydro_t h, double* totals) {
     int rc = usable(h);
     if (rc) return rc;
     if (!totals) return HYDRO_E_INVAL;
+    if (h->smr) {
+        // per level (its own cell volume), then summed
+        const long long BS = (long long)h->ncomp * h->geo.ncells;
+        for (int c = 0; c < h->ncomp; ++c) totals[c] = 0.0;
+        double dV = h->dV;
+        for (int lev = 0; lev < 2; ++lev, dV *= 1.0 / (1 << h->cfg.ndim)) {
+            if (h->lev_count[lev] == 0) continue;
+            hipError_t e = launch_totals(h->lgeo[lev], h->U + h->lev_start[lev] * BS, h->parts, kTotalsParts,
+                                         h->ctrl, h->stream);
+            if (e != hipSuccess) return fail(h, e);
+            rc = read_ctrl(h);
+            if (rc && rc != HYDRO_E_NONPHYSICAL) return rc;
+            for (int c = 0; c < h->ncomp; ++c)
+                totals[c] += dV * (h->host_ctrl->sums[2 * c] + h->host_ctrl->sums[2 * c + 1]);
+        }
+        return rc;
+    }
     hipError_t e = launch_totals(h->geo, h->U, h->parts, kTotalsParts, h->ctrl, h->stream);
     if (e != hipSuccess) return fail(h, e);
     rc = read_ctrl(h);
@@ -602,6 +957,7 @@ int hydro_steps_done(hydro_t h, int64_t* steps) {
 int hydro_stage_rhs(hydro_t h, double dt, double* dU_host) {
     int rc = usable(h);
     if (rc) return rc;
+    if (h->smr) return HYDRO_E_INVAL;
     if (!dU_host || !(dt > 0.0) || !std::isfinite(dt)) return HYDRO_E_INVAL;
     StageArgs a = stage_args(h);
     a.dt_host = dt;
@@ -632,6 +988,7 @@ int hydro_stage_rhs(hydro_t h, double dt, double* dU_host) {
 int hydro_padded_primitive(hydro_t h, double* Wpad_host) {
     int rc = usable(h);
     if (rc) return rc;
+    if (h->smr) return HYDRO_E_INVAL;
     if (!Wpad_host) return HYDRO_E_INVAL;
     size_t total = (size_t)h->ncomp;
     for (int d = 0; d < 3; ++d) total *= (size_t)(h->cfg.n[d] + (d < h->cfg.ndim ? 4 : 0));
@@ -678,6 +1035,7 @@ int hydro_get_stage_tile(hydro_t h, int stage, int* tx, int* ty, int* kz) {
 int hydro_autotune(hydro_t h, int steps_per_tile, double t_end, int* tiles, double* ms_per_step) {
     int rc = usable(h);
     if (rc) return rc;
+    if (h->smr) return HYDRO_E_INVAL;
     if (steps_per_tile < 1 || steps_per_tile > 64 || !(t_end >= 0.0) || !std::isfinite(t_end) || !tiles ||
         !ms_per_step)
         return HYDRO_E_INVAL;
@@ -833,7 +1191,7 @@ int hydro_profile_read(hydro_t h, double* ms_stage1, double* ms_stage2, int64_t*
 int hydro_set_block_streams(hydro_t h, int on) {
     int rc = usable(h);
     if (rc) return rc;
-    if (on != 0 && on != 1) return HYDRO_E_INVAL;
+    if ((on != 0 && on != 1) || (on && h->smr)) return HYDRO_E_INVAL;
     if (on && h->nblk > 1) {
         // streams made while no work of this handle is in flight
         hipError_t e = hipStreamSynchronize(h->stream);
@@ -850,6 +1208,7 @@ int hydro_destroy(hydro_t h) {
     if (!h->broken) (void)hipStreamSynchronize(h->stream);
     block_streams_free(h);
     profile_free(h);
+    delete[] h->leaves;
     (void)hipHostFree(h->host_ctrl);
     delete h;
     return HYDRO_OK;

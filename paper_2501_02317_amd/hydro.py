@@ -48,6 +48,11 @@ _SIG = {
     "hydro_get_state_device": (C.c_int, [_h, _vp]),
     "hydro_state_device": (C.c_int, [_h, C.POINTER(_vp)]),
     "hydro_set_block_streams": (C.c_int, [_h, C.c_int]),
+    "hydro_smr_workspace_bytes": (C.c_size_t, [C.POINTER(Config), C.c_int, C.POINTER(C.c_int32)]),
+    "hydro_smr_create": (C.c_int, [C.POINTER(Config), C.c_int, C.POINTER(C.c_int32), _vp, C.c_size_t, _vp,
+                                   C.POINTER(_h)]),
+    "hydro_smr_leaves": (C.c_int, [C.POINTER(Config), C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                   C.c_int]),
     "hydro_cfl_dt": (C.c_int, [_h, _dp]),
     "hydro_step": (C.c_int, [_h, C.c_double]),
     "hydro_step_auto": (C.c_int, [_h, C.c_int, C.c_double]),
@@ -125,8 +130,26 @@ def make_config(n, gamma, cfl, precision=FP64, lo=None, hi=None, bc=None, integr
     return cfg
 
 
-def workspace_bytes(cfg):
+def workspace_bytes(cfg, refined=None):
+    if refined is not None:
+        r = _refined_arr(refined)
+        return int(_lib.hydro_smr_workspace_bytes(C.byref(cfg), len(refined), r))
     return int(_lib.hydro_workspace_bytes(C.byref(cfg)))
+
+
+def _refined_arr(refined):
+    return (C.c_int32 * max(1, len(refined)))(*[int(r) for r in refined])
+
+
+def smr_leaves(cfg, refined):
+    """(level, c0, c1, c2) per leaf of a two-level refinement of cfg's blocks."""
+    r = _refined_arr(refined)
+    cap = 1 << 12
+    out = (C.c_int32 * (4 * cap))()
+    n = _lib.hydro_smr_leaves(C.byref(cfg), len(refined), r, out, cap)
+    if n < 0:
+        raise HydroError(n, "invalid refinement")
+    return np.array(out[: 4 * n], dtype=np.int32).reshape(n, 4)
 
 
 def _ptr(a):
@@ -140,19 +163,25 @@ class Hydro:
     """
 
     def __init__(self, n, gamma, cfl, precision=FP64, lo=None, hi=None, bc=None, device=None,
-                 stream=None, workspace=None, integrator=HEUN, blocks=None):
+                 stream=None, workspace=None, integrator=HEUN, blocks=None, refined=None):
         import torch
 
         self.cfg = make_config(n, gamma, cfl, precision, lo, hi, bc, integrator, blocks)
         self.integrator = int(integrator)
-        self.blocks = tuple(self.cfg.blocks[d] for d in range(len(n)))
+        self.blocks = tuple(max(1, self.cfg.blocks[d]) for d in range(len(n)))
+        self.refined = None if refined is None else [int(r) for r in refined]
         self.ndim = len(n)
         self.n = tuple(int(v) for v in n)
         self.precision = int(precision)
         self.ncomp = self.ndim + 2
         nn = list(n) + [1] * (3 - len(n))
         self.shape = (self.ncomp, nn[2], nn[1], nn[0])
-        nbytes = workspace_bytes(self.cfg)
+        if self.refined is not None:
+            # a refined mesh: fields in the block layout of its leaves
+            self.leaves = smr_leaves(self.cfg, self.refined)
+            b = list(self.blocks) + [1] * (3 - len(self.blocks))
+            self.shape = (len(self.leaves), self.ncomp, nn[2] // b[2], nn[1] // b[1], nn[0] // b[0])
+        nbytes = workspace_bytes(self.cfg, self.refined)
         if nbytes == 0:
             raise HydroError(E_INVAL, "invalid configuration")
         if workspace is not None:
@@ -168,8 +197,13 @@ class Hydro:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         h = _h()
-        _check(_lib.hydro_create(C.byref(self.cfg), _vp(self.workspace.data_ptr()), nbytes,
-                                 _vp(stream.cuda_stream), C.byref(h)), "hydro_create")
+        if self.refined is not None:
+            _check(_lib.hydro_smr_create(C.byref(self.cfg), len(self.refined), _refined_arr(self.refined),
+                                         _vp(self.workspace.data_ptr()), nbytes, _vp(stream.cuda_stream),
+                                         C.byref(h)), "hydro_smr_create")
+        else:
+            _check(_lib.hydro_create(C.byref(self.cfg), _vp(self.workspace.data_ptr()), nbytes,
+                                     _vp(stream.cuda_stream), C.byref(h)), "hydro_create")
         self._h = h
 
     # ---- state
@@ -209,7 +243,7 @@ class Hydro:
         n = int(np.prod(self.shape))
         v = self.workspace[off: off + 8 * n].view(torch.float64)
         nb = int(np.prod(self.blocks))
-        if nb == 1:
+        if nb == 1 or self.refined is not None:
             return v.view(self.shape)
         b = list(self.blocks) + [1] * (3 - len(self.blocks))
         return v.view(nb, self.ncomp, self.shape[1] // b[2], self.shape[2] // b[1], self.shape[3] // b[0])

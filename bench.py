@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-vl2", action="store_true", help="skip the van Leer integrator leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--no-blocks", action="store_true", help="skip the multi-block leg")
+    ap.add_argument("--no-smr", action="store_true", help="skip the static-refinement leg")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--serve-calib", type=int, default=300,
@@ -183,6 +184,42 @@ def run_batch(H, wl, count, steps, precision):
             "one_at_a_time_cell_updates_per_s": cells * steps / t_one,
             "speedup": t_one / t_batch, "batched_s": t_batch, "one_at_a_time_s": t_one,
             "launch_groups": info["groups"], "graph": info["graph"], "tile_rule": rule}
+
+
+def run_smr(H, wl, steps, warmup):
+    """Two-level static refinement in 3-D: 128^3 level-0 cells in 4x4x4
+    blocks of 32^3 with the central 2x2x2 blocks refined (120 leaves), mixed
+    precision, against the same blocks unrefined (64 leaves of 32^3)."""
+    import torch
+    n, B = (128, 128, 128), (4, 4, 4)
+    refined = [bx + 4 * (by + 4 * bz) for bz in (1, 2) for by in (1, 2) for bx in (1, 2)]
+
+    def timed(ref):
+        cfg = H.make_config(n, 5.0 / 3.0, 0.3, precision=H.MIXED, blocks=B)
+        leaves = H.smr_leaves(cfg, ref)
+        W = wl.smr_field(leaves, n, B, mach=1.0)
+        h = H.Hydro(n, 5.0 / 3.0, 0.3, precision=H.MIXED, blocks=B, refined=ref)
+        h.set_primitive(W)
+        h.step_auto(warmup)
+        torch.cuda.synchronize()
+        h.set_primitive(W)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        h.step_auto(steps)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        cells = int(W.shape[0] * np.prod(W.shape[2:]))
+        h.close()
+        return cells * steps / (ms * 1e-3), ms / steps, len(leaves), cells
+
+    v, ms, nl, cells = timed(refined)
+    v0, ms0, _, cells0 = timed([])
+    return {"value": v, "ms_per_step": ms, "leaves": nl, "cells": cells, "precision": "mixed",
+            "split_value": v0, "split_ms_per_step": ms0, "split_cells": cells0,
+            "config": "128^3 level 0 in 4x4x4 blocks of 32^3, central 2x2x2 refined, smooth Mach-1 field"}
 
 
 def run_serving(count, calib):
@@ -347,6 +384,10 @@ def main():
                 print(f"[bench] blocks {key} {mode}: {r['rate']:.3e} cell-updates/s, "
                       f"{r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
         out["blocks"] = {"precision": "mixed", "integrator": "heun", **bl}
+    if not args.no_smr and "mixed" in res:
+        out["smr"] = run_smr(H, wl, args.steps, args.warmup)
+        print(f"[bench] smr: {out['smr']['value']:.3e} cell-updates/s ({out['smr']['leaves']} leaves), "
+              f"split mesh {out['smr']['split_value']:.3e}", file=sys.stderr, flush=True)
     if not args.no_batch:
         print("[bench] batched 2-D workload ...", file=sys.stderr, flush=True)
         out["batch"] = run_batch(H, wl, args.batch_count, 300, H.MIXED)

@@ -1526,9 +1526,9 @@ __device__ __forceinline__ constexpr int active_axis(int k) {
 // Restriction onto the two ghost layers of a coarse block's side that faces
 // finer blocks: each ghost is the volume average of the 2^NDIM fine cells it
 // covers (pairwise means along x, then y, then z), on primitive variables;
-// stored as conserved values.  One work-group per ghost slot.
+// stored as conserved values.  blockIdx.x: the slot; one thread per ghost.
 template <int NDIM>
-__global__ __launch_bounds__(256) void smr_restrict_kernel(Geo g, const double* __restrict__ U,
+__global__ __launch_bounds__(64) void smr_restrict_kernel(Geo g, const double* __restrict__ U,
                                                            const int* __restrict__ side, double* __restrict__ gbuf,
                                                            long long gcs, const GhostTask* __restrict__ tasks,
                                                            Ctrl* ctrl) {
@@ -1539,7 +1539,8 @@ __global__ __launch_bounds__(256) void smr_restrict_kernel(Geo g, const double* 
     transverse(t.ax, lo, hi);
     const int nlo = g.n[lo], nhi = g.n[hi], face = nlo * nhi;
     bool bad = false;
-    for (int q = threadIdx.x; q < 2 * face; q += blockDim.x) {
+    const int q = blockIdx.y * blockDim.x + threadIdx.x;
+    if (q < 2 * face) {
         const int layer = q / face, r = q - layer * face;
         const int tl = r % nlo, th = r / nlo;
         double v[NC][K];
@@ -1590,9 +1591,10 @@ __global__ __launch_bounds__(256) void smr_restrict_kernel(Geo g, const double* 
 // minmod-limited difference (eq. minmod), signed by the side of the coarse
 // centre the ghost's centre lies on; the coarse block's own ghosts (same
 // level, boundary rule, restricted slots) complete its stencil.  Primitive
-// variables; stored as conserved values.  One work-group per ghost slot.
+// variables; stored as conserved values.  blockIdx.x: the slot; one thread
+// per ghost.
 template <int NDIM>
-__global__ __launch_bounds__(256) void smr_prolong_kernel(Geo g, const double* __restrict__ U,
+__global__ __launch_bounds__(64) void smr_prolong_kernel(Geo g, const double* __restrict__ U,
                                                           const int* __restrict__ side, double* __restrict__ gbuf,
                                                           long long gcs, const GhostTask* __restrict__ tasks,
                                                           Ctrl* ctrl) {
@@ -1604,7 +1606,8 @@ __global__ __launch_bounds__(256) void smr_prolong_kernel(Geo g, const double* _
     const int cblk = t.src[0];
     const Links L = table_links(side, cblk);
     bool bad = false;
-    for (int q = threadIdx.x; q < 2 * face; q += blockDim.x) {
+    const int q = blockIdx.y * blockDim.x + threadIdx.x;
+    if (q < 2 * face) {
         const int layer = q / face, r = q - layer * face;
         int ci[3] = {0, 0, 0};
         double sg[3] = {0.0, 0.0, 0.0};
@@ -1649,9 +1652,10 @@ __global__ __launch_bounds__(256) void smr_prolong_kernel(Geo g, const double* _
 // mean of the fine fluxes) (sign by side), so that its update uses the fine
 // fluxes' mean in place of its own.  The fluxes are recomputed from the same
 // stage input, ghosts and operations as in the stage kernel, so F_coarse
-// cancels exactly.  One work-group per coarse ghost slot of that axis.
+// cancels exactly.  blockIdx.x: a coarse ghost slot of that axis; one thread
+// per coarse face.
 template <int NDIM, typename R, int AX>
-__global__ __launch_bounds__(256) void smr_reflux_kernel(Geo g0, Geo g1, const double* __restrict__ in,
+__global__ __launch_bounds__(64) void smr_reflux_kernel(Geo g0, Geo g1, const double* __restrict__ in,
                                                          double* out, double factor, int use_device_dt,
                                                          double dt_host, const int* __restrict__ side,
                                                          const double* __restrict__ gbuf, long long gcs,
@@ -1670,7 +1674,8 @@ __global__ __launch_bounds__(256) void smr_reflux_kernel(Geo g0, Geo g1, const d
     const int n = g0.n[AX];
     const Links Lc = table_links(side, t.leaf);
     bool bad = false;
-    for (int r = threadIdx.x; r < face; r += blockDim.x) {
+    const int r = blockIdx.y * blockDim.x + threadIdx.x;
+    if (r < face) {
         const int tl = r % nlo, th = r / nlo;
         int x3[3] = {0, 0, 0};
         x3[lo] = tl;
@@ -2073,10 +2078,12 @@ hipError_t launch_padded_prim(const Geo& g, int precision, const double* U, doub
 hipError_t launch_smr_restrict(const Geo& g, const double* U, const int* side, double* gbuf, long long gcs,
                                const GhostTask* tasks, int n, Ctrl* ctrl, hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    // one thread per ghost of the largest slot (gcs = its two layers)
+    const dim3 grid(n, (unsigned)((gcs + 63) / 64));
     switch (g.ndim) {
-        case 1: hipLaunchKernelGGL(smr_restrict_kernel<1>, dim3(n), dim3(256), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
-        case 2: hipLaunchKernelGGL(smr_restrict_kernel<2>, dim3(n), dim3(256), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
-        case 3: hipLaunchKernelGGL(smr_restrict_kernel<3>, dim3(n), dim3(256), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
+        case 1: hipLaunchKernelGGL(smr_restrict_kernel<1>, grid, dim3(64), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
+        case 2: hipLaunchKernelGGL(smr_restrict_kernel<2>, grid, dim3(64), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
+        case 3: hipLaunchKernelGGL(smr_restrict_kernel<3>, grid, dim3(64), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2085,10 +2092,11 @@ hipError_t launch_smr_restrict(const Geo& g, const double* U, const int* side, d
 hipError_t launch_smr_prolong(const Geo& g, const double* U, const int* side, double* gbuf, long long gcs,
                               const GhostTask* tasks, int n, Ctrl* ctrl, hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    const dim3 grid(n, (unsigned)((gcs + 63) / 64));
     switch (g.ndim) {
-        case 1: hipLaunchKernelGGL(smr_prolong_kernel<1>, dim3(n), dim3(256), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
-        case 2: hipLaunchKernelGGL(smr_prolong_kernel<2>, dim3(n), dim3(256), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
-        case 3: hipLaunchKernelGGL(smr_prolong_kernel<3>, dim3(n), dim3(256), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
+        case 1: hipLaunchKernelGGL(smr_prolong_kernel<1>, grid, dim3(64), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
+        case 2: hipLaunchKernelGGL(smr_prolong_kernel<2>, grid, dim3(64), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
+        case 3: hipLaunchKernelGGL(smr_prolong_kernel<3>, grid, dim3(64), 0, s, g, U, side, gbuf, gcs, tasks, ctrl); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2098,7 +2106,8 @@ template <int NDIM, typename R>
 hipError_t reflux_t(int ax, const Geo& g0, const Geo& g1, const double* in, double* out, double factor, int ud,
                     double dth, const int* side, const double* gbuf, long long gcs, const GhostTask* tasks, int n,
                     Ctrl* ctrl, hipStream_t s) {
-#define RF(AXV) hipLaunchKernelGGL((smr_reflux_kernel<NDIM, R, AXV>), dim3(n), dim3(256), 0, s, g0, g1, in, out, \
+    const dim3 grid(n, (unsigned)((gcs / 2 + 63) / 64));  // one thread per face of the largest side
+#define RF(AXV) hipLaunchKernelGGL((smr_reflux_kernel<NDIM, R, AXV>), grid, dim3(64), 0, s, g0, g1, in, out, \
                                    factor, ud, dth, side, gbuf, gcs, tasks, ctrl)
     if (ax == 0) {
         RF(0);

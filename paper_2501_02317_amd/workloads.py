@@ -23,6 +23,8 @@ Workloads (paper sections in brackets):
   * implosion_2d   -- diagonal two-state problem in a reflecting box
                       [Sec. 4.3, eq. lw-init].
   * batch_sizes    -- ragged 2-D mesh sizes for the batched workload.
+  * smr_field      -- a smooth periodic random state (a few Fourier modes)
+                      on the cell centres of a refined block mesh's leaves.
 """
 from dataclasses import dataclass, field
 
@@ -334,3 +336,48 @@ def random_field_device(ndim, n, mach, gamma, seed, kmax=16, sigma=0.1, modes=48
     stack = stack.permute(0, *range(ndim, 0, -1))
     full = (1,) * (3 - ndim) + (n,) * ndim
     return stack.reshape((ndim + 2,) + full).contiguous()
+
+
+def leaf_centres(leaves, n, blocks, lo=None, hi=None):
+    """Cell-centre coordinates of each leaf of a refined block mesh: leaves
+    rows are (level, c0, c1, c2) on the leaf's level; n the level-0 cell
+    counts; returns ndim arrays of shape (nleaf, bz, by, bx)."""
+    nd = len(n)
+    lo = lo or (0.0,) * nd
+    hi = hi or (1.0,) * nd
+    leaves = np.asarray(leaves)
+    bn = [n[d] // blocks[d] for d in range(nd)] + [1] * (3 - nd)
+    out = []
+    for d in range(nd):
+        dxl = (hi[d] - lo[d]) / n[d] / 2.0 ** leaves[:, 0]
+        org = lo[d] + leaves[:, 1 + d] * bn[d] * dxl
+        shp = [1, 1, 1]
+        shp[2 - d] = bn[d]
+        x = org[:, None, None, None] + (np.arange(bn[d]).reshape(shp)[None] + 0.5) * dxl[:, None, None, None]
+        out.append(np.broadcast_to(x, (len(leaves), bn[2], bn[1], bn[0])).copy())
+    return out
+
+
+def smr_field(leaves, n, blocks, gamma=5.0 / 3.0, mach=0.5, amp=0.2, seed=71, modes=6):
+    """Block-layout primitive state (nleaf, ndim + 2, bz, by, bx) of a smooth
+    periodic random field on a unit box: density and pressure 1 + amp f,
+    velocities mach f, each f a mean of `modes` seeded sines with integer
+    wavenumbers 1..2 per axis."""
+    rng = np.random.default_rng(seed)
+    nd = len(n)
+    X = leaf_centres(leaves, n, blocks)
+
+    def f(scale):
+        acc = np.zeros(X[0].shape)
+        for _ in range(modes):
+            k = rng.integers(1, 3, size=nd)
+            ph = rng.random() * 2 * np.pi
+            acc = acc + np.sin(sum(2 * np.pi * k[d] * X[d] for d in range(nd)) + ph)
+        return scale * acc / modes
+
+    W = np.empty((len(X[0]), nd + 2) + X[0].shape[1:])
+    W[:, 0] = 1.0 + f(amp)
+    for d in range(nd):
+        W[:, 1 + d] = f(mach)
+    W[:, -1] = 1.0 / gamma + f(amp / gamma)
+    return W

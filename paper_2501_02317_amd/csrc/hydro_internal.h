@@ -143,22 +143,27 @@ hipError_t launch_riemann(int precision, int ntan, double gamma, long long n, co
                           const double* WR, double* F, hipStream_t s);
 
 // Static refinement passes over the ghost slots tasks[0, n) (all of one
-// kind): restriction or prolongation of the stage input U into gbuf (conserved
-// FP64 values), and the fine-flux correction of the coarse cells next to the
-// level jumps of kernel axis ax: out += factor * lam (difference of the coarse
-// flux and the mean of the fine fluxes), from the stage input in.  g0 and g1
-// are the coarse and fine levels' geometries.
+// kind): restriction or prolongation of the stage input U into gbuf
+// (conserved FP64 values); the fine-flux corrections of the coarse cells next
+// to every level jump, from the stage input in, into dbuf (factor * lam *
+// (coarse flux - mean of the fine fluxes), [slot][comp][face]); and their
+// addition to out for the restriction slots idx0 .. idx0 + n - 1 of one
+// kernel axis.  g0 and g1 are the coarse and fine levels' geometries.
 hipError_t launch_smr_restrict(const Geo& g, const double* U, const int* side, double* gbuf, long long gcs,
                                const GhostTask* tasks, int n, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_smr_prolong(const Geo& g, const double* U, const int* side, double* gbuf, long long gcs,
                               const GhostTask* tasks, int n, Ctrl* ctrl, hipStream_t s);
-hipError_t launch_smr_reflux(int precision, int ax, const Geo& g0, const Geo& g1, const double* in, double* out,
+hipError_t launch_smr_reflux(int precision, const Geo& g0, const Geo& g1, const double* in, double* dbuf,
                              double factor, int use_device_dt, double dt_host, const int* side,
                              const double* gbuf, long long gcs, const GhostTask* tasks, int n, Ctrl* ctrl,
                              hipStream_t s);
-// dt reduction over the blocks [0, blocks[0]) of U (geo of one level); with
-// skip_done, nothing once the run limit is reached.
-hipError_t launch_dt_blocks(const Geo& g, const double* U, Ctrl* ctrl, int skip_done, hipStream_t s);
+hipError_t launch_smr_apply(const Geo& g0, double* out, const double* dbuf, long long gcs, const GhostTask* tasks,
+                            int idx0, int n, int use_device_dt, Ctrl* ctrl, hipStream_t s);
+// dt reduction over the nblk blocks of U, blocks from start1 on with the cell
+// widths of g1 (a refined mesh's second level); with skip_done, nothing once
+// the run limit is reached.
+hipError_t launch_dt_levels(const Geo& g0, const Geo& g1, int start1, int nblk, const double* U, Ctrl* ctrl,
+                            int skip_done, hipStream_t s);
 
 // Default tile for a mesh (kernel axes) and precision.
 Tile default_tile(const Geo& g, int precision, int mode);

@@ -1215,11 +1215,18 @@ void stage_kernel_batch(
 
 // ------------------------------------------------------------- small kernels
 
-// blockIdx.y: the block of the mesh (block layout)
+// blockIdx.y: the block of the mesh (block layout); blocks from start1 on
+// take the cell widths of g1 (a refined mesh's second level)
 template <int NDIM>
-__global__ __launch_bounds__(256) void dt_kernel(Geo g, const double* __restrict__ U, Ctrl* ctrl, int skip_done) {
+__global__ __launch_bounds__(256) void dt_kernel(Geo g0, Geo g1, int start1, const double* __restrict__ U,
+                                                 Ctrl* ctrl, int skip_done) {
     constexpr int NC = NDIM + 2;
     if (skip_done && ctrl->done) return;  // uniform over the grid
+    Geo g = g0;
+    if ((int)blockIdx.y >= start1) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g.inv_dx[k] = g1.inv_dx[k];
+    }
     U += (long long)blockIdx.y * NC * g.ncells;
     double best = 0.0;
     bool bad = false;
@@ -1455,6 +1462,18 @@ __device__ __forceinline__ void transverse(int ax, int& lo, int& hi) {
     hi = ax == 2 ? 1 : 2;
 }
 
+// Element i (a run-time index) of a three- or four-element array, by
+// selects: indexing the array itself would place it in private memory.
+__device__ __forceinline__ int at3(const int (&a)[3], int i) { return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]); }
+__device__ __forceinline__ void set3(int (&a)[3], int i, int v) {
+    a[0] = i == 0 ? v : a[0];
+    a[1] = i == 1 ? v : a[1];
+    a[2] = i == 2 ? v : a[2];
+}
+__device__ __forceinline__ int at4(const int (&a)[4], int i) {
+    return i == 0 ? a[0] : (i == 1 ? a[1] : (i == 2 ? a[2] : a[3]));
+}
+
 // Raw conserved values of cell (x, y, z) of block blk of a refined mesh, at
 // most one coordinate outside the block (by up to two cells): through the
 // block's side codes, from a neighbouring block, by a mesh face's boundary
@@ -1537,7 +1556,8 @@ __global__ __launch_bounds__(64) void smr_restrict_kernel(Geo g, const double* _
     const GhostTask t = tasks[blockIdx.x];
     int lo, hi;
     transverse(t.ax, lo, hi);
-    const int nlo = g.n[lo], nhi = g.n[hi], face = nlo * nhi;
+    const int gn[3] = {g.n[0], g.n[1], g.n[2]};
+    const int nlo = at3(gn, lo), nhi = at3(gn, hi), face = nlo * nhi;
     bool bad = false;
     const int q = blockIdx.y * blockDim.x + threadIdx.x;
     if (q < 2 * face) {
@@ -1561,7 +1581,7 @@ __global__ __launch_bounds__(64) void smr_restrict_kernel(Geo g, const double* _
                     x3[ax] = p - cb[ax] * g.n[ax];
                 }
             }
-            const int fb = t.src[cb[lo] + 2 * cb[hi]];
+            const int fb = at4(t.src, at3(cb, lo) + 2 * at3(cb, hi));
             const Links L = table_links(side, fb);
             double w[NC];
             smr_prim<NDIM>(g, L, U, gbuf, gcs, fb, x3[0], x3[1], x3[2], w, bad);
@@ -1602,7 +1622,8 @@ __global__ __launch_bounds__(64) void smr_prolong_kernel(Geo g, const double* __
     const GhostTask t = tasks[blockIdx.x];
     int lo, hi;
     transverse(t.ax, lo, hi);
-    const int nlo = g.n[lo], nhi = g.n[hi], face = nlo * nhi;
+    const int gn[3] = {g.n[0], g.n[1], g.n[2]};
+    const int nlo = at3(gn, lo), nhi = at3(gn, hi), face = nlo * nhi;
     const int cblk = t.src[0];
     const Links L = table_links(side, cblk);
     bool bad = false;
@@ -1611,16 +1632,19 @@ __global__ __launch_bounds__(64) void smr_prolong_kernel(Geo g, const double* __
         const int layer = q / face, r = q - layer * face;
         int ci[3] = {0, 0, 0};
         double sg[3] = {0.0, 0.0, 0.0};
-        ci[t.ax] = t.s ? 0 : g.n[t.ax] - 1;
-        sg[t.ax] = t.s ? (layer == 0 ? -1.0 : 1.0) : (layer == 0 ? 1.0 : -1.0);
         const int tl = r % nlo, th = r / nlo;
 #pragma unroll
         for (int k = 0; k < NDIM; ++k) {
             const int ax = active_axis<NDIM>(k);
-            if (ax == t.ax) continue;
-            const int p = t.child[ax] * g.n[ax] + (ax == lo ? tl : th);  // fine index from the parent's origin
-            ci[ax] = p >> 1;
-            sg[ax] = (p & 1) ? 1.0 : -1.0;
+            if (ax == t.ax) {
+                // the coarse cell next to the face; the ghost's side of its centre
+                ci[ax] = t.s ? 0 : g.n[ax] - 1;
+                sg[ax] = t.s ? (layer == 0 ? -1.0 : 1.0) : (layer == 0 ? 1.0 : -1.0);
+            } else {
+                const int p = t.child[ax] * g.n[ax] + (ax == lo ? tl : th);  // fine index from the parent's origin
+                ci[ax] = p >> 1;
+                sg[ax] = (p & 1) ? 1.0 : -1.0;
+            }
         }
         double wc[NC], acc[NC];
         smr_prim<NDIM>(g, L, U, gbuf, gcs, cblk, ci[0], ci[1], ci[2], wc, bad);
@@ -1647,100 +1671,151 @@ __global__ __launch_bounds__(64) void smr_prolong_kernel(Geo g, const double* __
     if (bad) atomicOr(&ctrl->flags, FLAG_NONPHYSICAL);
 }
 
-// Flux correction at the level jumps of kernel axis AX: each coarse cell next
-// to a face shared with finer blocks gets out += factor * lam * (F_coarse -
-// mean of the fine fluxes) (sign by side), so that its update uses the fine
-// fluxes' mean in place of its own.  The fluxes are recomputed from the same
-// stage input, ghosts and operations as in the stage kernel, so F_coarse
-// cancels exactly.  blockIdx.x: a coarse ghost slot of that axis; one thread
-// per coarse face.
+// Flux correction at a level jump of kernel axis AX, for coarse face r of
+// restriction slot t: the coarse cell next to the face is to get
+// factor * lam * (F_coarse - mean of the fine fluxes) (sign by side), so that
+// its update uses the fine fluxes' mean in place of its own.  The fluxes are
+// recomputed from the same stage input, ghosts and operations as in the
+// stage kernel, so F_coarse cancels exactly.  The correction goes to
+// dbuf[idx][comp][r]; smr_apply_kernel adds it.
 template <int NDIM, typename R, int AX>
-__global__ __launch_bounds__(64) void smr_reflux_kernel(Geo g0, Geo g1, const double* __restrict__ in,
-                                                         double* out, double factor, int use_device_dt,
-                                                         double dt_host, const int* __restrict__ side,
-                                                         const double* __restrict__ gbuf, long long gcs,
-                                                         const GhostTask* __restrict__ tasks, Ctrl* ctrl) {
+__device__ __forceinline__ void reflux_face(const Geo& g0, const Geo& g1, const double* __restrict__ in,
+                                            double* __restrict__ dbuf, double factor, double dt,
+                                            const int* __restrict__ side, const double* __restrict__ gbuf,
+                                            long long gcs, const GhostTask& t, int idx, int r, bool& bad) {
     constexpr int NC = NDIM + 2;
     constexpr int NT = NDIM - 1;
-    if (use_device_dt && ctrl->done) return;  // uniform over the grid
-    const double dt = use_device_dt ? device_dt(ctrl) : dt_host;
     const double lam = dt / g0.dx[AX];
     const Gas<R> gr = make_gas<R>(g0.gamma);
     const double gm1 = g0.gamma - 1.0;
-    const GhostTask t = tasks[blockIdx.x];
     int lo, hi;
     transverse(AX, lo, hi);
     const int nlo = g0.n[lo], nhi = g0.n[hi], face = nlo * nhi;
+    if (r >= face) return;
     const int n = g0.n[AX];
     const Links Lc = table_links(side, t.leaf);
-    bool bad = false;
-    const int r = blockIdx.y * blockDim.x + threadIdx.x;
-    if (r < face) {
-        const int tl = r % nlo, th = r / nlo;
-        int x3[3] = {0, 0, 0};
-        x3[lo] = tl;
-        x3[hi] = th;
-        // the coarse face flux from the four coarse cells across it
-        R w[4][NC];
+    const int tl = r % nlo, th = r / nlo;
+    int x3[3] = {0, 0, 0};
+    x3[lo] = tl;
+    x3[hi] = th;
+    // the coarse face flux from the four coarse cells across it
+    R w[4][NC];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        int c3[3] = {x3[0], x3[1], x3[2]};
+        c3[AX] = t.s ? n - 2 + j : -2 + j;
+        double u[NC];
+        int vax, vm;
+        smr_cell<NC>(g0, Lc, in, gbuf, gcs, t.leaf, c3[0], c3[1], c3[2], u, vax, vm);
+        in_to_w<NDIM, R, false>(gm1, u, vax, vm, w[j], bad);
+    }
+    R Fc[NC];
+    face_flux<NDIM, AX, R>(gr, w[0], w[1], w[2], w[3], Fc);
+    // the fine fluxes through it, by transverse child offsets
+    // pairwise means as the fluxes arrive (offsets 0, 1 -> a; 2, 3 -> b),
+    // the same operations as a tree of pairwise means
+    double fa[NC], fb2[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) fa[c] = fb2[c] = 0.0;
+    // not unrolled: one fine face's stencil and Riemann solve live at a time
+#pragma unroll 1
+    for (int o = 0; o < (1 << NT); ++o) {
+        int f3[3] = {0, 0, 0};
+        int cb[3] = {0, 0, 0};
+        int bit = 0;
+#pragma unroll
+        for (int k = 0; k < NDIM; ++k) {
+            const int ax = active_axis<NDIM>(k);
+            if (ax == AX) continue;
+            const int p = 2 * x3[ax] + ((o >> bit) & 1);
+            ++bit;
+            cb[ax] = p / g1.n[ax];
+            f3[ax] = p - cb[ax] * g1.n[ax];
+        }
+        const int fb = at4(t.src, cb[lo] + 2 * cb[hi]);
+        const Links Lf = table_links(side, fb);
+        R v[4][NC];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            int c3[3] = {x3[0], x3[1], x3[2]};
-            c3[AX] = t.s ? n - 2 + j : -2 + j;
+            int c3[3] = {f3[0], f3[1], f3[2]};
+            c3[AX] = t.s ? -2 + j : g1.n[AX] - 2 + j;
             double u[NC];
             int vax, vm;
-            smr_cell<NC>(g0, Lc, in, gbuf, gcs, t.leaf, c3[0], c3[1], c3[2], u, vax, vm);
-            in_to_w<NDIM, R, false>(gm1, u, vax, vm, w[j], bad);
+            smr_cell<NC>(g1, Lf, in, gbuf, gcs, fb, c3[0], c3[1], c3[2], u, vax, vm);
+            in_to_w<NDIM, R, false>(gm1, u, vax, vm, v[j], bad);
         }
-        R Fc[NC];
-        face_flux<NDIM, AX, R>(gr, w[0], w[1], w[2], w[3], Fc);
-        // the fine fluxes through it, by transverse child offsets
-        double Ff[NC][4];
-#pragma unroll
-        for (int o = 0; o < (1 << NT); ++o) {
-            int f3[3] = {0, 0, 0};
-            int cb[3] = {0, 0, 0};
-            int bit = 0;
-#pragma unroll
-            for (int k = 0; k < NDIM; ++k) {
-                const int ax = active_axis<NDIM>(k);
-                if (ax == AX) continue;
-                const int p = 2 * x3[ax] + ((o >> bit) & 1);
-                ++bit;
-                cb[ax] = p / g1.n[ax];
-                f3[ax] = p - cb[ax] * g1.n[ax];
-            }
-            const int fb = t.src[cb[lo] + 2 * cb[hi]];
-            const Links Lf = table_links(side, fb);
-            R v[4][NC];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                int c3[3] = {f3[0], f3[1], f3[2]};
-                c3[AX] = t.s ? -2 + j : g1.n[AX] - 2 + j;
-                double u[NC];
-                int vax, vm;
-                smr_cell<NC>(g1, Lf, in, gbuf, gcs, fb, c3[0], c3[1], c3[2], u, vax, vm);
-                in_to_w<NDIM, R, false>(gm1, u, vax, vm, v[j], bad);
-            }
-            R F[NC];
-            face_flux<NDIM, AX, R>(gr, v[0], v[1], v[2], v[3], F);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) Ff[c][o] = (double)F[c];
-        }
-        const long long N = g0.ncells;
-        int c3[3] = {x3[0], x3[1], x3[2]};
-        c3[AX] = t.s ? n - 1 : 0;
-        const long long cell = (long long)t.leaf * NC * N + ((long long)c3[2] * g0.n[1] + c3[1]) * g0.n[0] + c3[0];
+        R F[NC];
+        face_flux<NDIM, AX, R>(gr, v[0], v[1], v[2], v[3], F);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-#pragma unroll
-            for (int k = 0; k < NT; ++k)
-#pragma unroll
-                for (int i = 0; i < ((1 << NT) >> (k + 1)); ++i) Ff[c][i] = 0.5 * (Ff[c][2 * i] + Ff[c][2 * i + 1]);
-            const double d = t.s ? ((double)Fc[c] - Ff[c][0]) : (Ff[c][0] - (double)Fc[c]);
-            out[cell + c * N] = out[cell + c * N] + factor * (lam * d);
+            const double f = (double)F[c];
+            if (o == 0) fa[c] = f;
+            else if (o == 1) fa[c] = 0.5 * (fa[c] + f);
+            else if (o == 2) fb2[c] = f;
+            else fb2[c] = 0.5 * (fb2[c] + f);
         }
     }
+    const long long fs = gcs / 2;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const double mean = NT == 2 ? 0.5 * (fa[c] + fb2[c]) : fa[c];
+        const double d = t.s ? ((double)Fc[c] - mean) : (mean - (double)Fc[c]);
+        dbuf[((long long)idx * NC + c) * fs + r] = factor * (lam * d);
+    }
+}
+
+// The corrections of every restriction slot, one launch for all axes:
+// blockIdx.x the slot (in slot order), one thread per coarse face.
+template <int NDIM, typename R>
+__global__ __launch_bounds__(64) void smr_reflux_kernel(Geo g0, Geo g1, const double* __restrict__ in,
+                                                         double* __restrict__ dbuf, double factor,
+                                                         int use_device_dt, double dt_host,
+                                                         const int* __restrict__ side,
+                                                         const double* __restrict__ gbuf, long long gcs,
+                                                         const GhostTask* __restrict__ tasks, Ctrl* ctrl) {
+    if (use_device_dt && ctrl->done) return;  // uniform over the grid
+    const double dt = use_device_dt ? device_dt(ctrl) : dt_host;
+    const GhostTask t = tasks[blockIdx.x];
+    const int r = blockIdx.y * blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (t.ax == 0) {
+        reflux_face<NDIM, R, 0>(g0, g1, in, dbuf, factor, dt, side, gbuf, gcs, t, blockIdx.x, r, bad);
+    } else if (t.ax == 1) {
+        if constexpr (NDIM == 3)
+            reflux_face<NDIM, R, 1>(g0, g1, in, dbuf, factor, dt, side, gbuf, gcs, t, blockIdx.x, r, bad);
+    } else {
+        if constexpr (NDIM >= 2)
+            reflux_face<NDIM, R, 2>(g0, g1, in, dbuf, factor, dt, side, gbuf, gcs, t, blockIdx.x, r, bad);
+    }
     if (bad) atomicOr(&ctrl->flags, FLAG_NONPHYSICAL);
+}
+
+// Add the corrections of the restriction slots idx0 .. idx0 + gridDim.x - 1
+// (one kernel axis) to their coarse cells: out += dbuf.  One launch per axis,
+// in axis order, so a coarse cell next to jumps on two axes is corrected in a
+// fixed order.
+template <int NDIM>
+__global__ __launch_bounds__(64) void smr_apply_kernel(Geo g0, double* __restrict__ out,
+                                                        const double* __restrict__ dbuf, long long gcs,
+                                                        const GhostTask* __restrict__ tasks, int idx0,
+                                                        int use_device_dt, Ctrl* ctrl) {
+    constexpr int NC = NDIM + 2;
+    if (use_device_dt && ctrl->done) return;  // uniform over the grid
+    const GhostTask t = tasks[blockIdx.x];
+    int lo, hi;
+    transverse(t.ax, lo, hi);
+    const int nlo = g0.n[lo], face = nlo * g0.n[hi];
+    const int r = blockIdx.y * blockDim.x + threadIdx.x;
+    if (r >= face) return;
+    int c3[3] = {0, 0, 0};
+    c3[lo] = r % nlo;
+    c3[hi] = r / nlo;
+    c3[t.ax] = t.s ? g0.n[t.ax] - 1 : 0;
+    const long long N = g0.ncells;
+    const long long cell = (long long)t.leaf * NC * N + ((long long)c3[2] * g0.n[1] + c3[1]) * g0.n[0] + c3[0];
+    const long long fs = gcs / 2;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[cell + c * N] = out[cell + c * N] + dbuf[((long long)(idx0 + blockIdx.x) * NC + c) * fs + r];
 }
 
 // Mesh layout [comp][k][j][i] <-> block layout; q runs over the mesh cells.
@@ -1985,21 +2060,21 @@ hipError_t launch_ctrl_batch(const MeshDesc* d, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_dt_blocks(const Geo& g, const double* U, Ctrl* ctrl, int skip_done, hipStream_t s) {
-    const int nblk = geo_nblk(g);
+hipError_t launch_dt_levels(const Geo& g0, const Geo& g1, int start1, int nblk, const double* U, Ctrl* ctrl,
+                            int skip_done, hipStream_t s) {
     if (nblk < 1) return hipSuccess;
-    const dim3 grid(grid_for(g.ncells, 256, (2048 + nblk - 1) / nblk), nblk);
-    switch (g.ndim) {
-        case 1: hipLaunchKernelGGL(dt_kernel<1>, grid, dim3(256), 0, s, g, U, ctrl, skip_done); break;
-        case 2: hipLaunchKernelGGL(dt_kernel<2>, grid, dim3(256), 0, s, g, U, ctrl, skip_done); break;
-        case 3: hipLaunchKernelGGL(dt_kernel<3>, grid, dim3(256), 0, s, g, U, ctrl, skip_done); break;
+    const dim3 grid(grid_for(g0.ncells, 256, (2048 + nblk - 1) / nblk), nblk);
+    switch (g0.ndim) {
+        case 1: hipLaunchKernelGGL(dt_kernel<1>, grid, dim3(256), 0, s, g0, g1, start1, U, ctrl, skip_done); break;
+        case 2: hipLaunchKernelGGL(dt_kernel<2>, grid, dim3(256), 0, s, g0, g1, start1, U, ctrl, skip_done); break;
+        case 3: hipLaunchKernelGGL(dt_kernel<3>, grid, dim3(256), 0, s, g0, g1, start1, U, ctrl, skip_done); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_dt(const Geo& g, const double* U, Ctrl* ctrl, hipStream_t s) {
-    return launch_dt_blocks(g, U, ctrl, 0, s);
+    return launch_dt_levels(g, g, geo_nblk(g), geo_nblk(g), U, ctrl, 0, s);
 }
 
 hipError_t launch_ctrl(Ctrl* c, int op, double a0, double a1, double cfl, hipStream_t s) {
@@ -2102,42 +2177,41 @@ hipError_t launch_smr_prolong(const Geo& g, const double* U, const int* side, do
     return hipGetLastError();
 }
 
-template <int NDIM, typename R>
-hipError_t reflux_t(int ax, const Geo& g0, const Geo& g1, const double* in, double* out, double factor, int ud,
-                    double dth, const int* side, const double* gbuf, long long gcs, const GhostTask* tasks, int n,
-                    Ctrl* ctrl, hipStream_t s) {
+hipError_t launch_smr_reflux(int precision, const Geo& g0, const Geo& g1, const double* in, double* dbuf,
+                             double factor, int use_device_dt, double dt_host, const int* side,
+                             const double* gbuf, long long gcs, const GhostTask* tasks, int n, Ctrl* ctrl,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
     const dim3 grid(n, (unsigned)((gcs / 2 + 63) / 64));  // one thread per face of the largest side
-#define RF(AXV) hipLaunchKernelGGL((smr_reflux_kernel<NDIM, R, AXV>), grid, dim3(64), 0, s, g0, g1, in, out, \
-                                   factor, ud, dth, side, gbuf, gcs, tasks, ctrl)
-    if (ax == 0) {
-        RF(0);
-    } else if (NDIM == 3 && ax == 1) {
-        RF(1);
-    } else if (NDIM >= 2 && ax == 2) {
-        RF(2);
-    } else {
-        return hipErrorInvalidValue;
+#define RF(ND, RT) hipLaunchKernelGGL((smr_reflux_kernel<ND, RT>), grid, dim3(64), 0, s, g0, g1, in, dbuf, factor, \
+                                      use_device_dt, dt_host, side, gbuf, gcs, tasks, ctrl)
+    switch (g0.ndim * 2 + (precision == 0 ? 0 : 1)) {
+        case 2: RF(1, double); break;
+        case 3: RF(1, float); break;
+        case 4: RF(2, double); break;
+        case 5: RF(2, float); break;
+        case 6: RF(3, double); break;
+        case 7: RF(3, float); break;
+        default: return hipErrorInvalidValue;
     }
 #undef RF
     return hipGetLastError();
 }
 
-hipError_t launch_smr_reflux(int precision, int ax, const Geo& g0, const Geo& g1, const double* in, double* out,
-                             double factor, int use_device_dt, double dt_host, const int* side,
-                             const double* gbuf, long long gcs, const GhostTask* tasks, int n, Ctrl* ctrl,
-                             hipStream_t s) {
+hipError_t launch_smr_apply(const Geo& g0, double* out, const double* dbuf, long long gcs, const GhostTask* tasks,
+                            int idx0, int n, int use_device_dt, Ctrl* ctrl, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-#define RFD(ND) (precision == 0 ? reflux_t<ND, double>(ax, g0, g1, in, out, factor, use_device_dt, dt_host, side, \
-                                                       gbuf, gcs, tasks, n, ctrl, s)                              \
-                                : reflux_t<ND, float>(ax, g0, g1, in, out, factor, use_device_dt, dt_host, side,  \
-                                                      gbuf, gcs, tasks, n, ctrl, s))
+    const dim3 grid(n, (unsigned)((gcs / 2 + 63) / 64));
+#define AP(ND) hipLaunchKernelGGL((smr_apply_kernel<ND>), grid, dim3(64), 0, s, g0, out, dbuf, gcs, tasks, idx0, \
+                                  use_device_dt, ctrl)
     switch (g0.ndim) {
-        case 1: return RFD(1);
-        case 2: return RFD(2);
-        case 3: return RFD(3);
+        case 1: AP(1); break;
+        case 2: AP(2); break;
+        case 3: AP(3); break;
         default: return hipErrorInvalidValue;
     }
-#undef RFD
+#undef AP
+    return hipGetLastError();
 }
 
 hipError_t launch_riemann(int precision, int ntan, double gamma, long long n, const double* WL,

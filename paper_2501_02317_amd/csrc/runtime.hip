@@ -38,6 +38,7 @@ struct hydro_ctx {
     GhostTask* d_tasks;            // restriction slots by kernel axis, then prolongation slots
     int nres, npro, res_off[4];
     double* gbuf;
+    double* dbuf;                  // flux corrections per restriction slot
     long long gcs;
     int32_t* leaves;               // host: (level, c0, c1, c2) per leaf
     Tile tile[2];  // stage 1 (and the rhs), stage 2
@@ -357,12 +358,12 @@ hipError_t timed_stage(hydro_t h, int mode, const StageArgs& a) {
 // One step of a refined mesh (Heun).  Each stage: the ghost slots of the
 // level jumps from the stage input (restriction, then prolongation, which
 // reads the restricted slots), the stage kernel per level, then the flux
-// correction of the coarse cells at the level jumps, axis by axis (a cell
-// next to two jumps is corrected once per axis, in order).  The CFL rate of
+// correction of the coarse cells at the level jumps (computed for every jump
+// in one launch, added axis by axis: a cell next to two jumps is corrected
+// once per axis, in order).  The CFL rate of
 // the corrected state is a reduction of its own.
 hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
     hipError_t e = hipSuccess;
-    const long long BS = (long long)h->ncomp * h->geo.ncells;
     for (int st = 0; st < 2 && e == hipSuccess; ++st) {
         const double* in = st == 0 ? h->U : h->U1;
         double* out = st == 0 ? h->U1 : h->U;
@@ -384,16 +385,17 @@ hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
             a.want_dt = 0;
             e = timed_stage(h, st == 0 ? MODE_STAGE1 : MODE_STAGE2, a);
         }
+        if (e == hipSuccess)
+            e = launch_smr_reflux(h->cfg.precision, h->lgeo[0], h->lgeo[1], in, h->dbuf, st == 0 ? 1.0 : 0.5,
+                                  device_dt ? 1 : 0, dt, h->d_side, h->gbuf, h->gcs, h->d_tasks, h->nres, h->ctrl,
+                                  h->stream);
         for (int ax = 0; ax < 3 && e == hipSuccess; ++ax)
-            e = launch_smr_reflux(h->cfg.precision, ax, h->lgeo[0], h->lgeo[1], in, out, st == 0 ? 1.0 : 0.5,
-                                  device_dt ? 1 : 0, dt, h->d_side, h->gbuf, h->gcs, h->d_tasks + h->res_off[ax],
-                                  h->res_off[ax + 1] - h->res_off[ax], h->ctrl, h->stream);
+            e = launch_smr_apply(h->lgeo[0], out, h->dbuf, h->gcs, h->d_tasks + h->res_off[ax], h->res_off[ax],
+                                 h->res_off[ax + 1] - h->res_off[ax], device_dt ? 1 : 0, h->ctrl, h->stream);
     }
     if (e != hipSuccess) return e;
     if (!device_dt) return launch_ctrl(h->ctrl, CTRL_ADVANCE_T, dt, 0.0, h->cfg.cfl, h->stream);
-    for (int lev = 0; lev < 2 && e == hipSuccess; ++lev)
-        if (h->lev_count[lev] > 0)
-            e = launch_dt_blocks(h->lgeo[lev], h->U + h->lev_start[lev] * BS, h->ctrl, 1, h->stream);
+    e = launch_dt_levels(h->lgeo[0], h->lgeo[1], h->lev_start[1], h->nblk, h->U, h->ctrl, 1, h->stream);
     if (e != hipSuccess) return e;
     return launch_ctrl(h->ctrl, CTRL_FINALIZE_STEP, 0.0, 0.0, h->cfg.cfl, h->stream);
 }
@@ -422,10 +424,8 @@ hipError_t enqueue_step(hydro_t h, bool device_dt, double dt) {
 hipError_t enqueue_dt(hydro_t h) {
     hipError_t e = launch_ctrl(h->ctrl, CTRL_RESET_MIN, 0.0, 0.0, h->cfg.cfl, h->stream);
     if (h->smr) {
-        const long long BS = (long long)h->ncomp * h->geo.ncells;
-        for (int lev = 0; lev < 2 && e == hipSuccess; ++lev)
-            if (h->lev_count[lev] > 0)
-                e = launch_dt_blocks(h->lgeo[lev], h->U + h->lev_start[lev] * BS, h->ctrl, 0, h->stream);
+        if (e == hipSuccess)
+            e = launch_dt_levels(h->lgeo[0], h->lgeo[1], h->lev_start[1], h->nblk, h->U, h->ctrl, 0, h->stream);
     } else if (e == hipSuccess) {
         e = launch_dt(h->geo, h->U, h->ctrl, h->stream);
     }
@@ -604,7 +604,8 @@ size_t smr_bytes(const hydro_config* c, const SmrPlan& P) {
     const size_t field = align_up(nc * cells * (size_t)P.nleaf * sizeof(double));
     return 2 * field + align_up(sizeof(Ctrl)) + align_up((size_t)kTotalsParts * kMaxComp * 2 * sizeof(double)) +
            align_up(P.side.size() * sizeof(int)) + align_up(P.tasks.size() * sizeof(GhostTask)) +
-           align_up(P.tasks.size() * nc * (size_t)P.gcs * sizeof(double));
+           align_up(P.tasks.size() * nc * (size_t)P.gcs * sizeof(double)) +
+           align_up((size_t)P.nres * nc * (size_t)(P.gcs / 2) * sizeof(double));
 }
 
 }  // namespace
@@ -724,6 +725,8 @@ int hydro_smr_create(const hydro_config* cfg, int nref, const int32_t* refined, 
     h->d_tasks = (GhostTask*)p;
     p += align_up(P.tasks.size() * sizeof(GhostTask));
     h->gbuf = (double*)p;
+    p += align_up(P.tasks.size() * nc * (size_t)P.gcs * sizeof(double));
+    h->dbuf = (double*)p;
     if (hipHostMalloc((void**)&h->host_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
         delete[] h->leaves;
         delete h;

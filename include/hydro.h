@@ -9,7 +9,8 @@
  * (eqs. hllc-contact-spd and hllc-mixed-dvel), a flux-divergence update in
  * the Heun two-stage integrator (Sec. 3.3), and a global CFL time step taken
  * at the first sub-step (Sec. 3.1).  Ghost zones follow Sec. 3.1.1 and are
- * resolved inside the kernels' loads; no ghost layers are stored.
+ * resolved inside the kernels' loads; no ghost layers are stored, except the
+ * restricted and prolonged layers at the level jumps of a refined mesh.
  *
  * Data conventions
  *   - ndim in {1,2,3}; n[d] interior cells on axis d; axes d >= ndim must

@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--no-blocks", action="store_true", help="skip the multi-block leg")
     ap.add_argument("--no-smr", action="store_true", help="skip the static-refinement leg")
+    ap.add_argument("--smr-only", action="store_true",
+                    help="run only the static-refinement leg and print its record (for kernel traces)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--serve-calib", type=int, default=300,
@@ -307,6 +309,10 @@ def main():
         return
     from paper_2501_02317_amd import hydro as H
     from paper_2501_02317_amd import workloads as wl
+    if args.smr_only:
+        # diagnostic mode for kernel traces of the refined-mesh leg alone
+        print(json.dumps({"smr": run_smr(H, wl, args.steps, args.warmup)}), flush=True)
+        return
 
     case = wl.turbulence_3d(n=args.n, mach=2.0, seed=301, steps=100, cfl=0.3)
     print(f"[bench] workload {case.name} steps {args.steps} warmup {args.warmup}", file=sys.stderr,

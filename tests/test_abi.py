@@ -122,3 +122,28 @@ def test_block_split_validation(H):
     cfg = H.make_config((8, 4), 1.4, 0.3, bc=((3, 3), (2, 1)), blocks=(4, 2))
     assert H.workspace_bytes(cfg) > 0
     assert H._lib.hydro_set_block_streams(None, 1) == H.E_INVAL
+
+
+def test_refinement_validation_and_leaves(H):
+    """Refinement plans on the host: leaf order (level 0 by root, then level
+    1 by the level-1 grid), the workspace, and the rejected cases."""
+    import numpy as np
+    cfg = H.make_config((32, 16), 1.4, 0.4, blocks=(4, 2))
+    L = H.smr_leaves(cfg, [1, 6])
+    assert [tuple(r) for r in L[:6]] == [(0, 0, 0, 0), (0, 2, 0, 0), (0, 3, 0, 0), (0, 0, 1, 0), (0, 1, 1, 0),
+                                         (0, 3, 1, 0)]
+    assert len(L) == 6 + 8 and np.all(L[6:, 0] == 1)
+    assert [tuple(r[1:3]) for r in L[6:]] == [(2, 0), (3, 0), (2, 1), (3, 1), (4, 2), (5, 2), (4, 3), (5, 3)]
+    assert H.workspace_bytes(cfg, [1, 6]) > H.workspace_bytes(cfg, [])
+    assert H.workspace_bytes(cfg, []) > 0
+    bad = [
+        (cfg, [8]),                                                          # no such root
+        (cfg, [1, 1]),                                                       # listed twice
+        (H.make_config((24, 16), 1.4, 0.4, blocks=(8, 2)), [0]),             # blocks of 3 cells
+        (H.make_config((8, 16), 1.4, 0.4, blocks=(4, 2)), [0]),              # blocks of 2 cells
+        (H.make_config((32, 16), 1.4, 0.4, blocks=(4, 2), integrator=1), [0]),  # van Leer
+    ]
+    for c, ref in bad:
+        assert H.workspace_bytes(c, ref) == 0, ref
+        with pytest.raises(H.HydroError):
+            H.smr_leaves(c, ref)

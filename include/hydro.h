@@ -270,13 +270,14 @@ int hydro_smr_create(const hydro_config* cfg, int nref, const int32_t* refined, 
 int hydro_smr_leaves(const hydro_config* cfg, int nref, const int32_t* refined, int32_t* leaves, int max);
 
 /*
- * How the stages of a split mesh are launched (Sec. 3, Fig. hydro_proc: each
- * block's work on a stream of its own).  on = 0 (the default): one launch per
- * stage covers every block.  on = 1: each block's stages are launched on
- * their own, spread over four streams the handle creates (default priority,
- * not synchronising with the legacy default stream); a block's stage 2
- * waits only for its face neighbours' stage 1, and the step's time-step
- * update waits for every block.  The results do not depend on the choice.
+ * How the stages of a split mesh are launched (Sec. 3, Fig. hydro_proc: the
+ * blocks' work on streams of their own).  on = 0 (the default): one launch
+ * per stage covers every block.  on = 1: the blocks are split into up to four
+ * groups of contiguous blocks, each with a stream the handle creates (default
+ * priority, not synchronising with the legacy default stream); each group's
+ * stage is one launch; a group's stage 2 waits only for the groups that hold
+ * its blocks' face neighbours to finish stage 1, and the step's time-step
+ * update waits for every group.  The results do not depend on the choice.
  * Stage timing (hydro_profile) records only the one-launch form.  No effect
  * on a mesh of one block.  Blocks until the handle's stream has drained.
  */

@@ -28,8 +28,11 @@ struct hydro_ctx {
     hipStream_t bs[kBlockStreams];
     hipEvent_t ev_fork;
     hipEvent_t ev_join[kBlockStreams];
-    hipEvent_t* ev_s1;             // per block: its stage 1 has finished
+    hipEvent_t* ev_s1;             // per stream's block group: its stage 1 has finished
     int* nbr;                      // per block: up to 6 distinct face neighbours, -1 padded
+    // block group g = blocks [g nblk / nbs, (g + 1) nblk / nbs) runs on stream g;
+    // gadj[g][o]: a block of group o is a face neighbour of a block of group g
+    bool gadj[kBlockStreams][kBlockStreams];
     // static refinement (two levels; leaves of level 0, then of level 1)
     bool smr;
     int lev_start[2], lev_count[2];
@@ -234,7 +237,15 @@ void block_streams_free(hydro_t h) {
     h->nbs = 0;
 }
 
-// Streams and events of the per-block launches, made on first use.
+// The stream group of block b (contiguous ranges, nbs of them).
+int block_group(hydro_t h, int b) {
+    int g = (int)(((long long)b * h->nbs) / h->nblk);
+    while (g > 0 && b < (int)(((long long)g * h->nblk) / h->nbs)) --g;
+    while (g + 1 < h->nbs && b >= (int)(((long long)(g + 1) * h->nblk) / h->nbs)) ++g;
+    return g;
+}
+
+// Streams and events of the per-group launches, made on first use.
 hipError_t block_streams_make(hydro_t h) {
     if (h->nbs > 0) return hipSuccess;
     h->nbr = new (std::nothrow) int[6 * (size_t)h->nblk];
@@ -276,43 +287,51 @@ hipError_t block_streams_make(hydro_t h) {
         return e;
     }
     h->nbs = ns;
+    for (int g = 0; g < ns; ++g)
+        for (int o = 0; o < ns; ++o) h->gadj[g][o] = false;
+    for (int b = 0; b < h->nblk; ++b)
+        for (int q = 0; q < 6; ++q) {
+            const int nb = h->nbr[6 * b + q];
+            if (nb >= 0) h->gadj[block_group(h, b)][block_group(h, nb)] = true;
+        }
     return hipSuccess;
 }
 
-// One step with each block's stages launched on its own stream: stage 1 of
-// every block, then stage 2 of a block once its face neighbours' stage 1 has
-// finished (no wait on the other blocks), then the step's finalisation on
-// the handle's stream after every block.
+// One step with the blocks' stages launched by group, each group of
+// contiguous blocks on a stream of its own: stage 1 of every group, then
+// stage 2 of a group once the groups holding its blocks' face neighbours have
+// finished stage 1 (no wait on the others), then the step's finalisation on
+// the handle's stream after every group.
 hipError_t enqueue_step_streams(hydro_t h, bool device_dt, double dt) {
     StageArgs a = stage_args(h);
     a.use_device_dt = device_dt ? 1 : 0;
     a.dt_host = dt;
-    a.nblk = 1;
-    a.conc = h->nbs;  // one block per stream at a time
+    a.conc = h->nblk;  // the groups run at once
     hipError_t e = hipEventRecord(h->ev_fork, h->stream);
     for (int i = 0; i < h->nbs && e == hipSuccess; ++i) e = hipStreamWaitEvent(h->bs[i], h->ev_fork, 0);
-    for (int b = 0; b < h->nblk && e == hipSuccess; ++b) {
-        hipStream_t s = h->bs[b % h->nbs];
-        a.blk0 = b;
+    auto range = [&](int g) {
+        a.blk0 = (int)(((long long)g * h->nblk) / h->nbs);
+        a.nblk = (int)(((long long)(g + 1) * h->nblk) / h->nbs) - a.blk0;
+    };
+    for (int g = 0; g < h->nbs && e == hipSuccess; ++g) {
+        range(g);
         a.in = h->U;
         a.base = h->U;
         a.out = h->U1;
         a.want_dt = 0;
-        e = launch_stage(h->cfg.precision, stage1_mode(&h->cfg), h->tile[0], a, s);
-        if (e == hipSuccess) e = hipEventRecord(h->ev_s1[b], s);
+        e = launch_stage(h->cfg.precision, stage1_mode(&h->cfg), h->tile[0], a, h->bs[g]);
+        if (e == hipSuccess) e = hipEventRecord(h->ev_s1[g], h->bs[g]);
     }
-    for (int b = 0; b < h->nblk && e == hipSuccess; ++b) {
-        hipStream_t s = h->bs[b % h->nbs];
-        for (int q = 0; q < 6 && e == hipSuccess; ++q) {
-            const int nb = h->nbr[6 * b + q];
-            if (nb >= 0 && nb % h->nbs != b % h->nbs) e = hipStreamWaitEvent(s, h->ev_s1[nb], 0);
-        }
-        a.blk0 = b;
+    for (int g = 0; g < h->nbs && e == hipSuccess; ++g) {
+        // it reads their stage-1 output, and they read the state it overwrites
+        for (int o = 0; o < h->nbs && e == hipSuccess; ++o)
+            if (o != g && h->gadj[g][o]) e = hipStreamWaitEvent(h->bs[g], h->ev_s1[o], 0);
+        range(g);
         a.in = h->U1;
         a.base = h->U;
         a.out = h->U;
         a.want_dt = device_dt ? 1 : 0;
-        if (e == hipSuccess) e = launch_stage(h->cfg.precision, stage2_mode(&h->cfg), h->tile[1], a, s);
+        if (e == hipSuccess) e = launch_stage(h->cfg.precision, stage2_mode(&h->cfg), h->tile[1], a, h->bs[g]);
     }
     for (int i = 0; i < h->nbs && e == hipSuccess; ++i) {
         e = hipEventRecord(h->ev_join[i], h->bs[i]);

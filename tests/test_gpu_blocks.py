@@ -207,3 +207,14 @@ def test_batch_rejects_split_members(H):
     with pytest.raises(H.HydroError):
         H.Batch([h])
     h.close()
+
+
+def test_nonphysical_state_in_one_block_is_reported(H):
+    c = wl.turbulence_3d(n=(16, 16, 16), mach=1.0, seed=47)
+    c.W[-1, 12, 3, 13] = -1.0                       # negative pressure in the last block
+    say("blocks nonphysical")
+    h = mesh(H, c, 0, blocks=(2, 2, 2))
+    with pytest.raises(H.HydroError) as e:
+        h.cfl_dt()
+    assert e.value.status == H.E_NONPHYSICAL
+    h.close()

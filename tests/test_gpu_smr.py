@@ -199,3 +199,19 @@ def test_refined_handle_rejects_unsupported_calls(H):
     with pytest.raises(H.HydroError):
         H.Batch([h])
     h.close()
+
+
+def test_nonphysical_state_in_a_fine_block_is_reported(H):
+    n, B, ref = (32, 32, 16), (2, 2, 2), [0, 3]
+    m = O.Mesh(n, 1.4)
+    S = O.SMR(m, B, ref)
+    W = smooth_state(S, seed=66)
+    W[-1, -1, 2, 3, 4] = -1.0                       # negative pressure in the last (fine) leaf
+    assert S.leaves[-1][0] == 1
+    say("smr nonphysical")
+    h = H.Hydro(n, 1.4, 0.4, blocks=B, refined=ref)
+    h.set_primitive(W)
+    with pytest.raises(H.HydroError) as e:
+        h.cfl_dt()
+    assert e.value.status == H.E_NONPHYSICAL
+    h.close()

@@ -260,6 +260,9 @@ int hydro_profile_read(hydro_t h, double* ms_stage1, double* ms_stage2, int64_t*
  *     jump is corrected so that its update uses the mean of the fine fluxes
  *     through its face, which keeps the totals conserved.  One global time
  *     step (the paper's default), taken from a reduction after the step.
+ *     The prolongation and the flux recomputation run on a second stream the
+ *     handle creates (default priority, non-blocking), overlapping the
+ *     level-0 stage; every step joins it back into the handle's stream.
  *   - Not available on a refined handle (HYDRO_E_INVAL): hydro_stage_rhs,
  *     hydro_padded_primitive, hydro_autotune, hydro_set_block_streams(h, 1),
  *     batch membership.

@@ -42,6 +42,8 @@ struct hydro_ctx {
     int nres, npro, res_off[4];
     double* gbuf;
     double* dbuf;                  // flux corrections per restriction slot
+    hipStream_t smr_aux;           // second stream of the level-jump passes (null: none)
+    hipEvent_t ev_smr[3];          // restriction done, prolongation done, recomputation done
     long long gcs;
     int32_t* leaves;               // host: (level, c0, c1, c2) per leaf
     Tile tile[2];  // stage 1 (and the rhs), stage 2
@@ -383,15 +385,30 @@ hipError_t timed_stage(hydro_t h, int mode, const StageArgs& a) {
 // the corrected state is a reduction of its own.
 hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
     hipError_t e = hipSuccess;
+    // With a second stream (smr_aux), the passes that the level-0 stage does
+    // not need overlap it: the prolongation (read only by level 1) and the
+    // flux recomputation (reads the stage input and the slots, not the
+    // stage's output); level 1 waits for the prolongation, the additions for
+    // the recomputation.
+    hipStream_t aux = h->smr_aux ? h->smr_aux : h->stream;
     for (int st = 0; st < 2 && e == hipSuccess; ++st) {
         const double* in = st == 0 ? h->U : h->U1;
         double* out = st == 0 ? h->U1 : h->U;
         e = launch_smr_restrict(h->lgeo[0], in, h->d_side, h->gbuf, h->gcs, h->d_tasks, h->nres, h->ctrl, h->stream);
+        if (e == hipSuccess && h->smr_aux) e = hipEventRecord(h->ev_smr[0], h->stream);
+        if (e == hipSuccess && h->smr_aux) e = hipStreamWaitEvent(aux, h->ev_smr[0], 0);
         if (e == hipSuccess)
             e = launch_smr_prolong(h->lgeo[0], in, h->d_side, h->gbuf, h->gcs, h->d_tasks + h->nres, h->npro,
-                                   h->ctrl, h->stream);
+                                   h->ctrl, aux);
+        if (e == hipSuccess && h->smr_aux) e = hipEventRecord(h->ev_smr[1], aux);
+        if (e == hipSuccess)
+            e = launch_smr_reflux(h->cfg.precision, h->lgeo[0], h->lgeo[1], in, h->dbuf, st == 0 ? 1.0 : 0.5,
+                                  device_dt ? 1 : 0, dt, h->d_side, h->gbuf, h->gcs, h->d_tasks, h->nres, h->ctrl,
+                                  aux);
+        if (e == hipSuccess && h->smr_aux) e = hipEventRecord(h->ev_smr[2], aux);
         for (int lev = 0; lev < 2 && e == hipSuccess; ++lev) {
-            if (h->lev_count[lev] == 0) continue;
+            if (lev == 1 && h->smr_aux) e = hipStreamWaitEvent(h->stream, h->ev_smr[1], 0);
+            if (e != hipSuccess || h->lev_count[lev] == 0) continue;
             StageArgs a = stage_args(h);
             a.geo = h->lgeo[lev];
             a.blk0 = h->lev_start[lev];
@@ -404,10 +421,7 @@ hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
             a.want_dt = 0;
             e = timed_stage(h, st == 0 ? MODE_STAGE1 : MODE_STAGE2, a);
         }
-        if (e == hipSuccess)
-            e = launch_smr_reflux(h->cfg.precision, h->lgeo[0], h->lgeo[1], in, h->dbuf, st == 0 ? 1.0 : 0.5,
-                                  device_dt ? 1 : 0, dt, h->d_side, h->gbuf, h->gcs, h->d_tasks, h->nres, h->ctrl,
-                                  h->stream);
+        if (e == hipSuccess && h->smr_aux) e = hipStreamWaitEvent(h->stream, h->ev_smr[2], 0);
         for (int ax = 0; ax < 3 && e == hipSuccess; ++ax)
             e = launch_smr_apply(h->lgeo[0], out, h->dbuf, h->gcs, h->d_tasks + h->res_off[ax], h->res_off[ax],
                                  h->res_off[ax + 1] - h->res_off[ax], device_dt ? 1 : 0, h->ctrl, h->stream);
@@ -759,6 +773,24 @@ int hydro_smr_create(const hydro_config* cfg, int nref, const int32_t* refined, 
                            h->stream);
     if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_INIT, 0.0, 0.0, cfg->cfl, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // the plan's host vectors end here
+    if (e == hipSuccess && P.tasks.size() > 0) {
+        // default priority, not synchronising with the legacy default stream
+        hipStream_t aux = nullptr;
+        e = hipStreamCreateWithFlags(&aux, hipStreamNonBlocking);
+        if (e == hipSuccess) {
+            int made = 0;
+            for (; made < 3; ++made) {
+                e = hipEventCreateWithFlags(&h->ev_smr[made], hipEventDisableTiming);
+                if (e != hipSuccess) break;
+            }
+            if (e == hipSuccess) {
+                h->smr_aux = aux;
+            } else {
+                for (int i = 0; i < made; ++i) (void)hipEventDestroy(h->ev_smr[i]);
+                (void)hipStreamDestroy(aux);
+            }
+        }
+    }
     if (e != hipSuccess) {
         (void)hipHostFree(h->host_ctrl);
         delete[] h->leaves;
@@ -1230,6 +1262,10 @@ int hydro_destroy(hydro_t h) {
     if (!h->broken) (void)hipStreamSynchronize(h->stream);
     block_streams_free(h);
     profile_free(h);
+    if (h->smr_aux) {
+        for (int i = 0; i < 3; ++i) (void)hipEventDestroy(h->ev_smr[i]);
+        (void)hipStreamDestroy(h->smr_aux);
+    }
     delete[] h->leaves;
     (void)hipHostFree(h->host_ctrl);
     delete h;

@@ -32,7 +32,8 @@
  *     hydro_workspace_bytes(cfg) bytes (256-byte aligned), which must outlive
  *     the handle.  The handle itself owns only host metadata, a small
  *     pinned host staging buffer and, once hydro_set_block_streams turns them
- *     on, its block streams and events.  hydro_stage_rhs,
+ *     on, its block streams and events (a refined handle: its second stream
+ *     and three events).  hydro_stage_rhs,
  *     hydro_padded_primitive and the host transfers of a split mesh take a
  *     temporary device buffer (stream-ordered allocation) for the call.
  *   - All device work is enqueued on the caller's HIP stream given at

@@ -161,7 +161,12 @@ int hydro_step(hydro_t h, double dt);
  * synchronisation).  The dt of each step comes from the previous step's
  * stage-2 epilogue (the first from a standalone reduction).  When t_end > 0
  * the step that would pass t_end is shortened to land on it and later steps
- * are no-ops. */
+ * are no-ops.
+ * hydro_step and hydro_step_auto enqueue kernels only (no allocation, memset
+ * or host synchronisation), so a caller may capture them into a HIP graph on
+ * the handle's stream.  While that stream is being captured, the forms that
+ * fork work onto other streams (block streams, a refined mesh's second
+ * stream) run on the handle's stream alone; the results are the same. */
 int hydro_step_auto(hydro_t h, int nsteps, double t_end);
 
 /* dV-weighted conserved totals, ncomp values: deterministic compensated

@@ -376,6 +376,16 @@ hipError_t timed_stage(hydro_t h, int mode, const StageArgs& a) {
 // One step: stage 1 (Heun: U1 = U^n + dt L(U^n); van Leer: the predicted
 // primitive state) then stage 2 in place over U^n, dt either from the host or
 // from the device control block (clamped to the run limit kept there).
+// Whether the handle's stream is being captured into a graph.  The forms
+// that fork work onto other streams and join it back by events (block
+// streams, a refined mesh's second stream) then run on the handle's stream
+// alone: capturing the forked form crashed in the HIP runtime at the end of
+// the capture.  The results do not depend on the form.
+bool capturing(hydro_t h) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(h->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
 // One step of a refined mesh (Heun).  Each stage: the ghost slots of the
 // level jumps from the stage input (restriction, then prolongation, which
 // reads the restricted slots), the stage kernel per level, then the flux
@@ -390,24 +400,25 @@ hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
     // flux recomputation (reads the stage input and the slots, not the
     // stage's output); level 1 waits for the prolongation, the additions for
     // the recomputation.
-    hipStream_t aux = h->smr_aux ? h->smr_aux : h->stream;
+    const bool fork = h->smr_aux && !capturing(h);
+    hipStream_t aux = fork ? h->smr_aux : h->stream;
     for (int st = 0; st < 2 && e == hipSuccess; ++st) {
         const double* in = st == 0 ? h->U : h->U1;
         double* out = st == 0 ? h->U1 : h->U;
         e = launch_smr_restrict(h->lgeo[0], in, h->d_side, h->gbuf, h->gcs, h->d_tasks, h->nres, h->ctrl, h->stream);
-        if (e == hipSuccess && h->smr_aux) e = hipEventRecord(h->ev_smr[0], h->stream);
-        if (e == hipSuccess && h->smr_aux) e = hipStreamWaitEvent(aux, h->ev_smr[0], 0);
+        if (e == hipSuccess && fork) e = hipEventRecord(h->ev_smr[0], h->stream);
+        if (e == hipSuccess && fork) e = hipStreamWaitEvent(aux, h->ev_smr[0], 0);
         if (e == hipSuccess)
             e = launch_smr_prolong(h->lgeo[0], in, h->d_side, h->gbuf, h->gcs, h->d_tasks + h->nres, h->npro,
                                    h->ctrl, aux);
-        if (e == hipSuccess && h->smr_aux) e = hipEventRecord(h->ev_smr[1], aux);
+        if (e == hipSuccess && fork) e = hipEventRecord(h->ev_smr[1], aux);
         if (e == hipSuccess)
             e = launch_smr_reflux(h->cfg.precision, h->lgeo[0], h->lgeo[1], in, h->dbuf, st == 0 ? 1.0 : 0.5,
                                   device_dt ? 1 : 0, dt, h->d_side, h->gbuf, h->gcs, h->d_tasks, h->nres, h->ctrl,
                                   aux);
-        if (e == hipSuccess && h->smr_aux) e = hipEventRecord(h->ev_smr[2], aux);
+        if (e == hipSuccess && fork) e = hipEventRecord(h->ev_smr[2], aux);
         for (int lev = 0; lev < 2 && e == hipSuccess; ++lev) {
-            if (lev == 1 && h->smr_aux) e = hipStreamWaitEvent(h->stream, h->ev_smr[1], 0);
+            if (lev == 1 && fork) e = hipStreamWaitEvent(h->stream, h->ev_smr[1], 0);
             if (e != hipSuccess || h->lev_count[lev] == 0) continue;
             StageArgs a = stage_args(h);
             a.geo = h->lgeo[lev];
@@ -421,7 +432,7 @@ hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
             a.want_dt = 0;
             e = timed_stage(h, st == 0 ? MODE_STAGE1 : MODE_STAGE2, a);
         }
-        if (e == hipSuccess && h->smr_aux) e = hipStreamWaitEvent(h->stream, h->ev_smr[2], 0);
+        if (e == hipSuccess && fork) e = hipStreamWaitEvent(h->stream, h->ev_smr[2], 0);
         for (int ax = 0; ax < 3 && e == hipSuccess; ++ax)
             e = launch_smr_apply(h->lgeo[0], out, h->dbuf, h->gcs, h->d_tasks + h->res_off[ax], h->res_off[ax],
                                  h->res_off[ax + 1] - h->res_off[ax], device_dt ? 1 : 0, h->ctrl, h->stream);
@@ -435,7 +446,7 @@ hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
 
 hipError_t enqueue_step(hydro_t h, bool device_dt, double dt) {
     if (h->smr) return enqueue_step_smr(h, device_dt, dt);
-    if (h->block_streams && h->nblk > 1) return enqueue_step_streams(h, device_dt, dt);
+    if (h->block_streams && h->nblk > 1 && !capturing(h)) return enqueue_step_streams(h, device_dt, dt);
     StageArgs a = stage_args(h);
     a.use_device_dt = device_dt ? 1 : 0;
     a.dt_host = dt;

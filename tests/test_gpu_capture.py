@@ -22,27 +22,36 @@ def H():
     return hydro
 
 
-def make(H, c, stream, blocks=None, refined=None, streams=False, W=None):
-    h = H.Hydro(c.n, c.gamma, c.cfl, precision=H.MIXED, lo=c.lo, hi=c.hi, bc=c.bc, stream=stream,
-                blocks=blocks, refined=refined)
+def make(H, c, stream, blocks=None, refined=None, streams=False, W=None, precision=1, integrator=0):
+    h = H.Hydro(c.n, c.gamma, c.cfl, precision=precision, lo=c.lo, hi=c.hi, bc=c.bc, stream=stream,
+                blocks=blocks, refined=refined, integrator=integrator)
     if streams:
         h.set_block_streams(True)
     h.set_primitive(c.W if W is None else W)
     return h
 
 
-CASES = [("single", None, None, False), ("blocks", (2, 2, 2), None, False),
-         pytest.param("block streams", (2, 2, 4), None, True, marks=pytest.mark.skip(
-             reason="capturing the forked per-group streams crashed the host process inside the HIP "
-                    "runtime at the end of the capture; the library now runs that form on the "
-                    "handle's stream while it is captured, and this case stays off until the crash "
-                    "is understood")),
-         ("refined", (2, 2, 2), [0, 5], False)]
+SKIP_STREAMS = pytest.mark.skip(
+    reason="capturing the forked per-group streams crashed the host process inside the HIP runtime at the "
+           "end of the capture; the library now runs that form on the handle's stream while it is "
+           "captured, and this case stays off until the crash is understood")
+# name, blocks, refined, block streams, precision, integrator, t_end
+CASES = [pytest.param("single", None, None, False, 1, 0, 0.0, id="single"),
+         pytest.param("blocks", (2, 2, 2), None, False, 1, 0, 0.0, id="blocks"),
+         pytest.param("block streams", (2, 2, 4), None, True, 1, 0, 0.0, id="block streams",
+                      marks=SKIP_STREAMS),
+         pytest.param("refined", (2, 2, 2), [0, 5], False, 1, 0, 0.0, id="refined"),
+         pytest.param("fp64", None, None, False, 0, 0, 0.0, id="fp64"),
+         pytest.param("van Leer", (1, 2, 2), None, False, 1, 1, 0.0, id="van Leer"),
+         pytest.param("refined fp64", (2, 2, 2), [1, 2, 7], False, 0, 0, 0.0, id="refined fp64"),
+         # the end time falls inside the second replay: the step that would
+         # pass it lands on it, and the third replay changes nothing
+         pytest.param("to t_end", (2, 1, 1), None, False, 1, 0, 0.0135, id="to t_end")]
 
 
-@pytest.mark.parametrize("name,blocks,refined,streams", CASES,
-                         ids=["single", "blocks", "block streams", "refined"])
-def test_captured_steps_replay_like_eager_steps(H, name, blocks, refined, streams):
+@pytest.mark.parametrize("name,blocks,refined,streams,precision,integrator,t_end", CASES)
+def test_captured_steps_replay_like_eager_steps(H, name, blocks, refined, streams, precision, integrator,
+                                                t_end):
     import torch
     c = wl.turbulence_3d(n=(32, 32, 32), mach=1.0, seed=81)
     W = None
@@ -52,18 +61,21 @@ def test_captured_steps_replay_like_eager_steps(H, name, blocks, refined, stream
     nsteps, replays = 3, 3
     say("capture", name)
     s = torch.cuda.Stream()
+    opts = dict(blocks=blocks, refined=refined, streams=streams, W=W, precision=precision, integrator=integrator)
     # eager reference: the same calls, states after each call
-    ref = make(H, c, s, blocks, refined, streams, W)
+    ref = make(H, c, s, **opts)
     expect = []
     for _ in range(replays):
-        ref.step_auto(nsteps)
+        ref.step_auto(nsteps, t_end)
         expect.append((ref.get_state(), ref.time(), ref.steps_done()))
     ref.close()
-    h = make(H, c, s, blocks, refined, streams, W)
+    if t_end > 0.0:
+        assert expect[0][1] < t_end and expect[1][1] == t_end and expect[2][2] == expect[1][2]
+    h = make(H, c, s, **opts)
     s.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
-        h.step_auto(nsteps)
+        h.step_auto(nsteps, t_end)
     for r in range(replays):
         g.replay()
         # eager work of the program between replays, then a host synchronisation

@@ -3,6 +3,13 @@ import sys
 
 import pytest
 
+# Under pytest-xdist every worker loads the OpenMP oracle: without a cap each
+# would start one thread per core, and the spinning thread teams of the
+# workers make the CPU suite crawl.  Share the cores between the workers.
+if "PYTEST_XDIST_WORKER_COUNT" in os.environ and "OMP_NUM_THREADS" not in os.environ:
+    _workers = max(1, int(os.environ["PYTEST_XDIST_WORKER_COUNT"]))
+    os.environ["OMP_NUM_THREADS"] = str(max(1, (os.cpu_count() or 1) // _workers))
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

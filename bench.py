@@ -14,6 +14,9 @@ U^n and writes U1, stage 2 reads U1 and U^n and writes U^{n+1}, 5 x ncomp x
 8 B = 200 B per 3-D cell-update) against the 8 TB/s HBM peak, timed with HIP
 events on the launch stream inside the timed region.  cpu_baseline = the
 FP64 oracle on the host cores for one Heun step of the same 256^3 state.
+by_precision.*.host_inclusive = the same run with the state handed over in
+host memory (upload over PCIe, the steps, download), measured after the timed
+region; it is never the value.
 """
 import argparse
 import hashlib
@@ -92,7 +95,7 @@ def bytes_per_update(ndim, precision=0, integrator=0):
 
 
 def run_precision(H, case, precision, steps, warmup, tile=None, tune=True, integrator=0, blocks=None,
-                  streams=False):
+                  streams=False, host_io=False):
     import torch
     h = H.Hydro(case.n, case.gamma, case.cfl, precision=precision, lo=case.lo, hi=case.hi, bc=case.bc,
                 integrator=integrator, blocks=blocks)
@@ -124,6 +127,7 @@ def run_precision(H, case, precision, steps, warmup, tile=None, tune=True, integ
     h.profile(0)
     t_sim = h.time()
     T = h.totals()
+    host = host_inclusive(h, case, steps) if host_io else None
     h.close()
     cells = case.ncells
     rate = cells * steps / (ms * 1e-3)
@@ -138,7 +142,27 @@ def run_precision(H, case, precision, steps, warmup, tile=None, tune=True, integ
         "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS if achieved else None, "totals": T.tolist(),
         "step_frac": rate * bytes_per_update(case.ndim, precision, integrator) / 1e9 / HBM_PEAK_GBS,
         "tiles": [list(t) for t in tiles],
+        "host_inclusive": host,
     }
+
+
+def host_inclusive(h, case, steps):
+    """The same run with the state handed over in host memory, after the
+    timed region: primitive state uploaded over PCIe (and converted to
+    conserved variables), the steps, the conserved state downloaded."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.set_primitive(case.W)
+    t1 = time.perf_counter()
+    h.step_auto(steps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    U = h.get_state()
+    t3 = time.perf_counter()
+    return {"value": case.ncells * steps / (t3 - t0), "unit": "cell-updates/s",
+            "upload_s": t1 - t0, "steps_s": t2 - t1, "download_s": t3 - t2,
+            "bytes_each_way": int(U.nbytes)}
 
 
 def run_batch(H, wl, count, steps, precision):
@@ -322,7 +346,7 @@ def main():
         if args.precision not in ("both", name):
             continue
         fixed = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
-        res[name] = run_precision(H, case, prec, args.steps, args.warmup, fixed, not args.no_tune)
+        res[name] = run_precision(H, case, prec, args.steps, args.warmup, fixed, not args.no_tune, host_io=True)
         print(f"[bench] {name}: {res[name]['rate']:.3e} cell-updates/s, "
               f"{res[name]['ms_per_step']:.3f} ms/step, stage kernel {res[name]['achieved_gbs']:.0f} GB/s",
               file=sys.stderr, flush=True)
@@ -357,7 +381,7 @@ def main():
         "by_precision": {k: {"value": v["rate"], "ms_per_step": v["ms_per_step"],
                              "roofline_frac": v["frac"], "step_roofline_frac": v["step_frac"],
                              "stage_ms": v["stage_ms"], "achieved_gbs": v["achieved_gbs"],
-                             "tiles": v["tiles"]}
+                             "tiles": v["tiles"], "host_inclusive": v["host_inclusive"]}
                          for k, v in res.items()},
     }
     if "mixed" in res and "fp64" in res:

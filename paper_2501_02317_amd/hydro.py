@@ -227,10 +227,17 @@ class Hydro:
         assert out.is_cuda and out.is_contiguous() and tuple(out.shape) == tuple(self.shape)
         _check(_lib.hydro_get_state_device(self._h, _vp(out.data_ptr())), "hydro_get_state_device")
 
-    def get_state(self):
-        U = np.empty(self.shape)
-        _check(_lib.hydro_get_state(self._h, _ptr(U)), "hydro_get_state")
-        return U
+    def get_state(self, out=None):
+        """Conserved state copied to host memory, into out if given (a
+        C-contiguous float64 array of the state's shape, e.g. one kept across
+        calls so its pages are not touched for the first time on every copy)."""
+        if out is None:
+            out = np.empty(self.shape)
+        elif not (isinstance(out, np.ndarray) and out.dtype == np.float64 and out.flags.c_contiguous
+                  and out.flags.writeable and tuple(out.shape) == tuple(self.shape)):
+            raise ValueError(f"out must be a writeable C-contiguous float64 array of shape {tuple(self.shape)}")
+        _check(_lib.hydro_get_state(self._h, _ptr(out)), "hydro_get_state")
+        return out
 
     def state_view(self):
         """Zero-copy torch view of the device state (valid until the next

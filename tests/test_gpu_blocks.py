@@ -143,6 +143,14 @@ def test_transfers_and_views(H):
     assert bitwise_equal(b.get_state(), Ua)
     b.set_state(Ua)
     assert bitwise_equal(b.get_state(), Ua)
+    # into a caller's array, for both layouts
+    for h in (a, b):
+        buf = np.full(Ua.shape, np.nan)
+        assert h.get_state(out=buf) is buf and bitwise_equal(buf, Ua)
+        for bad in (np.empty(Ua.shape, dtype=np.float32), np.empty(Ua.shape[::-1]),
+                    np.empty(Ua.shape, order="F")):
+            with pytest.raises(ValueError):
+                h.get_state(out=bad)
     # diagnostics
     assert a.cfl_dt() == b.cfl_dt()
     assert bitwise_equal(a.stage_rhs(1e-3), b.stage_rhs(1e-3))

@@ -323,7 +323,7 @@ def traffic_record(precision, tiles):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU path is a design only)", file=sys.stderr)
         sys.exit(2)
     import torch

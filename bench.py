@@ -125,6 +125,11 @@ def run_precision(H, case, precision, steps, warmup, tile=None, tune=True, integ
     ms = start.elapsed_time(stop)
     ms1, ms2, (n1, n2) = h.profile_read()
     h.profile(0)
+    # the timed launches advanced the run: stage kernels return early once a
+    # run limit is reached, and timing such empty launches would mean nothing
+    done = h.steps_done()
+    if done != steps or (not streams and (n1 != steps or n2 != steps)):
+        raise RuntimeError(f"timed run advanced {done} steps ({n1}, {n2} stage launches), expected {steps}")
     t_sim = h.time()
     T = h.totals()
     host = host_inclusive(h, case, steps) if host_io else None
@@ -239,6 +244,8 @@ def run_smr(H, wl, steps, warmup):
         b.record(stream)
         torch.cuda.synchronize()
         ms = a.elapsed_time(b)
+        if h.steps_done() != steps:
+            raise RuntimeError(f"refined timed run advanced {h.steps_done()} steps, expected {steps}")
         cells = int(W.shape[0] * np.prod(W.shape[2:]))
         h.close()
         return cells * steps / (ms * 1e-3), ms / steps, len(leaves), cells

@@ -90,7 +90,9 @@ _i64p = C.POINTER(C.c_int64)
 def lib():
     global _lib
     if _lib is None:
-        path = _build.build(force=False)
+        # ORACLE_LIB names another build of the same sources (the tests run
+        # a sanitizer-instrumented build in a subprocess through it)
+        path = os.environ.get("ORACLE_LIB") or _build.build(force=False)
         L = C.CDLL(path)
         mp = C.POINTER(_Mesh)
         sig = {

@@ -2,8 +2,9 @@
 
     python -m paper_2501_02317_amd.build
 
-Flags: gfx950 only; no FP contraction (the FP64 path evaluates exactly the
-written IEEE operations); packed FP32 instructions disabled.
+Flags: gfx950 only; no implicit FP contraction (the kernels place their
+fused multiply-adds and Newton-refined reciprocals by hand, so the FP64 path
+agrees with the oracle to rounding); packed FP32 instructions disabled.
 """
 import os
 import subprocess

@@ -191,8 +191,9 @@ class Hydro:
             self.device = workspace.device
             self.workspace = workspace
         else:
-            self.device = torch.device(device if device is not None else "cuda")
-            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8,
+                                         device=torch.device(device if device is not None else "cuda"))
+            self.device = self.workspace.device  # with its index
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
@@ -215,17 +216,28 @@ class Hydro:
         W = np.ascontiguousarray(W, dtype=np.float64).reshape(self.shape)
         _check(_lib.hydro_set_primitive(self._h, _ptr(W)), "hydro_set_primitive")
 
+    def _device_field(self, t, what):
+        """Refuse a tensor the C call would overrun: the library reads or
+        writes ncomp * ncells doubles at the pointer on this mesh's device."""
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and t.device == self.device and tuple(t.shape) == tuple(self.shape)):
+            raise HydroError(E_INVAL, f"{what}: needs a contiguous float64 tensor of shape {tuple(self.shape)} "
+                                      f"on {self.device}")
+        return _vp(t.data_ptr())
+
     def set_primitive_device(self, W):
-        """W: float64 CUDA tensor of shape (ncomp, nz, ny, nx), contiguous.
-        The tensor must stay alive until the stream passes this call."""
-        assert W.is_cuda and W.dtype.is_floating_point and W.is_contiguous()
-        assert tuple(W.shape) == tuple(self.shape)
-        _check(_lib.hydro_set_primitive_device(self._h, _vp(W.data_ptr())), "hydro_set_primitive_device")
+        """W: float64 CUDA tensor of shape (ncomp, nz, ny, nx), contiguous, on
+        this mesh's device.  The tensor must stay alive until the stream
+        passes this call."""
+        p = self._device_field(W, "set_primitive_device")
+        _check(_lib.hydro_set_primitive_device(self._h, p), "hydro_set_primitive_device")
 
     def get_state_device(self, out):
-        """Copy the state into a float64 CUDA tensor (async on the mesh's stream)."""
-        assert out.is_cuda and out.is_contiguous() and tuple(out.shape) == tuple(self.shape)
-        _check(_lib.hydro_get_state_device(self._h, _vp(out.data_ptr())), "hydro_get_state_device")
+        """Copy the state into a float64 CUDA tensor of the state's shape on
+        this mesh's device (async on the mesh's stream)."""
+        p = self._device_field(out, "get_state_device")
+        _check(_lib.hydro_get_state_device(self._h, p), "hydro_get_state_device")
 
     def get_state(self, out=None):
         """Conserved state copied to host memory, into out if given (a

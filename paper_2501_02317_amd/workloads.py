@@ -21,7 +21,7 @@ Workloads (paper sections in brackets):
   * shear_layer_2d -- double tanh shear layer with density ratio 1:2
                       [Sec. 4.5].
   * implosion_2d   -- diagonal two-state problem in a reflecting box
-                      [Sec. 4.3, eq. lw-init].
+                      [Sec. 4.4, eq. lw-init].
   * batch_sizes    -- ragged 2-D mesh sizes for the batched workload.
   * smr_field      -- a smooth periodic random state (a few Fourier modes)
                       on the cell centres of a refined block mesh's leaves.
@@ -114,7 +114,7 @@ def sod_1d(N=256):
 
 def implosion_2d(N=256, side=0.3, t_end=2.5, gamma=1.4, cfl=0.4):
     """Diagonal two-state problem with reflecting walls (the implosion of
-    Sec. 4.3, eq. lw-init): (rho, p, v) = (0.125, 0.14, 0) where x + y <
+    Sec. 4.4, eq. lw-init): (rho, p, v) = (0.125, 0.14, 0) where x + y <
     0.15, (1, 1, 0) elsewhere, on the square [0, side]^2 (side: a reading,
     twice the leg of the low-pressure triangle).  Symmetric under x <-> y."""
     n = (N, N)

@@ -136,6 +136,15 @@ def test_transfers_and_views(H):
     b.get_state_device(out)
     torch.cuda.synchronize()
     assert bitwise_equal(out.cpu().numpy(), Ua)
+    # tensors the C calls would overrun (wrong dtype, shape or device) are
+    # refused before any device work
+    for bad in (torch.empty(Ua.shape, dtype=torch.float32, device=b.device),
+                torch.empty(Ua.shape[::-1], dtype=torch.float64, device=b.device),
+                torch.empty(Ua.shape, dtype=torch.float64)):
+        with pytest.raises(H.HydroError):
+            b.get_state_device(bad)
+        with pytest.raises(H.HydroError):
+            b.set_primitive_device(bad)
     Wd = torch.from_numpy(np.ascontiguousarray(c.W)).to(b.device)
     b.set_state(np.zeros_like(Ua))
     b.set_primitive_device(Wd)

@@ -1,4 +1,4 @@
-"""Directional symmetry with reflecting walls (Sec. 4.3): the diagonal
+"""Directional symmetry with reflecting walls (Sec. 4.4): the diagonal
 implosion (eq. lw-init) run on the GPU to t = 2.5 stays exactly symmetric
 about the diagonal in both precisions and with both integrators, and
 matches the oracle early in the run."""

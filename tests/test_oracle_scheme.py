@@ -311,7 +311,7 @@ def test_sampled_cells_match_full_mesh_bitwise(ndim, bc):
 
 @pytest.mark.parametrize("integrator", [0, 1])
 def test_diagonal_implosion_keeps_reflection_symmetry(integrator):
-    """Sec. 4.3: a state symmetric about the diagonal, in a reflecting box,
+    """Sec. 4.4: a state symmetric about the diagonal, in a reflecting box,
     stays exactly symmetric (x <-> y with v_x <-> v_y), both integrators."""
     c = wl.implosion_2d(N=48, t_end=0.05)
     m = O.Mesh(c.n, c.gamma, c.lo, c.hi, c.bc, integrator=integrator)

@@ -75,13 +75,23 @@ def test_admission_respects_memory_budget():
     assert torch.cuda.is_available()
     from paper_2501_02317_amd import serving as S
     reqs = S.request_stream(10, 1000.0, seed=12, n2=(128, 128), n3=(48, 48), steps=(10, 20))
-    budget = max(S.footprint(r) for r in reqs) + 4096      # the largest request fits alone
+    for r in reqs:
+        r.arrival = 0.0                                      # all waiting at the start
+    fp = [S.footprint(r) for r in reqs]
+    # the largest request fits alone and the first two fit together, but not all ten
+    budget = max(max(fp), fp[0] + fp[1]) + 4096
+    assert budget < sum(fp)
     say("admission budget", budget)
     srv = S.Server(budget, steps_per_iter=8)
     srv.run(reqs)
     assert all(r.finished is not None and not r.failed for r in reqs)
     # at every admission, the requests resident then fit the budget together
+    resident_at = []
     for r in reqs:
         resident = [q for q in reqs if q.admitted <= r.admitted < q.finished]
         assert sum(S.footprint(q) for q in resident) <= budget
-    assert max(len([q for q in reqs if q.admitted <= r.admitted < q.finished]) for r in reqs) >= 1
+        resident_at.append(len(resident))
+    # requests ran concurrently (both first requests were admitted at once),
+    # and the budget made some wait for memory to free up
+    assert max(resident_at) >= 2
+    assert any(q.admitted >= p.finished for p in reqs for q in reqs if q is not p)

@@ -14,7 +14,8 @@ import oracle as O
 from paper_2501_02317_amd import workloads as wl
 from gpu_util import gpu_mesh, oracle_mesh, rel_l1, say
 
-pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+# the oracle runs inside the first test of each workload: minutes, not seconds
+pytestmark = [pytest.mark.gpu, pytest.mark.slow, pytest.mark.timeout(900)]
 
 
 @pytest.fixture(scope="module")

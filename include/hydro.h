@@ -173,6 +173,33 @@ int hydro_step_auto(hydro_t h, int nsteps, double t_end);
  * FP64 sums in a fixed order (blocks). */
 int hydro_conserved_totals(hydro_t h, double* totals);
 
+/* For callers that cannot allocate or synchronise (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): the totals of
+ * hydro_conserved_totals for a state the caller holds in device memory,
+ * computed with no allocation, no host synchronisation and no memset, and
+ * written to device memory.
+ *   cfg       the mesh (as for hydro_create; precision and integrator are not
+ *             used); its cell volume dV = prod_d (hi_d - lo_d) / n_d.
+ *   d_U       device, ncomp * n[0] * n[1] * n[2] doubles, caller-owned: the
+ *             layout of hydro_state_device for that configuration (the mesh
+ *             layout [comp][k][j][i]; for a split mesh the block layout).
+ *   d_totals  device, ncomp doubles, caller-owned: totals_c = dV * sum_i U_c,i,
+ *             bitwise the values hydro_conserved_totals returns for a handle
+ *             of the same configuration holding the same state.
+ *   hip_stream  the work is enqueued there and the call returns at once.
+ * Scratch: the partial sums live in a static device array of the library,
+ * 2 * 5 * 1024 doubles (80 KiB) per device, which each device holds until
+ * the process ends; the reduction never needs more, whatever the mesh size
+ * (at most 1024 work-groups of partials; a configuration needing more is
+ * refused with HYDRO_E_INVAL).  Calls on one device share that array:
+ * calls that overlap on one device (different streams, or threads) race and
+ * must be serialised by the caller.  The first call on a device resolves the
+ * array's device address (hipGetSymbolAddress), so make it outside a graph
+ * capture.  Returns HYDRO_E_INVAL for an invalid cfg or null pointer,
+ * HYDRO_E_DEVICE when a HIP call fails; state errors are not checked. */
+int hydro_conserved_totals_noalloc(const hydro_config* cfg, const double* d_U, double* d_totals,
+                                   void* hip_stream);
+
 /* Run limit kept on the device: device-dt steps (hydro_step_auto, batches)
  * stop advancing this mesh once max_steps more steps are done (0: no step
  * limit) or t reaches t_end (0: no time limit; the last step is shortened to

@@ -132,6 +132,10 @@ hipError_t launch_dt(const Geo& g, const double* U, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_ctrl(Ctrl* c, int op, double a0, double a1, double cfl, hipStream_t s);
 hipError_t launch_totals(const Geo& g, const double* U, double* partials, int nparts, Ctrl* ctrl,
                          hipStream_t s);
+// The same reduction, written as out[c] = dV (sum + compensation) on the
+// device (partials: 2 ncomp nparts doubles of scratch).
+hipError_t launch_totals_out(const Geo& g, const double* U, double* partials, int nparts, double* out, double dV,
+                             hipStream_t s);
 // W and U in the block layout; in place when W == U.
 hipError_t launch_prim_to_cons(const Geo& g, const double* W, double* U, hipStream_t s);
 // Copy a field between the mesh layout [comp][k][j][i] (mesh) and the block

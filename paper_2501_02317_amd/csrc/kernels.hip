@@ -1369,9 +1369,12 @@ __global__ __launch_bounds__(256) void totals_pass1(long long ncells, const doub
         }
 }
 
+// The fixed tree over the partials.  out == null: the (sum, compensation)
+// pairs go to sums[2 c], sums[2 c + 1]; else out[c] = dV (sum + compensation).
 template <int NC>
 __global__ __launch_bounds__(256) void totals_pass2(int nparts, const double* __restrict__ parts,
-                                                    Ctrl* ctrl) {
+                                                    double* __restrict__ sums, double* __restrict__ out,
+                                                    double dV) {
     __shared__ double ss[NC][256], sc[NC][256];
     Comp acc[NC];
 #pragma unroll
@@ -1401,8 +1404,12 @@ __global__ __launch_bounds__(256) void totals_pass2(int nparts, const double* __
     if (threadIdx.x == 0)
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            ctrl->sums[2 * c] = ss[c][0];
-            ctrl->sums[2 * c + 1] = sc[c][0];
+            if (out) {
+                out[c] = dV * (ss[c][0] + sc[c][0]);
+            } else {
+                sums[2 * c] = ss[c][0];
+                sums[2 * c + 1] = sc[c][0];
+            }
         }
 }
 
@@ -2094,8 +2101,10 @@ hipError_t launch_ctrl(Ctrl* c, int op, double a0, double a1, double cfl, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_totals(const Geo& g, const double* U, double* parts, int nparts, Ctrl* ctrl,
-                         hipStream_t s) {
+namespace {
+// Partials pass then the tree over them; sums or out as in totals_pass2.
+hipError_t totals_launch(const Geo& g, const double* U, double* parts, int nparts, double* sums, double* out,
+                         double dV, hipStream_t s) {
     // nparts partials shared out over the blocks (at least one each)
     const int nblk = geo_nblk(g);
     if (nblk > nparts) return hipErrorInvalidValue;
@@ -2106,19 +2115,31 @@ hipError_t launch_totals(const Geo& g, const double* U, double* parts, int npart
     switch (NC) {
         case 3:
             hipLaunchKernelGGL(totals_pass1<3>, grid, dim3(256), 0, s, g.ncells, U, parts);
-            hipLaunchKernelGGL(totals_pass2<3>, dim3(1), dim3(256), 0, s, np, parts, ctrl);
+            hipLaunchKernelGGL(totals_pass2<3>, dim3(1), dim3(256), 0, s, np, parts, sums, out, dV);
             break;
         case 4:
             hipLaunchKernelGGL(totals_pass1<4>, grid, dim3(256), 0, s, g.ncells, U, parts);
-            hipLaunchKernelGGL(totals_pass2<4>, dim3(1), dim3(256), 0, s, np, parts, ctrl);
+            hipLaunchKernelGGL(totals_pass2<4>, dim3(1), dim3(256), 0, s, np, parts, sums, out, dV);
             break;
         case 5:
             hipLaunchKernelGGL(totals_pass1<5>, grid, dim3(256), 0, s, g.ncells, U, parts);
-            hipLaunchKernelGGL(totals_pass2<5>, dim3(1), dim3(256), 0, s, np, parts, ctrl);
+            hipLaunchKernelGGL(totals_pass2<5>, dim3(1), dim3(256), 0, s, np, parts, sums, out, dV);
             break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_totals(const Geo& g, const double* U, double* parts, int nparts, Ctrl* ctrl,
+                         hipStream_t s) {
+    return totals_launch(g, U, parts, nparts, ctrl->sums, nullptr, 0.0, s);
+}
+
+hipError_t launch_totals_out(const Geo& g, const double* U, double* parts, int nparts, double* out, double dV,
+                             hipStream_t s) {
+    if (!out) return hipErrorInvalidValue;
+    return totals_launch(g, U, parts, nparts, nullptr, out, dV, s);
 }
 
 hipError_t launch_prim_to_cons(const Geo& g, const double* W, double* U, hipStream_t s) {

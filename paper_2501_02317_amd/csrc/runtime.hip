@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -997,6 +998,54 @@ int hydro_conserved_totals(hydro_t h, double* totals) {
     for (int c = 0; c < h->ncomp; ++c)
         totals[c] = h->dV * (h->host_ctrl->sums[2 * c] + h->host_ctrl->sums[2 * c + 1]);
     return rc;
+}
+
+// Scratch of hydro_conserved_totals_noalloc: the per-work-group partials,
+// (sum, compensation) per component, of at most kTotalsParts work-groups.
+// Every call on a device shares that device's copy; pass 1 writes every
+// partial that pass 2 reads, so nothing needs clearing between calls.
+constexpr int kScratchParts = kTotalsParts;
+static __device__ __align__(256) double scratch[2 * kMaxComp * kScratchParts];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices];  // per device: the device address of its scratch copy
+
+// The current device's scratch address, looked up once per device (the
+// symbol's host name is no device address).
+hipError_t scratch_address(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch[dev] = (double*)p;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+int hydro_conserved_totals_noalloc(const hydro_config* cfg, const double* d_U, double* d_totals,
+                                   void* hip_stream) {
+    if (!config_ok(cfg) || !d_U || !d_totals) return HYDRO_E_INVAL;
+    const Geo g = make_geo(cfg);
+    const int nblk = geo_nblk(g);
+    // every block takes one partial at least (config_ok caps the blocks at
+    // kMaxBlocks == kScratchParts)
+    if (nblk > kScratchParts) return HYDRO_E_INVAL;
+    double dV = 1.0;
+    for (int d = 0; d < cfg->ndim; ++d) dV *= (cfg->hi[d] - cfg->lo[d]) / cfg->n[d];
+    double* parts = nullptr;
+    hipError_t e = scratch_address(&parts);
+    if (e == hipSuccess) e = launch_totals_out(g, d_U, parts, kScratchParts, d_totals, dV, (hipStream_t)hip_stream);
+    return e == hipSuccess ? HYDRO_OK : HYDRO_E_DEVICE;
 }
 
 int hydro_time(hydro_t h, double* t) {

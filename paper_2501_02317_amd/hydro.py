@@ -57,6 +57,7 @@ _SIG = {
     "hydro_step": (C.c_int, [_h, C.c_double]),
     "hydro_step_auto": (C.c_int, [_h, C.c_int, C.c_double]),
     "hydro_conserved_totals": (C.c_int, [_h, _dp]),
+    "hydro_conserved_totals_noalloc": (C.c_int, [C.POINTER(Config), _vp, _vp, _vp]),
     "hydro_time": (C.c_int, [_h, _dp]),
     "hydro_steps_done": (C.c_int, [_h, C.POINTER(C.c_int64)]),
     "hydro_stage_rhs": (C.c_int, [_h, C.c_double, _dp]),
@@ -460,6 +461,26 @@ def riemann_fluxes(precision, gamma, WL, WR, stream=None):
            "hydro_riemann_fluxes")
     s.synchronize()
     return dF.cpu().numpy()
+
+
+def conserved_totals_noalloc(cfg, U, out, stream=None):
+    """hydro_conserved_totals_noalloc: the dV-weighted totals of the device
+    state U (a contiguous float64 CUDA tensor in the layout of
+    Hydro.state_view for the configuration cfg) written into out (a
+    contiguous float64 CUDA tensor of ncomp values on U's device), enqueued on
+    stream (default: the current stream) with no allocation and no host
+    synchronisation."""
+    import torch
+    nc = cfg.ndim + 2
+    cells = cfg.n[0] * cfg.n[1] * cfg.n[2]
+    for t, k, what in ((U, nc * cells, "U"), (out, nc, "out")):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and t.numel() == k and t.device == U.device):
+            raise HydroError(E_INVAL, f"conserved_totals_noalloc: {what} needs a contiguous float64 CUDA "
+                                      f"tensor of {k} values on the state's device")
+    s = stream or torch.cuda.current_stream(U.device)
+    _check(_lib.hydro_conserved_totals_noalloc(C.byref(cfg), _vp(U.data_ptr()), _vp(out.data_ptr()),
+                                                _vp(s.cuda_stream)), "hydro_conserved_totals_noalloc")
 
 
 def tile_candidates(ndim, n, precision=FP64):

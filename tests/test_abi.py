@@ -68,6 +68,13 @@ def test_create_rejects_bad_arguments_without_device(H):
     assert H._lib.hydro_riemann_fluxes(3, 1, 1.4, 10, None, None, None, None) == H.E_INVAL
     assert H._lib.hydro_riemann_fluxes(0, 1, 1.4, 0, None, None, None, None) == H.OK
     assert "non-physical" in H.strerror(H.E_NONPHYSICAL)
+    # the allocation-free totals refuse an invalid call before any device work
+    bad = H.make_config((64,), 1.0, 0.4)
+    p = C.c_void_p(256)
+    assert H._lib.hydro_conserved_totals_noalloc(C.byref(cfg), None, p, None) == H.E_INVAL
+    assert H._lib.hydro_conserved_totals_noalloc(C.byref(cfg), p, None, None) == H.E_INVAL
+    assert H._lib.hydro_conserved_totals_noalloc(None, p, p, None) == H.E_INVAL
+    assert H._lib.hydro_conserved_totals_noalloc(C.byref(bad), p, p, None) == H.E_INVAL
 
 
 def test_batch_rejects_invalid_members_without_device(H):

@@ -17,10 +17,11 @@
 // Floating point: the compiler contracts nothing on its own (contraction is
 // off), but the code fuses by hand where it pays -- explicit fused
 // multiply-adds, FP64 reciprocals and reciprocal square roots from the
-// hardware estimates refined by two Newton steps (about 1 ulp), and
-// algebraically equal rearrangements of the written formulas.  The FP64 path
-// therefore agrees with a plain serial evaluation of the same formulas to
-// rounding, not bitwise.
+// hardware estimates refined by Newton steps (two, about 1 ulp, in the
+// conversions and the time step; one, about 2^-45 relative, in the HLLC
+// solve), and algebraically equal rearrangements of the written formulas.
+// The FP64 path therefore agrees with a plain serial evaluation of the same
+// formulas to rounding, not bitwise.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -51,8 +52,11 @@ __device__ __forceinline__ constexpr int vcomp(int ax) {
 // Arithmetic policy.  FP32 (the mixed path's reconstruction and Riemann
 // solve): the hardware reciprocal and reciprocal square root (1 ulp), which
 // the FP32 tolerance of that path absorbs.  FP64: the hardware estimates
-// refined by two Newton steps each (about 1 ulp), instead of the longer
-// correctly rounded division and square-root sequences.
+// (relative error up to about 2^-23) refined by Newton steps instead of the
+// longer correctly rounded division and square-root sequences -- two steps
+// (about 1 ulp) for the conversions and the time step, one step (relative
+// error about 2^-45) for the six per HLLC face (rcp1, rsq1), well inside the
+// 1e-12 agreement the FP64 path keeps with a plain evaluation.
 template <typename R>
 struct Ops;
 
@@ -73,6 +77,14 @@ struct Ops<double> {
         e = __builtin_fma(-x * y, y, 1.0);
         return __builtin_fma(0.5 * y, e, y);
     }
+    static __device__ __forceinline__ double rcp1(double x) {
+        const double r = __builtin_amdgcn_rcp(x);
+        return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    }
+    static __device__ __forceinline__ double rsq1(double x) {
+        const double y = __builtin_amdgcn_rsq(x);
+        return __builtin_fma(0.5 * y, __builtin_fma(-x * y, y, 1.0), y);
+    }
     static __device__ __forceinline__ double max0(double x) { return __builtin_fmax(x, 0.0); }
     // median of (a, b, 0): the minmod of eq. minmod
     static __device__ __forceinline__ double minmod(double a, double b) {
@@ -85,6 +97,8 @@ struct Ops<float> {
     static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float rcp1(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float rsq1(float x) { return __builtin_amdgcn_rsqf(x); }
     static __device__ __forceinline__ float max0(float x) { return __builtin_fmaxf(x, 0.0f); }
     static __device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
 };
@@ -120,12 +134,15 @@ __device__ __forceinline__ R minmod(R a, R b) {
 // Conserved -> primitive in FP64 (Sec. 3.1): r = 1/rho, v_d = m_d r,
 // p = (gamma - 1)(E - (1/2) r sum_d m_d^2); returns admissibility.  The
 // squares are rounded separately and summed in axis order, so interchanging
-// x and y leaves the result bitwise unchanged.
-template <int NDIM>
+// x and y leaves the result bitwise unchanged.  LOWP: the values are rounded
+// to FP32 afterwards, so 1/rho takes one Newton step instead of two.
+// Admissibility is rho and p positive and finite: a non-finite momentum or
+// energy makes p NaN or infinite, so it needs no test of its own.
+template <int NDIM, bool LOWP = false>
 __device__ __forceinline__ bool cons_to_prim(double gm1, const double (&u)[NDIM + 2],
                                              double (&w)[NDIM + 2]) {
     const double rho = u[0];
-    const double r = Ops<double>::rcp(rho);
+    const double r = LOWP ? Ops<double>::rcp1(rho) : Ops<double>::rcp(rho);
     double msq = 0.0;
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) {
@@ -135,10 +152,7 @@ __device__ __forceinline__ bool cons_to_prim(double gm1, const double (&u)[NDIM 
     const double p = gm1 * __builtin_fma(-0.5 * r, msq, u[NDIM + 1]);
     w[0] = rho;
     w[NDIM + 1] = p;
-    bool fin = true;
-#pragma unroll
-    for (int c = 0; c < NDIM + 2; ++c) fin = fin && __builtin_isfinite(u[c]);
-    return fin && rho > 0.0 && p > 0.0 && __builtin_isfinite(p);
+    return rho > 0.0 && rho < __builtin_inf() && p > 0.0 && p < __builtin_inf();
 }
 
 // HLLC flux in the face-normal frame, W = (rho, u, t_1..t_NT, p).
@@ -160,18 +174,18 @@ __device__ __forceinline__ void hllc(const Gas<R>& gas, const R (&WL)[NT + 3], c
     const R rl = WL[0], ul = WL[1], pl = WL[NC - 1];
     const R rr = WR[0], ur = WR[1], pr = WR[NC - 1];
     const R gpl = g * pl, gpr = g * pr;
-    const R cl = gpl * O::rsq(gpl * rl);
-    const R cr = gpr * O::rsq(gpr * rr);
+    const R cl = gpl * O::rsq1(gpl * rl);
+    const R cr = gpr * O::rsq1(gpr * rr);
     const R ppv = R(0.5) * (pl + pr) - R(0.125) * (ur - ul) * (rl + rr) * (cl + cr);
     const R ps = O::max0(ppv);
     const R al = g * O::fma(gas.z, O::max0(ps - pl), pl);
     const R ar = g * O::fma(gas.z, O::max0(ps - pr), pr);
-    const R dsl = -(al * O::rsq(al * rl));
-    const R dsr = ar * O::rsq(ar * rr);
+    const R dsl = -(al * O::rsq1(al * rl));
+    const R dsr = ar * O::rsq1(ar * rr);
     const R sl = ul + dsl;
     const R sr = ur + dsr;
     const R ml = rl * dsl, mr = rr * dsr;  // rho_K ds_K
-    const R ss = (O::fma(-mr, ur, pr) - O::fma(-ml, ul, pl)) * O::rcp(ml - mr);
+    const R ss = (O::fma(-mr, ur, pr) - O::fma(-ml, ul, pl)) * O::rcp1(ml - mr);
 
     // s_L >= 0: F_L ; s_* >= 0: F*_L ; s_R > 0: F*_R ; else F_R
     const bool left = (sl >= R(0)) || (ss >= R(0));
@@ -208,7 +222,7 @@ __device__ __forceinline__ void hllc(const Gas<R>& gas, const R (&WL)[NT + 3], c
     // star state chi (1, s_*, t, E/rho + (s_* - u)(s_* + p/(rho ds))),
     // chi = rho ds / (s - s_*), with 1/(s - s_*) and 1/(rho ds) from one reciprocal
     const R t1 = sK - ss;
-    const R q = O::rcp(t1 * mK);
+    const R q = O::rcp1(t1 * mK);
     const R chi = mK * (mK * q);
     const R p_m = p * (t1 * q);
     const R e_rho = O::fma(cK * cK, gas.inv_g_gm1, R(0.5) * vsq);
@@ -606,7 +620,7 @@ __device__ __forceinline__ void to_prim(double gm1, const double (&u)[NDIM + 2],
                                         R (&W)[NDIM + 2], bool& bad) {
     constexpr int NC = NDIM + 2;
     double w[NC];
-    const bool ok = cons_to_prim<NDIM>(gm1, u, w);
+    const bool ok = cons_to_prim<NDIM, sizeof(R) == 4>(gm1, u, w);
     if (CHECK) bad |= !ok;
     if (vax >= 0) {
         const int vc = vax == 0 ? 1 : (vax == 1 ? 2 : NDIM);
@@ -728,6 +742,11 @@ struct StageOccupancy {
     static constexpr bool kOneBarrier =
         (NDIM == 3 || kOne2D) &&
         ((sizeof(R) == 4 && MODE == MODE_STAGE1) || (sizeof(R) == 8 && MODE == MODE_STAGE2));
+    // The raw halo cell of the next plane loaded one iteration ahead, so the
+    // barrier after the plane's W does not wait for it: ten more registers,
+    // which the Heun stage 2 (three waves per SIMD in mixed precision, two in
+    // FP64) holds without losing occupancy; the stage 1 would lose a wave.
+    static constexpr bool kHaloPrefetch = NDIM == 3 && MODE == MODE_STAGE2;
 };
 
 template <int NDIM, typename R, int MODE, int TX, int TY>
@@ -818,6 +837,10 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
         }
     }
 
+    // whether an in-plane side treats the normal velocity of its ghosts
+    // (outflow, reflecting); uniform over the grid
+    const bool halo_vm = g.bc[0][0] >= BC_OUTFLOW || g.bc[0][1] >= BC_OUTFLOW ||
+                         (HY && (g.bc[1][0] >= BC_OUTFLOW || g.bc[1][1] >= BC_OUTFLOW));
     const double dt_step = a.use_device_dt ? device_dt(a.ctrl) : a.dt_host;
     const double dt = PRED ? 0.5 * dt_step : dt_step;  // the predictor advances half a step
     const double lam0 = dt / g.dx[0];
@@ -849,6 +872,9 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
     // between iterations so a load lands directly where it is consumed
     double uiA[NC], uiB[NC];
     int vmA = VM_NONE, vmB = VM_NONE;
+    // the raw halo cell of this thread (HALO_PF: the next plane's, in flight)
+    constexpr bool HALO_PF = StageOccupancy<NDIM, R, MODE>::kHaloPrefetch;
+    double uhalo[NC];
 
     // interior plane z (any z: outside the mesh it is a ghost plane)
     // cell (plane offset poff, the same for the work-group) + (in-plane index tc)
@@ -932,6 +958,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
         }
         load_interior(z0 + 2, uiA, vmA);
     }
+    if (HALO_PF && hact && z0 < z1) load_halo(z0, uhalo);
 
     // One iteration: plane k enters the stencil (its raw data ui, the ghost
     // treatment vmi), plane k+3 is loaded into un (vmn), and one plane is
@@ -948,7 +975,10 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
             if (HZ) {
                 // W_{k+2} arrived: z face k+1/2 from (W_k, W_{k+1}, W_{k+2})
                 R w2[NC], wr[NC];
-                in_to_w<NDIM, R, PRIM_IN>(gm1, ui, vmi == VM_NONE ? -1 : 2, vmi, w2, bad);
+                // the ghost treatment of a plane is the same for the whole
+                // work-group: held in a scalar register, it costs no divergence
+                const int vz = __builtin_amdgcn_readfirstlane(vmi);
+                in_to_w<NDIM, R, PRIM_IN>(gm1, ui, vz == VM_NONE ? -1 : 2, vz, w2, bad);
                 // plane k+2 is an interior plane whenever its update comes
                 if (RING) {
 #pragma unroll
@@ -999,13 +1029,15 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
             for (int c = 0; c < NC; ++c) sW[bw][c][ly + 2][lx + 2] = wc[c];
         }
         if (live && hact) {
-            double uh[NC];
             R wh[NC];
-            load_halo(k, uh);
+            // the halo cell of plane k: loaded one iteration ahead (HALO_PF),
+            // else now
+            if (!HALO_PF) load_halo(k, uhalo);
             // not checked here: every cell is checked by the tile that owns it
-            in_to_w<NDIM, R, PRIM_IN, false>(gm1, uh, hvax, hvm, wh, bad);
+            in_to_w<NDIM, R, PRIM_IN, false>(gm1, uhalo, halo_vm ? hvax : -1, hvm, wh, bad);
 #pragma unroll
             for (int c = 0; c < NC; ++c) sW[bw][c][hy + 2][hx + 2] = wh[c];
+            if (HALO_PF && k + 1 < z1) load_halo(k + 1, uhalo);
         }
         __syncthreads();
 

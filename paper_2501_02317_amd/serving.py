@@ -40,6 +40,7 @@ class Request:
     admitted: float = None
     finished: float = None
     failed: bool = False
+    steps_done: int = 0            # steps completed when the request was retired
     result: np.ndarray = None
 
     @property
@@ -198,13 +199,14 @@ class Server:
             self.iterations += 1
             now = time.perf_counter() - start
             keep = []
-            for m, d, f in zip(active, done, flags):
+            for m, d, f, k in zip(active, done, flags, steps):
                 m["W"] = None                           # upload has completed
                 if d or f:
                     r = m["req"]
                     r.finished = now
                     finished += 1
                     r.failed = bool(f)
+                    r.steps_done = int(k)
                     if r.rid in self.keep:
                         r.result = m["h"].get_state()
                     m["h"].close()
@@ -243,6 +245,12 @@ def latency_report(requests, warmup_frac=0.05):
         "mean_queue_s": float(wait.mean()) if len(wait) else None,
         "mean_service_s": float(serv.mean()) if len(serv) else None,
         "cell_updates_per_s": work / (t1 - t0) if t1 > t0 else None,
+        # the spec of every failed request (its initial state follows from
+        # the spec alone), so it can be re-run on its own or by the oracle
+        "failed_requests": [
+            {"rid": r.rid, "ndim": r.ndim, "n": r.n, "steps": r.steps, "steps_done": r.steps_done,
+             "mach": r.mach, "gamma": r.gamma, "precision": "fp64" if r.precision == H.FP64 else "mixed",
+             "seed": r.seed} for r in requests if r.failed],
     }
 
 

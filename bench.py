@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the library's default stage tiles (no autotuning), e.g. for profiler "
                          "runs that should see one kernel per stage")
+    ap.add_argument("--cpu-worker", default="",
+                    help="internal: run one single-thread oracle worker seed,n,steps,start_at and exit")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes five times "
                          "(calibrates the HBM byte counters) and exit")
@@ -294,18 +296,78 @@ def run_serving(count, calib):
     return rep
 
 
-def cpu_baseline(case):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_worker(seed, n, steps, start_at):
+    """One single-threaded oracle run (bench.py --cpu-worker): a seeded n^3
+    Mach-1 random field, `steps` Heun steps from its CFL dt, started at the
+    wall-clock time start_at so that concurrent workers overlap."""
     import oracle as O
+    from paper_2501_02317_amd import workloads as wl
+    c = wl.turbulence_3d(n=n, mach=1.0, seed=seed, steps=steps, cfl=0.3)
+    m = O.Mesh(c.n, c.gamma, c.lo, c.hi, c.bc)
+    U = O.prim_to_cons(m, c.W)
+    time.sleep(max(0.0, start_at - time.time()))
+    t0 = time.time()
+    _, _, done, _ = O.run(m, U, c.cfl, max_steps=steps)
+    t1 = time.time()
+    print(json.dumps({"cells": c.ncells, "steps": done, "start": t0, "end": t1}), flush=True)
+
+
+def cpu_workers(count, n, steps, seed0, delay=15.0):
+    """count concurrent single-thread oracle processes; returns
+    (cell-updates/s over the common window, per-worker records)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    start_at = time.time() + delay + 0.5 * count  # after every worker has built its state
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker",
+                               f"{seed0 + i},{n},{steps},{start_at}"], env=env, stdout=subprocess.PIPE,
+                              text=True) for i in range(count)]
+    recs = []
+    for p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle worker failed ({p.returncode})")
+        recs.append(json.loads(out.strip().splitlines()[-1]))
+    work = sum(r["cells"] * r["steps"] for r in recs)
+    wall = max(r["end"] for r in recs) - min(r["start"] for r in recs)
+    return work / wall, recs
+
+
+def cpu_baseline(case):
+    """The FP64 oracle on the host cores, as it stands (not tuned): one
+    thread on a 128^3 mesh; one single-thread process per core of this
+    process's CPU set (at most 16, the box's share), each on its own seeded
+    128^3 mesh, run at once (the value); and the OpenMP build over those
+    cores for one Heun step of the 256^3 benchmark state."""
+    import oracle as O
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    nproc = min(ncores, 16)
+    single, _ = cpu_workers(1, 128, 2, 7000)
+    allc, recs = cpu_workers(nproc, 128, 1, 7100)
     m = O.Mesh(case.n, case.gamma, case.lo, case.hi, case.bc)
     U = O.prim_to_cons(m, case.W)
     dt = O.cfl_dt(m, U, case.cfl)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = int(os.environ.get("OMP_NUM_THREADS", nproc))
     t0 = time.perf_counter()
     O.heun_step(m, U, dt)
     el = time.perf_counter() - t0
-    return {"value": case.ncells / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"one FP64 Heun step (dt from the oracle's CFL reduction) of the same "
-                      f"{'x'.join(map(str, case.n))} Mach-2 state, {el:.1f} s on the host"}
+    return {"value": allc, "unit": "cell-updates/s", "cores": nproc, "kind": "oracle",
+            "sample": f"{nproc} concurrent single-thread oracle processes, each one FP64 Heun step of its own "
+                      f"seeded 128^3 Mach-1 state ({sum(r['cells'] * r['steps'] for r in recs):.3g} "
+                      f"cell-updates in the common window)",
+            "single_core": single,
+            "openmp": {"value": case.ncells / el, "threads": threads,
+                       "sample": f"one Heun step of the {'x'.join(map(str, case.n))} Mach-2 state, {el:.1f} s"},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity_cores": ncores}
 
 
 def traffic_record(precision, tiles):
@@ -329,6 +391,10 @@ def traffic_record(precision, tiles):
 
 def main():
     args = parse()
+    if args.cpu_worker:
+        seed, n, steps, start_at = args.cpu_worker.split(",")
+        cpu_worker(int(seed), int(n), int(steps), float(start_at))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU path is a design only)", file=sys.stderr)

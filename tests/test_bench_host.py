@@ -43,3 +43,14 @@ def test_traffic_record_is_keyed_to_tiles_and_source():
         assert bench.traffic_record(prec, [[1, 1, 1], [1, 1, 1]]) is None
         got = bench.traffic_record(prec, entry["tiles"])
         assert got is None or got == entry["bytes_per_step_pair"]
+
+
+def test_concurrent_oracle_workers_report_a_common_window():
+    # two single-thread oracle processes on small seeded meshes: the rate is
+    # their summed cell-updates over the window from the first start to the
+    # last end, and every worker did the steps it was asked for
+    rate, recs = bench.cpu_workers(2, 16, 2, 9000, delay=3.0)
+    assert len(recs) == 2
+    assert all(r["cells"] == 16 ** 3 and r["steps"] == 2 and r["end"] > r["start"] for r in recs)
+    wall = max(r["end"] for r in recs) - min(r["start"] for r in recs)
+    assert rate == pytest.approx(2 * 2 * 16 ** 3 / wall)

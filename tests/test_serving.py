@@ -95,3 +95,59 @@ def test_admission_respects_memory_budget():
     # and the budget made some wait for memory to free up
     assert max(resident_at) >= 2
     assert any(q.admitted >= p.finished for p in reqs for q in reqs if q is not p)
+
+
+# The one request of the 2000-request serving run that was retired as failed:
+# 3-D 64^3, Mach 3.0, gamma 5/3, FP64, this seed (its spec as the bench's
+# serving record lists it).  Its flow expands until the pressure reaches zero.
+FAILED_SPEC = dict(ndim=3, n=64, mach=2.9989993467151863, gamma=5.0 / 3.0, seed=1069413739)
+
+
+def failed_request_state():
+    from paper_2501_02317_amd import workloads as wl
+    s = FAILED_SPEC
+    W = wl.random_field_device(s["ndim"], s["n"], s["mach"], s["gamma"], s["seed"], kmax=min(16, s["n"] // 8),
+                               device="cpu")
+    return W.numpy()
+
+
+def test_failed_request_is_nonphysical_in_the_oracle_too():
+    """The method has no density or pressure floors: the FP64 oracle takes
+    the failed request's state through 52 steps and meets a non-physical cell
+    in step 53, as the GPU did (it retired the request in the iteration that
+    ends with step 64)."""
+    import oracle as O
+    W = failed_request_state()
+    m = O.Mesh((64, 64, 64), FAILED_SPEC["gamma"], (0.0,) * 3, (1.0,) * 3, ((0, 0),) * 3)
+    U, t, s, _ = O.run(m, O.prim_to_cons(m, W), 0.3, max_steps=52)
+    assert s == 52
+    assert O.cons_to_prim(m, U)[4].min() > 0.0
+    with pytest.raises(O.OracleError, match="non-physical"):
+        O.run(m, U, 0.3, max_steps=1, t0=t)
+
+
+@pytest.mark.gpu
+def test_failed_request_fails_in_the_same_step_on_the_gpu():
+    """The FP64 GPU path on the failed request alone: after 52 steps it
+    matches the oracle and is physical; step 53 raises the non-physical flag."""
+    import torch
+    assert torch.cuda.is_available()
+    import oracle as O
+    from paper_2501_02317_amd import hydro as H
+    from gpu_util import rel_l1
+    W = failed_request_state()
+    m = O.Mesh((64, 64, 64), FAILED_SPEC["gamma"], (0.0,) * 3, (1.0,) * 3, ((0, 0),) * 3)
+    U_o, t_o, s_o, _ = O.run(m, O.prim_to_cons(m, W), 0.3, max_steps=52)
+    say("failed request alone", FAILED_SPEC)
+    h = H.Hydro((64, 64, 64), FAILED_SPEC["gamma"], 0.3, precision=H.FP64)
+    h.set_primitive(W)
+    h.step_auto(52)
+    U = h.get_state()
+    assert h.steps_done() == 52
+    assert np.all(rel_l1(U, U_o) <= 1e-12)
+    assert h.time() == pytest.approx(t_o, rel=1e-13)  # a blocking call: no flag yet
+    h.step_auto(1)
+    with pytest.raises(H.HydroError) as e:
+        h.time()
+    assert e.value.status == H.E_NONPHYSICAL
+    h.close()

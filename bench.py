@@ -273,7 +273,8 @@ def run_serving(count, calib):
     for r in sat:
         r.arrival = 0.0
     work = sum(r.cells * r.steps for r in sat)
-    t_served = S.Server(96 << 30, steps_per_iter=16).run(sat, time_limit=300.0, log=log)
+    sat_srv = S.Server(96 << 30, steps_per_iter=16)
+    t_served = sat_srv.run(sat, time_limit=300.0, log=log)
     capacity = work / t_served
     t0 = time.perf_counter()
     for r in S.request_stream(calib, 1.0, seed=502):
@@ -283,8 +284,12 @@ def run_serving(count, calib):
     rate = 0.8 * capacity / S.mean_work()
     reqs = S.request_stream(count, rate, seed=501)
     srv = S.Server(96 << 30, steps_per_iter=16)
-    srv.run(reqs, time_limit=600.0, log=log)
+    wall = srv.run(reqs, time_limit=600.0, log=log)
     rep = S.latency_report(reqs)
+    # host time per phase of the serving loop; "wait" is the status read,
+    # which waits for the device
+    rep["host_phase_s"] = {k: round(v, 3) for k, v in srv.phase_s.items()}
+    rep["wall_s"] = wall
     rep["offered_rate_per_s"] = rate
     rep["offered_load_frac"] = 0.8
     rep["requests"] = count
@@ -293,6 +298,8 @@ def run_serving(count, calib):
     rep["saturated_cell_updates_per_s"] = capacity
     rep["one_at_a_time_cell_updates_per_s"] = work / t_one
     rep["saturated_speedup"] = t_one / t_served
+    rep["saturated_host_phase_s"] = {k: round(v, 3) for k, v in sat_srv.phase_s.items()}
+    rep["saturated_wall_s"] = t_served
     return rep
 
 

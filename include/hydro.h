@@ -30,8 +30,8 @@
  *   - Device memory is owned by the caller: hydro_create carves its state
  *     out of a caller-provided device workspace of at least
  *     hydro_workspace_bytes(cfg) bytes (256-byte aligned), which must outlive
- *     the handle.  The handle itself owns only host metadata, a small
- *     pinned host staging buffer and, once hydro_set_block_streams turns them
+ *     the handle.  The handle itself owns only host metadata (among it a
+ *     pageable mirror of its control block) and, once hydro_set_block_streams turns them
  *     on, its block streams and events (a refined handle: its second stream
  *     and three events).  hydro_stage_rhs,
  *     hydro_padded_primitive and the host transfers of a split mesh take a
@@ -124,7 +124,9 @@ typedef struct {
 size_t hydro_workspace_bytes(const hydro_config* cfg);
 
 /* Validate cfg, carve the workspace, and bind the stream.  The state is zero
- * until hydro_set_state / hydro_set_primitive.  *out receives the handle. */
+ * until hydro_set_state / hydro_set_primitive.  *out receives the handle.
+ * The zeroing is enqueued on the stream and the call returns without waiting
+ * for the stream (work already in flight there is not waited for). */
 int hydro_create(const hydro_config* cfg, void* d_workspace, size_t nbytes, void* hip_stream,
                  hydro_t* out);
 
@@ -326,8 +328,8 @@ const char* hydro_strerror(int status);
 /*
  * Batches: many independent meshes (any mix of ndim, sizes, precision and
  * tiles) advanced together.  The members are existing handles that share one
- * HIP stream; the batch keeps a descriptor table and a work-group table in a
- * caller-owned device workspace of hydro_batch_workspace_bytes(n, members)
+ * HIP stream; the batch keeps a descriptor table, a work-group table and a
+ * member status table in a caller-owned device workspace of hydro_batch_workspace_bytes(n, members)
  * bytes (0 when the members are invalid: NULL, repeated, broken, or on
  * different streams).  A batched step is one launch per (ndim, precision,
  * tile) group for each stage over all members' tiles, then one launch that
@@ -360,7 +362,8 @@ int hydro_batch_autotune(hydro_batch_t b, int steps_per_rule, int* rule, double*
 
 /* Per-member run-limit flag (done[i] = 1 once member i reached its limit),
  * optional completed step counts and sticky error flags (bit 0:
- * non-physical state); blocks on the batch stream. */
+ * non-physical state); blocks on the batch stream (one small gather launch
+ * and one copy for all members). */
 int hydro_batch_status(hydro_batch_t b, int* done, int64_t* steps, int* flags);
 /* Number of launch groups, total work-groups per stage, and whether steps run from a graph. */
 int hydro_batch_info(hydro_batch_t b, int* groups, int64_t* workgroups, int* graph);

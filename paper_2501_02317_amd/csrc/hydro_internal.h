@@ -126,6 +126,8 @@ void plan_tiles(const Geo& g, const Tile& t, int& tiles_x, int& tiles_y, int& ch
 // blk[i] = (member, work-group within the member), nblk entries.
 hipError_t launch_stage_batch(int ndim, int precision, int mode, const Tile& tile, const MeshDesc* d,
                               const int2* blk, int nblk, hipStream_t s);
+// (done, flags, steps) of members [0, n) of a descriptor table into out[3 i ..].
+hipError_t launch_status_gather(const MeshDesc* d, int n, unsigned long long* out, hipStream_t s);
 // CTRL_FINALIZE_STEP for members [0, n) of a descriptor table.
 hipError_t launch_ctrl_batch(const MeshDesc* d, int n, hipStream_t s);
 hipError_t launch_dt(const Geo& g, const double* U, Ctrl* ctrl, hipStream_t s);

@@ -1335,6 +1335,17 @@ __global__ void ctrl_kernel(Ctrl* c, int op, double a0, double a1, double cfl) {
     }
 }
 
+// Status of every batch member (done, flags, steps) into one table.
+__global__ void status_gather_kernel(const MeshDesc* __restrict__ d, int n, unsigned long long* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const Ctrl* c = d[i].ctrl;
+        out[3 * i] = c->done;
+        out[3 * i + 1] = c->flags;
+        out[3 * i + 2] = c->steps;
+    }
+}
+
 __global__ void ctrl_batch_kernel(const MeshDesc* __restrict__ d, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) finalize_step(d[i].ctrl, d[i].geo.cfl);
@@ -2103,6 +2114,12 @@ hipError_t launch_stage_batch(int ndim, int precision, int mode, const Tile& til
     if (mode == MODE_RHS) return hipErrorInvalidValue;
     LaunchCtx L{nullptr, d, blk, nblk};
     return launch_any(ndim, precision, mode, tile, L, s);
+}
+
+hipError_t launch_status_gather(const MeshDesc* d, int n, unsigned long long* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(status_gather_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_ctrl_batch(const MeshDesc* d, int n, hipStream_t s) {

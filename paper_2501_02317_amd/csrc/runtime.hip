@@ -55,7 +55,7 @@ struct hydro_ctx {
     double* U1;     // predictor U1 / scratch
     double* parts;  // totals partials
     Ctrl* ctrl;
-    Ctrl* host_ctrl;  // pinned mirror for reads
+    Ctrl* host_ctrl;  // host mirror for reads (pageable: no pinning or unpinning per handle)
     bool broken;
     bool dt_valid;    // ctrl->dt_raw belongs to the current state (host-side knowledge)
     // optional event timing of the stage launches
@@ -689,15 +689,18 @@ int hydro_create(const hydro_config* cfg, void* d_workspace, size_t nbytes, void
     h->ctrl = (Ctrl*)p;
     p += align_up(sizeof(Ctrl));
     h->parts = (double*)p;
-    if (hipHostMalloc((void**)&h->host_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+    h->host_ctrl = new (std::nothrow) Ctrl;
+    if (!h->host_ctrl) {
         delete h;
         return HYDRO_E_NOMEM;
     }
+    // stream-ordered set-up, no host synchronisation: a handle made while
+    // other work is in flight on the stream (a serving loop admitting a
+    // request behind running steps) does not wait for that work
     hipError_t e = hipMemsetAsync(h->U, 0, sb + sb2, h->stream);
     if (e == hipSuccess) e = launch_ctrl(h->ctrl, CTRL_INIT, 0.0, 0.0, cfg->cfl, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
-        (void)hipHostFree(h->host_ctrl);
+        delete h->host_ctrl;
         delete h;
         return HYDRO_E_DEVICE;
     }
@@ -772,7 +775,8 @@ int hydro_smr_create(const hydro_config* cfg, int nref, const int32_t* refined, 
     h->gbuf = (double*)p;
     p += align_up(P.tasks.size() * nc * (size_t)P.gcs * sizeof(double));
     h->dbuf = (double*)p;
-    if (hipHostMalloc((void**)&h->host_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+    h->host_ctrl = new (std::nothrow) Ctrl;
+    if (!h->host_ctrl) {
         delete[] h->leaves;
         delete h;
         return HYDRO_E_NOMEM;
@@ -804,7 +808,7 @@ int hydro_smr_create(const hydro_config* cfg, int nref, const int32_t* refined, 
         }
     }
     if (e != hipSuccess) {
-        (void)hipHostFree(h->host_ctrl);
+        delete h->host_ctrl;
         delete[] h->leaves;
         delete h;
         return HYDRO_E_DEVICE;
@@ -1327,7 +1331,7 @@ int hydro_destroy(hydro_t h) {
         (void)hipStreamDestroy(h->smr_aux);
     }
     delete[] h->leaves;
-    (void)hipHostFree(h->host_ctrl);
+    delete h->host_ctrl;
     delete h;
     return HYDRO_OK;
 }
@@ -1375,7 +1379,8 @@ struct hydro_batch_ctx {
     int graph_steps;
     bool use_graph;
     bool broken;
-    Ctrl* h_ctrl;  // pinned staging for member status reads
+    unsigned long long* d_status;  // per member (done, flags, steps), gathered on the device
+    std::vector<unsigned long long> h_status;
 };
 
 namespace {
@@ -1451,7 +1456,8 @@ bool plan_batch(int n, const hydro_t* members, BatchPlan& P, int rule = 0) {
 }
 
 size_t batch_bytes(const BatchPlan& P) {
-    return align_up(P.desc.size() * sizeof(MeshDesc)) + align_up(P.blk.size() * sizeof(int2));
+    return align_up(P.desc.size() * sizeof(MeshDesc)) + align_up(P.blk.size() * sizeof(int2)) +
+           align_up(P.desc.size() * 3 * sizeof(unsigned long long));
 }
 
 bool members_ok(int n, const hydro_t* members) {
@@ -1526,11 +1532,11 @@ int hydro_batch_create(int n, const hydro_t* members, void* d_workspace, size_t 
     // stream capture needs a stream other than the legacy default stream
     b->use_graph = use_graph != 0 && b->stream != nullptr;
     b->broken = false;
-    b->h_ctrl = nullptr;
-    if (hipHostMalloc((void**)&b->h_ctrl, (size_t)n * sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
-        delete b;
-        return HYDRO_E_NOMEM;
-    }
+    // the status table after the two plan tables, whose sizes differ between
+    // tile rules: at the end of the workspace the largest plan needs
+    b->d_status = (unsigned long long*)((char*)d_workspace + hydro_batch_workspace_bytes(n, members) -
+                                        align_up((size_t)n * 3 * sizeof(unsigned long long)));
+    b->h_status.assign((size_t)n * 3, 0ull);
     hipError_t e = hipMemcpyAsync(b->d_desc, P.desc.data(), P.desc.size() * sizeof(MeshDesc),
                                   hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
@@ -1538,7 +1544,6 @@ int hydro_batch_create(int n, const hydro_t* members, void* d_workspace, size_t 
                            b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
-        (void)hipHostFree(b->h_ctrl);
         delete b;
         return HYDRO_E_DEVICE;
     }
@@ -1658,19 +1663,21 @@ int hydro_batch_status(hydro_batch_t b, int* done, int64_t* steps, int* flags) {
     if (!b || !done) return HYDRO_E_INVAL;
     if (b->broken) return HYDRO_E_STATE;
     const int n = (int)b->members.size();
-    // one asynchronous 192-byte copy per member into pinned staging, one sync
-    hipError_t e = hipSuccess;
-    for (int i = 0; i < n && e == hipSuccess; ++i)
-        e = hipMemcpyAsync(b->h_ctrl + i, b->members[i]->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, b->stream);
+    // every member's (done, flags, steps) gathered into one table on the
+    // device, one copy, one sync
+    hipError_t e = launch_status_gather(b->d_desc, n, b->d_status, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->h_status.data(), b->d_status, (size_t)n * 3 * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         b->broken = true;
         return HYDRO_E_DEVICE;
     }
     for (int i = 0; i < n; ++i) {
-        done[i] = b->h_ctrl[i].done ? 1 : 0;
-        if (steps) steps[i] = (int64_t)b->h_ctrl[i].steps;
-        if (flags) flags[i] = (int)b->h_ctrl[i].flags;
+        done[i] = b->h_status[3 * i] ? 1 : 0;
+        if (flags) flags[i] = (int)b->h_status[3 * i + 1];
+        if (steps) steps[i] = (int64_t)b->h_status[3 * i + 2];
     }
     return HYDRO_OK;
 }
@@ -1689,7 +1696,6 @@ int hydro_batch_destroy(hydro_batch_t b) {
     if (!b) return HYDRO_E_INVAL;
     if (!b->broken) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
-    (void)hipHostFree(b->h_ctrl);
     delete b;
     return HYDRO_OK;
 }

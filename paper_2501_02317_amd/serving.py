@@ -164,41 +164,65 @@ class Server:
 
     def run(self, requests, time_limit=None, log=None, log_every=10.0):
         """Serve requests (their arrival fields are offsets from the start).
-        log: optional callable given a progress line every log_every seconds."""
+        log: optional callable given a progress line every log_every seconds.
+
+        One iteration: (re)build the batch when its membership changed, enqueue
+        K batched steps, admit the requests that arrived meanwhile (their
+        set-up is host work that overlaps the steps on the device; their
+        initial states are enqueued behind the steps), then read every
+        member's status (the one synchronisation) and retire the finished
+        ones.  Host time per phase is accumulated in self.phase_s."""
         pending = collections.deque(sorted(requests, key=lambda q: q.arrival))
         total, finished, next_log = len(pending), 0, log_every
         queue = collections.deque()
-        active = []
+        active = []          # members of the current batch
+        joining = []         # admitted, joining at the next rebuild
         batch = None
-        dirty = True
+        ph = self.phase_s = collections.defaultdict(float)
         start = time.perf_counter()
-        while pending or queue or active:
-            now = time.perf_counter() - start
-            if time_limit is not None and now > time_limit:
-                break
+
+        def admit(now):
+            t = time.perf_counter()
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
-            while queue and len(active) < self.max_members:
+            while queue and len(active) + len(joining) < self.max_members:
                 m = self._admit(queue[0], now)
                 if m is None:
                     break
                 queue.popleft()
-                active.append(m)
-                dirty = True
-            if not active:
-                if pending:
-                    time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - start)))
-                continue
-            if dirty:
+                joining.append(m)
+            ph["admit"] += time.perf_counter() - t
+
+        while pending or queue or active or joining:
+            now = time.perf_counter() - start
+            if time_limit is not None and now > time_limit:
+                break
+            if not active and not joining:
+                admit(now)
+                if not joining:
+                    if pending:
+                        time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - start)))
+                    continue
+            if joining or batch is None:
+                t = time.perf_counter()
                 if batch is not None:
                     batch.close()
+                active.extend(joining)
+                joining = []
                 batch = H.Batch([m["h"] for m in active], use_graph=False)
-                dirty = False
+                ph["build"] += time.perf_counter() - t
+            t = time.perf_counter()
             batch.step(self.K)
+            ph["enqueue"] += time.perf_counter() - t
+            admit(time.perf_counter() - start)          # overlaps the steps
+            t = time.perf_counter()
             done, steps, flags = batch.status()        # synchronises the stream
+            ph["wait"] += time.perf_counter() - t
             self.iterations += 1
+            t = time.perf_counter()
             now = time.perf_counter() - start
             keep = []
+            retired = False
             for m, d, f, k in zip(active, done, flags, steps):
                 m["W"] = None                           # upload has completed
                 if d or f:
@@ -211,17 +235,24 @@ class Server:
                         r.result = m["h"].get_state()
                     m["h"].close()
                     self.arena.release(m["off"])
-                    dirty = True
+                    retired = True
                 else:
                     keep.append(m)
             active = keep
+            if retired:
+                if batch is not None:
+                    batch.close()
+                batch = None                            # rebuilt at the next iteration
+            for m in joining:
+                m["W"] = None
+            ph["retire"] += time.perf_counter() - t
             if log is not None and now >= next_log:
                 log(f"[serve] {now:.0f} s: {finished}/{total} finished, {len(active)} resident, "
                     f"{len(queue)} queued, {self.iterations} iterations")
                 next_log = now + log_every
         if batch is not None:
             batch.close()
-        for m in active:
+        for m in active + joining:
             m["h"].close()
             self.arena.release(m["off"])
         return time.perf_counter() - start

@@ -1,8 +1,9 @@
 """hydro_step_auto enqueues only kernels (no host synchronisation, no
 allocation, no memset), so it can be captured into a HIP graph: a single
 mesh, a mesh split into blocks, and a refined mesh.  While the handle's stream
-is captured, the forms that fork work onto other streams run on the handle's
-stream alone.  Each graph is replayed several times, with eager work and host
+is captured, the block-stream form adds its per-group stage kernels to the
+capture's graph as nodes with the group dependencies, and a refined mesh's
+second stream runs on the handle's stream.  Each graph is replayed several times, with eager work and host
 synchronisation between the replays, and every replay is checked bitwise
 against the same steps run eagerly."""
 import numpy as np
@@ -31,15 +32,10 @@ def make(H, c, stream, blocks=None, refined=None, streams=False, W=None, precisi
     return h
 
 
-SKIP_STREAMS = pytest.mark.skip(
-    reason="capturing the forked per-group streams crashed the host process inside the HIP runtime at the "
-           "end of the capture; the library now runs that form on the handle's stream while it is "
-           "captured, and this case stays off until the crash is understood")
 # name, blocks, refined, block streams, precision, integrator, t_end
 CASES = [pytest.param("single", None, None, False, 1, 0, 0.0, id="single"),
          pytest.param("blocks", (2, 2, 2), None, False, 1, 0, 0.0, id="blocks"),
-         pytest.param("block streams", (2, 2, 4), None, True, 1, 0, 0.0, id="block streams",
-                      marks=SKIP_STREAMS),
+         pytest.param("block streams", (2, 2, 4), None, True, 1, 0, 0.0, id="block streams"),
          pytest.param("refined", (2, 2, 2), [0, 5], False, 1, 0, 0.0, id="refined"),
          pytest.param("fp64", None, None, False, 0, 0, 0.0, id="fp64"),
          pytest.param("van Leer", (1, 2, 2), None, False, 1, 1, 0.0, id="van Leer"),

@@ -255,3 +255,42 @@ def test_invalid_refinement_rejected(bad):
     with pytest.raises(O.OracleError):
         O.SMR(O.Mesh((24, 16), 1.4), (4, 2), [0])     # blocks of 6 cells: fine
         O.SMR(O.Mesh((12, 16), 1.4), (4, 2), [0])     # blocks of 3 cells: odd
+
+
+def _sod_state(S, x0=0.3, axis=0):
+    """Sod's two states (1, 0, 1) | (0.125, 0, 0.1) split at x0 along axis."""
+    X = S.centres()
+    W = np.zeros(S.shape)
+    left = X[axis] < x0
+    W[:, 0] = np.where(left, 1.0, 0.125)
+    W[:, -1] = np.where(left, 1.0, 0.1)
+    return W
+
+
+def test_shock_through_refined_band_error_between_uniform_runs():
+    """Sod's shock tube with the refined band [0.375, 0.625) in its path: by
+    t = 0.2 the shock has entered and left the band (crossing both level
+    jumps, where the prolongation limiter and the flux correction act on a
+    discontinuity) and the contact sits inside it.  The density's L1 error
+    against the exact solution lies between those of the coarse and the fine
+    uniform meshes."""
+    gamma, x0 = 1.4, 0.3
+    left, right = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+
+    def err(n, B, ref):
+        m = O.Mesh((n,), gamma, bc=((F, F),))
+        S = O.SMR(m, (B,), ref)
+        U, t, s, _ = S.run(S.prim_to_cons(_sod_state(S, x0)), 0.4, t_end=0.2)
+        assert t == 0.2
+        W = S.cons_to_prim(U)
+        (X,) = S.centres()
+        ex = O.exact_sample(gamma, left, right, ((X - x0) / t).ravel())[0].reshape(X.shape)
+        dV = (1.0 / n) / 2.0 ** S.leaves[:, 0]
+        return float((np.abs(W[:, 0] - ex).reshape(len(S.leaves), -1).sum(axis=1) * dV).sum())
+
+    e_coarse, e_fine = err(64, 8, []), err(128, 16, [])
+    e_band = err(64, 8, [3, 4])
+    assert e_fine < e_band < e_coarse, (e_fine, e_band, e_coarse)
+    # refining the whole wave region gets close to the fine mesh
+    e_wide = err(64, 8, [2, 3, 4, 5])
+    assert e_wide < 1.1 * e_fine, (e_wide, e_fine)

@@ -120,6 +120,14 @@ struct MeshDesc {
 enum StageMode : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2, MODE_VL2_PRED = 3, MODE_VL2_CORR = 4 };
 
 hipError_t launch_stage(int precision, int mode, const Tile& tile, StageArgs a, hipStream_t s);
+// The same launch described (kernel, grid, block, arguments) instead of
+// enqueued, for a caller that adds it to a graph as a kernel node.
+struct StageLaunch {
+    const void* func;
+    dim3 grid, block;
+    StageArgs args;
+};
+hipError_t plan_stage_launch(int precision, int mode, const Tile& tile, StageArgs a, StageLaunch* out);
 // Fill the tiling fields of a descriptor for a tile.
 void plan_tiles(const Geo& g, const Tile& t, int& tiles_x, int& tiles_y, int& chunks_z, int& kz);
 // One stage over every mesh of a group sharing ndim, precision and tile:

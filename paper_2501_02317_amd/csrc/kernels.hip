@@ -1928,12 +1928,14 @@ int grid_for(long long work, int block, int cap) {
     return (int)(gb < cap ? gb : cap);
 }
 
-// Launch context: a single mesh (args) or a batch group (descriptor table).
+// Launch context: a single mesh (args) or a batch group (descriptor table);
+// with rec, a single-mesh launch is described there instead of enqueued.
 struct LaunchCtx {
     const StageArgs* a;
     const MeshDesc* d;
     const int2* blk;
     int nblk;
+    StageLaunch* rec;
 };
 
 // Work-groups of this stage kernel resident on the whole device at once
@@ -1972,6 +1974,13 @@ hipError_t launch_stage_t(const LaunchCtx& L, hipStream_t s) {
         }
         const long long nb = (long long)a.tiles_x * a.tiles_y * a.chunks_z * a.nblk;
         if (a.nblk < 1 || nb > 0x7fffffffll) return hipErrorInvalidValue;
+        if (L.rec) {
+            L.rec->func = reinterpret_cast<const void*>(&stage_kernel<NDIM, R, MODE, TX, TY>);
+            L.rec->grid = dim3((unsigned)nb);
+            L.rec->block = dim3(TX * TY);
+            L.rec->args = a;
+            return hipSuccess;
+        }
         hipLaunchKernelGGL((stage_kernel<NDIM, R, MODE, TX, TY>), dim3((unsigned)nb), dim3(TX * TY), 0, s, a);
     } else {
         if (L.nblk <= 0) return hipSuccess;
@@ -2105,14 +2114,22 @@ void plan_tiles(const Geo& g, const Tile& t, int& tiles_x, int& tiles_y, int& ch
 hipError_t launch_stage(int precision, int mode, const Tile& t, StageArgs a, hipStream_t s) {
     plan_tiles(a.geo, t, a.tiles_x, a.tiles_y, a.chunks_z, a.kz);
     if (t.kz == 0 && a.geo.ndim > 1) a.kz = 0;  // resolved per kernel at launch
-    LaunchCtx L{&a, nullptr, nullptr, 0};
+    LaunchCtx L{&a, nullptr, nullptr, 0, nullptr};
     return launch_any(a.geo.ndim, precision, mode, t, L, s);
+}
+
+hipError_t plan_stage_launch(int precision, int mode, const Tile& t, StageArgs a, StageLaunch* out) {
+    if (!out) return hipErrorInvalidValue;
+    plan_tiles(a.geo, t, a.tiles_x, a.tiles_y, a.chunks_z, a.kz);
+    if (t.kz == 0 && a.geo.ndim > 1) a.kz = 0;
+    LaunchCtx L{&a, nullptr, nullptr, 0, out};
+    return launch_any(a.geo.ndim, precision, mode, t, L, nullptr);
 }
 
 hipError_t launch_stage_batch(int ndim, int precision, int mode, const Tile& tile, const MeshDesc* d,
                               const int2* blk, int nblk, hipStream_t s) {
     if (mode == MODE_RHS) return hipErrorInvalidValue;
-    LaunchCtx L{nullptr, d, blk, nblk};
+    LaunchCtx L{nullptr, d, blk, nblk, nullptr};
     return launch_any(ndim, precision, mode, tile, L, s);
 }
 

@@ -345,6 +345,74 @@ hipError_t enqueue_step_streams(hydro_t h, bool device_dt, double dt) {
     return launch_ctrl(h->ctrl, CTRL_ADVANCE_T, dt, 0.0, h->cfg.cfl, h->stream);
 }
 
+// The same step while the handle's stream is captured into a graph: the
+// per-group stage launches become kernel nodes of the capture's graph with
+// the same dependencies (stage 1 of every group after what the stream had
+// captured; stage 2 of a group after stage 1 of its own group and of the
+// groups holding its blocks' face neighbours), the stream's capture then
+// continues from the stage-2 nodes.  No other stream and no event joins the
+// capture.
+hipError_t enqueue_step_streams_graph(hydro_t h, bool device_dt, double dt) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    unsigned long long id = 0;
+    hipGraph_t graph = nullptr;
+    const hipGraphNode_t* deps = nullptr;
+    size_t nd = 0;
+    hipError_t e = hipStreamGetCaptureInfo_v2(h->stream, &st, &id, &graph, &deps, &nd);
+    if (e != hipSuccess) return e;
+    if (st != hipStreamCaptureStatusActive || !graph) return hipErrorIllegalState;
+    const std::vector<hipGraphNode_t> d0(deps, deps + nd);  // valid until the next capture call
+    StageArgs a = stage_args(h);
+    a.use_device_dt = device_dt ? 1 : 0;
+    a.dt_host = dt;
+    a.conc = h->nblk;  // the groups run at once
+    auto range = [&](int g) {
+        a.blk0 = (int)(((long long)g * h->nblk) / h->nbs);
+        a.nblk = (int)(((long long)(g + 1) * h->nblk) / h->nbs) - a.blk0;
+    };
+    auto add = [&](int mode, const Tile& t, const std::vector<hipGraphNode_t>& dep, hipGraphNode_t* node) {
+        StageLaunch L;
+        hipError_t r = plan_stage_launch(h->cfg.precision, mode, t, a, &L);
+        if (r != hipSuccess) return r;
+        void* args[] = {&L.args};
+        hipKernelNodeParams p;
+        std::memset(&p, 0, sizeof(p));
+        p.func = const_cast<void*>(L.func);
+        p.gridDim = L.grid;
+        p.blockDim = L.block;
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        return hipGraphAddKernelNode(node, graph, dep.empty() ? nullptr : dep.data(), dep.size(), &p);
+    };
+    std::vector<hipGraphNode_t> s1(h->nbs, nullptr), s2(h->nbs, nullptr);
+    for (int g = 0; g < h->nbs && e == hipSuccess; ++g) {
+        range(g);
+        a.in = h->U;
+        a.base = h->U;
+        a.out = h->U1;
+        a.want_dt = 0;
+        e = add(stage1_mode(&h->cfg), h->tile[0], d0, &s1[g]);
+    }
+    for (int g = 0; g < h->nbs && e == hipSuccess; ++g) {
+        // it reads their stage-1 output, and they read the state it overwrites
+        std::vector<hipGraphNode_t> dep{s1[g]};
+        for (int o = 0; o < h->nbs; ++o)
+            if (o != g && h->gadj[g][o]) dep.push_back(s1[o]);
+        range(g);
+        a.in = h->U1;
+        a.base = h->U;
+        a.out = h->U;
+        a.want_dt = device_dt ? 1 : 0;
+        e = add(stage2_mode(&h->cfg), h->tile[1], dep, &s2[g]);
+    }
+    if (e == hipSuccess)
+        e = hipStreamUpdateCaptureDependencies(h->stream, s2.data(), s2.size(), hipStreamSetCaptureDependencies);
+    if (e != hipSuccess) return e;
+    if (device_dt) return launch_ctrl(h->ctrl, CTRL_FINALIZE_STEP, 0.0, 0.0, h->cfg.cfl, h->stream);
+    return launch_ctrl(h->ctrl, CTRL_ADVANCE_T, dt, 0.0, h->cfg.cfl, h->stream);
+}
+
 // Whether host transfers convert between the mesh layout and the block
 // layout: a split mesh; a refined mesh's transfers use the block layout.
 bool mesh_relayout(hydro_t h) { return h->nblk > 1 && !h->smr; }
@@ -378,10 +446,13 @@ hipError_t timed_stage(hydro_t h, int mode, const StageArgs& a) {
 // primitive state) then stage 2 in place over U^n, dt either from the host or
 // from the device control block (clamped to the run limit kept there).
 // Whether the handle's stream is being captured into a graph.  The forms
-// that fork work onto other streams and join it back by events (block
-// streams, a refined mesh's second stream) then run on the handle's stream
-// alone: capturing the forked form crashed in the HIP runtime at the end of
-// the capture.  The results do not depend on the form.
+// that fork work onto other streams and join it back by events are then not
+// captured as such: capturing that form (group streams waiting on each
+// other's events) crashed the host process in the HIP runtime at the end of
+// the capture.  The block-stream step is captured as explicit graph nodes
+// with the same dependencies instead (enqueue_step_streams_graph), and a
+// refined mesh's second stream runs on the handle's stream.  The results do
+// not depend on the form.
 bool capturing(hydro_t h) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     return hipStreamIsCapturing(h->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
@@ -447,7 +518,8 @@ hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
 
 hipError_t enqueue_step(hydro_t h, bool device_dt, double dt) {
     if (h->smr) return enqueue_step_smr(h, device_dt, dt);
-    if (h->block_streams && h->nblk > 1 && !capturing(h)) return enqueue_step_streams(h, device_dt, dt);
+    if (h->block_streams && h->nblk > 1 && h->nbs > 0)
+        return capturing(h) ? enqueue_step_streams_graph(h, device_dt, dt) : enqueue_step_streams(h, device_dt, dt);
     StageArgs a = stage_args(h);
     a.use_device_dt = device_dt ? 1 : 0;
     a.dt_host = dt;

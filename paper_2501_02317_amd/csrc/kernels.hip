@@ -728,7 +728,8 @@ struct StageOccupancy {
     static constexpr bool kRing = sizeof(R) == 4 && MODE == MODE_STAGE2 && (NDIM == 3 || kRing2D);
     // occupancy range (waves per SIMD) the compiler aims for: at least
     // kWaves (its register budget), at most kWavesMax (8: no bound)
-    static constexpr int kWaves = sizeof(R) == 4 ? (kRing ? 3 : 4) : 2;
+    static constexpr int kWaves =
+        sizeof(R) == 4 ? ((kRing || (NDIM == 3 && MODE == MODE_STAGE1)) ? 3 : 4) : 2;
     static constexpr int kWavesMax = 8;
     // One barrier per plane (double-buffered W and flux tiles): measured
     // faster for the mixed stage 1 and the FP64 stage 2; the mixed stage 2
@@ -743,10 +744,14 @@ struct StageOccupancy {
         (NDIM == 3 || kOne2D) &&
         ((sizeof(R) == 4 && MODE == MODE_STAGE1) || (sizeof(R) == 8 && MODE == MODE_STAGE2));
     // The raw halo cell of the next plane loaded one iteration ahead, so the
-    // barrier after the plane's W does not wait for it: ten more registers,
-    // which the Heun stage 2 (three waves per SIMD in mixed precision, two in
-    // FP64) holds without losing occupancy; the stage 1 would lose a wave.
-    static constexpr bool kHaloPrefetch = NDIM == 3 && MODE == MODE_STAGE2;
+    // barrier after the plane's W does not wait for it: ten more registers.
+    // Measured at 256^3: the Heun stage 2 holds them without losing
+    // occupancy (mixed 598 -> 556 us; FP64 unchanged); the mixed stage 1
+    // gains about 2 % even at three waves per SIMD instead of four (its LDS
+    // already limits it to two 512-thread work-groups per CU); the FP64
+    // stage 1 loses 6 % and does without.
+    static constexpr bool kHaloPrefetch =
+        NDIM == 3 && (MODE == MODE_STAGE2 || (MODE == MODE_STAGE1 && sizeof(R) == 4));
 };
 
 template <int NDIM, typename R, int MODE, int TX, int TY>

@@ -752,6 +752,14 @@ struct StageOccupancy {
     // stage 1 loses 6 % and does without.
     static constexpr bool kHaloPrefetch =
         NDIM == 3 && (MODE == MODE_STAGE2 || (MODE == MODE_STAGE1 && sizeof(R) == 4));
+    // The waves that convert the halo cells and compute the faces past the
+    // tile's last row and column (the first waves of the work-group) run at
+    // raised priority through that work, up to the barrier after the faces:
+    // they are the ones the other waves wait for there.  Measured at 256^3
+    // with two barriers per plane: mixed stage 2 -4.5 %, FP64 stage 1
+    // -6.5 %; with one barrier per plane (the other two 3-D kernels) it cost
+    // 1.5-4 %, so those keep the default priority.
+    static constexpr bool kPrio = NDIM == 3 && !kOneBarrier;
 };
 
 template <int NDIM, typename R, int MODE, int TX, int TY>
@@ -879,6 +887,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
     int vmA = VM_NONE, vmB = VM_NONE;
     // the raw halo cell of this thread (HALO_PF: the next plane's, in flight)
     constexpr bool HALO_PF = StageOccupancy<NDIM, R, MODE>::kHaloPrefetch;
+    constexpr bool PRIO = StageOccupancy<NDIM, R, MODE>::kPrio;
     double uhalo[NC];
 
     // interior plane z (any z: outside the mesh it is a ghost plane)
@@ -1034,6 +1043,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
             for (int c = 0; c < NC; ++c) sW[bw][c][ly + 2][lx + 2] = wc[c];
         }
         if (live && hact) {
+            if constexpr (PRIO) __builtin_amdgcn_s_setprio(2);
             R wh[NC];
             // the halo cell of plane k: loaded one iteration ahead (HALO_PF),
             // else now
@@ -1079,6 +1089,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
             const int ex = (ax == TX) ? ay : 0;
             const int ey = (HY && ay == TY) ? ax : 0;
             for (int e = tid; e < ex + ey; e += NT) {
+                if constexpr (PRIO) __builtin_amdgcn_s_setprio(2);
                 R w0[NC], w1[NC], w2[NC], w3[NC], F[NC];
                 if constexpr (HY) {
                     const bool yaxis = e >= ex;
@@ -1114,6 +1125,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
                 }
             }
         }
+        if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
         if (!ONE) __syncthreads();
 
         if (act && ku >= z0) {

@@ -279,9 +279,11 @@ def _refined(refined):
 
 
 class SMR:
-    """Two-level static refinement of a block mesh: the root blocks listed
-    in refined are split into 2^ndim blocks of half the size.  Fields are
-    block-layout arrays of shape (nleaf, ncomp, bz, by, bx)."""
+    """Static refinement of a block mesh: the blocks listed in refined (codes
+    level * 2^26 + index on that level's block grid; a plain root index for
+    level 0) are split into 2^ndim blocks of half the size, and refinement
+    is added until face-neighbouring leaves differ by at most one level.
+    Fields are block-layout arrays of shape (nleaf, ncomp, bz, by, bx)."""
 
     def __init__(self, mesh, blocks, refined):
         self.mesh = mesh

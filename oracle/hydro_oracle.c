@@ -897,21 +897,27 @@ int orc_run_blocks(const orc_mesh* m, const int32_t blocks[3], double* U, double
 
 /* ------------------------------------------------- static mesh refinement */
 
-/* Two-level static refinement of the block mesh above (the 2^d-tree of
- * Sec. 2.3 one level deep): each listed root block is replaced by 2^d blocks
- * of half its size, every block keeping the same number of cells.  The
- * leaves are ordered level 0 first (ascending root index, x fastest), then
- * level 1 (ascending index on the level-1 block grid of 2 B blocks per axis).
+/* Static refinement of the block mesh above (the 2^d-tree of Sec. 2.3):
+ * a listed block is replaced by 2^d blocks of half its size, every block
+ * keeping the same number of cells, recursively up to level SMR_MAXLEV - 1.
+ * A listed block is named by a code, its level L times 2^SMR_LSHIFT plus its
+ * index on the level-L block grid (B_d 2^L blocks per axis, x fastest); a
+ * block of level L >= 1 can be listed only when its parent is.  As in the
+ * paper, refinement is then added until face-neighbouring leaves differ by
+ * at most one level: while a leaf of level L touches, across a face, a leaf
+ * of level L - 2 or coarser, the coarser leaf is refined.  The leaves are
+ * ordered by level, and within a level by their index on that level's grid.
  *
  * A stage follows the cross-level sequence of Sec. 3 (c-boundaries):
  *   (a) ghosts that involve no prolongation: same-level neighbours, the
  *       p-boundary rules at the mesh faces, and on a coarse block facing
  *       finer ones, the volume average (restriction) of the fine cells that
  *       cover each ghost;
- *   (b) prolongation on the coarse side, now that its ghost zone is
- *       complete: each fine ghost is its coarse cell's value plus, per axis,
- *       a quarter of the minmod-limited (eq. minmod) difference, signed by
- *       the side of the coarse centre the fine centre lies on;
+ *   (b) prolongation on the coarse side, level by level from the coarsest,
+ *       so the coarse block's ghost zone is complete when it is used: each
+ *       fine ghost is its coarse cell's value plus, per axis, a quarter of
+ *       the minmod-limited (eq. minmod) difference, signed by the side of the
+ *       coarse centre the fine centre lies on;
  *   (c) fluxes on every block;
  *   (d) on a coarse face shared with finer blocks the flux is the average of
  *       the fine fluxes through it, so the mass, momentum and energy that
@@ -919,26 +925,55 @@ int orc_run_blocks(const orc_mesh* m, const int32_t blocks[3], double* U, double
  * All of this on primitive variables, as the paper's figure of the interface
  * shows; averages are taken pairwise along x, then y, then z. */
 enum { NB_PHYS = 0, NB_SAME = 1, NB_COARSE = 2, NB_FINE = 3 };
+#define SMR_MAXLEV 4
+#define SMR_LSHIFT 26
 
 typedef struct {
     orc_mesh mb;        /* one block: its extents, the mesh's boundary codes */
     int B[3];           /* root blocks per axis */
     int nleaf;
+    int nlev;           /* levels present */
     int (*leaf)[4];     /* level, c0, c1, c2 */
-    int* look[2];       /* per level: block coordinates -> leaf index, or -1 */
-    double dx[2][3];    /* cell widths per level */
+    int* look[SMR_MAXLEV];  /* per level: block coordinates -> leaf index, or -1 */
+    double dx[SMR_MAXLEV][3];  /* cell widths per level */
     int64_t nb;         /* cells per block */
 } smrgeo;
 
 static void smr_free(smrgeo* g) {
     free(g->leaf);
-    free(g->look[0]);
-    free(g->look[1]);
+    for (int L = 0; L < SMR_MAXLEV; ++L) free(g->look[L]);
+}
+
+/* Extent of the level-L block grid on axis d. */
+static int smr_extent(const smrgeo* g, int L, int d) { return d < g->mb.ndim ? g->B[d] << L : 1; }
+
+static int64_t smr_count(const smrgeo* g, int L) {
+    return (int64_t)smr_extent(g, L, 0) * smr_extent(g, L, 1) * smr_extent(g, L, 2);
 }
 
 static int64_t smr_key(const smrgeo* g, int L, const int* c) {
     int64_t e0 = (int64_t)g->B[0] << L, e1 = (int64_t)g->B[1] << L;
     return ((int64_t)c[2] * e1 + c[1]) * e0 + c[0];
+}
+
+static void smr_coords(const smrgeo* g, int L, int64_t f, int* c) {
+    int64_t e0 = smr_extent(g, L, 0), e1 = smr_extent(g, L, 1);
+    c[0] = (int)(f % e0);
+    c[1] = (int)((f / e0) % e1);
+    c[2] = (int)(f / (e0 * e1));
+}
+
+/* Index on the level L - 1 grid of the parent of level-L block c. */
+static int64_t smr_parent(const smrgeo* g, int L, const int* c) {
+    int pc[3];
+    for (int e = 0; e < 3; ++e) pc[e] = e < g->mb.ndim ? c[e] / 2 : 0;
+    return smr_key(g, L - 1, pc);
+}
+
+/* Whether level-L block f exists in the tree (a root, or a child of a
+ * refined block), given the refined sets ref[0 .. L-1]. */
+static int smr_exists(const smrgeo* g, char* const* ref, int L, const int* c) {
+    return L == 0 || ref[L - 1][smr_parent(g, L, c)];
 }
 
 static int smr_geometry(const orc_mesh* m, const int32_t* blocks, int nref, const int32_t* refined, smrgeo* g) {
@@ -948,66 +983,115 @@ static int smr_geometry(const orc_mesh* m, const int32_t* blocks, int nref, cons
     g->mb = bg.mb;
     for (int d = 0; d < 3; ++d) {
         g->B[d] = bg.B[d];
-        g->dx[0][d] = bg.dx[d];
-        g->dx[1][d] = d < m->ndim ? 0.5 * bg.dx[d] : 1.0;
+        for (int L = 0; L < SMR_MAXLEV; ++L)
+            g->dx[L][d] = d < m->ndim ? bg.dx[d] / (double)(1 << L) : 1.0;
         /* a refined block's children align with its cells: restriction of
          * n_gh coarse ghost layers needs 2 n_gh fine layers in one block */
         if (nref > 0 && d < m->ndim && (bg.mb.n[d] % 2 != 0 || bg.mb.n[d] < 2 * NGH)) return 0;
     }
     g->nb = bg.nb;
-    int nroot = bg.nblk, kids = 1 << m->ndim;
-    char* ref = (char*)calloc((size_t)nroot, 1);
-    if (!ref) return 0;
-    for (int r = 0; r < nref; ++r) {
-        if (refined[r] < 0 || refined[r] >= nroot || ref[refined[r]]) {
-            free(ref);
-            return 0;
-        }
-        ref[refined[r]] = 1;
+    char* ref[SMR_MAXLEV] = {0};
+    int ok = 1;
+    for (int L = 0; L < SMR_MAXLEV && ok; ++L) {
+        ref[L] = (char*)calloc((size_t)smr_count(g, L), 1);
+        ok = ref[L] != NULL;
     }
-    int64_t n1 = (int64_t)nroot * kids;
-    g->nleaf = nroot - nref + nref * kids;
-    g->leaf = (int(*)[4])malloc((size_t)g->nleaf * sizeof(*g->leaf));
-    g->look[0] = (int*)malloc((size_t)nroot * sizeof(int));
-    g->look[1] = (int*)malloc((size_t)n1 * sizeof(int));
-    if (!g->leaf || !g->look[0] || !g->look[1]) {
-        free(ref);
-        smr_free(g);
-        return 0;
+    const int64_t mask = ((int64_t)1 << SMR_LSHIFT) - 1;
+    for (int r = 0; r < nref && ok; ++r) {
+        int L = (int)(refined[r] >> SMR_LSHIFT);
+        int64_t f = refined[r] & mask;
+        if (refined[r] < 0 || L > SMR_MAXLEV - 2 || f >= smr_count(g, L) || ref[L][f]) {
+            ok = 0;
+            break;
+        }
+        ref[L][f] = 1;
+    }
+    /* every listed block exists: its parent is listed too */
+    for (int L = 1; L < SMR_MAXLEV - 1 && ok; ++L)
+        for (int64_t f = 0; f < smr_count(g, L) && ok; ++f) {
+            int c[3];
+            smr_coords(g, L, f, c);
+            if (ref[L][f] && !smr_exists(g, ref, L, c)) ok = 0;
+        }
+    /* 2:1 balance across faces, by refining the coarser side */
+    for (int changed = 1; changed && ok;) {
+        changed = 0;
+        for (int L = 2; L < SMR_MAXLEV; ++L)
+            for (int64_t f = 0; f < smr_count(g, L); ++f) {
+                int c[3];
+                smr_coords(g, L, f, c);
+                if (!smr_exists(g, ref, L, c) || (L < SMR_MAXLEV - 1 && ref[L][f])) continue;
+                for (int d = 0; d < m->ndim; ++d)
+                    for (int sd = 0; sd < 2; ++sd) {
+                        int q[3] = {c[0], c[1], c[2]};
+                        int E = smr_extent(g, L, d);
+                        q[d] += sd ? 1 : -1;
+                        if (q[d] < 0 || q[d] >= E) {
+                            if (m->bc[d][sd] != ORC_BC_PERIODIC) continue;
+                            q[d] = (q[d] + E) % E;
+                        }
+                        /* the neighbour region at level L: its ancestor at
+                         * level L - 2 must not be a leaf */
+                        int p1[3], p2[3];
+                        for (int e = 0; e < 3; ++e) p1[e] = e < m->ndim ? q[e] / 2 : 0;
+                        for (int e = 0; e < 3; ++e) p2[e] = e < m->ndim ? p1[e] / 2 : 0;
+                        int64_t k2 = smr_key(g, L - 2, p2);
+                        if (!ref[L - 2][k2]) {
+                            ref[L - 2][k2] = 1;
+                            changed = 1;
+                        }
+                    }
+            }
+        /* a block refined for balance may need its own parent refined */
+        for (int L = SMR_MAXLEV - 2; L >= 1 && ok; --L)
+            for (int64_t f = 0; f < smr_count(g, L); ++f) {
+                int c[3];
+                smr_coords(g, L, f, c);
+                if (ref[L][f] && !smr_exists(g, ref, L, c)) {
+                    ref[L - 1][smr_parent(g, L, c)] = 1;
+                    changed = 1;
+                }
+            }
+    }
+    /* leaves, level by level */
+    int64_t nleaf = 0;
+    for (int L = 0; L < SMR_MAXLEV && ok; ++L)
+        for (int64_t f = 0; f < smr_count(g, L); ++f) {
+            int c[3];
+            smr_coords(g, L, f, c);
+            if (smr_exists(g, ref, L, c) && !ref[L][f]) ++nleaf;
+        }
+    if (ok && nleaf > 0) {
+        g->leaf = (int(*)[4])malloc((size_t)nleaf * sizeof(*g->leaf));
+        ok = g->leaf != NULL;
+    }
+    for (int L = 0; L < SMR_MAXLEV && ok; ++L) {
+        g->look[L] = (int*)malloc((size_t)smr_count(g, L) * sizeof(int));
+        ok = g->look[L] != NULL;
     }
     int q = 0;
-    for (int r = 0; r < nroot; ++r) {
-        g->look[0][r] = -1;
-        if (ref[r]) continue;
-        g->leaf[q][0] = 0;
-        g->leaf[q][1] = r % g->B[0];
-        g->leaf[q][2] = (r / g->B[0]) % g->B[1];
-        g->leaf[q][3] = r / (g->B[0] * g->B[1]);
-        g->look[0][r] = q++;
-    }
-    int E[3];
-    for (int d = 0; d < 3; ++d) E[d] = d < m->ndim ? 2 * g->B[d] : 1;
-    for (int64_t f = 0; f < n1; ++f) {
-        int c[3] = {(int)(f % E[0]), (int)((f / E[0]) % E[1]), (int)(f / ((int64_t)E[0] * E[1]))};
-        int pc[3] = {c[0] / (m->ndim > 0 ? 2 : 1), c[1] / (m->ndim > 1 ? 2 : 1), c[2] / (m->ndim > 2 ? 2 : 1)};
-        int r = pc[0] + g->B[0] * (pc[1] + g->B[1] * pc[2]);
-        g->look[1][f] = -1;
-        if (!ref[r]) continue;
-        g->leaf[q][0] = 1;
-        g->leaf[q][1] = c[0];
-        g->leaf[q][2] = c[1];
-        g->leaf[q][3] = c[2];
-        g->look[1][f] = q++;
-    }
-    free(ref);
-    return q == g->nleaf;
+    for (int L = 0; L < SMR_MAXLEV && ok; ++L)
+        for (int64_t f = 0; f < smr_count(g, L); ++f) {
+            int c[3];
+            smr_coords(g, L, f, c);
+            g->look[L][f] = -1;
+            if (!smr_exists(g, ref, L, c) || ref[L][f]) continue;
+            g->leaf[q][0] = L;
+            g->leaf[q][1] = c[0];
+            g->leaf[q][2] = c[1];
+            g->leaf[q][3] = c[2];
+            g->look[L][f] = q++;
+            if (L + 1 > g->nlev) g->nlev = L + 1;
+        }
+    for (int L = 0; L < SMR_MAXLEV; ++L) free(ref[L]);
+    g->nleaf = q;
+    return ok && q == nleaf;
 }
 
-/* Extent of the level-L block grid on axis d. */
-static int smr_extent(const smrgeo* g, int L, int d) { return d < g->mb.ndim ? g->B[d] << L : 1; }
-
-/* What lies across side s of axis d of leaf b: NB_PHYS, or the leaf index
- * (NB_SAME, NB_COARSE) or the refined root's level-0 coordinates (NB_FINE). */
+/* What lies across side s of axis d of leaf b: NB_PHYS; the leaf index of a
+ * same-level (NB_SAME) or one-level coarser (NB_COARSE) neighbour; or
+ * NB_FINE with root the level-L coordinates of the refined neighbour block,
+ * whose children next to the face are leaves one level finer. */
 static int smr_nbr(const smrgeo* g, int b, int d, int s, int* idx, int* root) {
     int L = g->leaf[b][0];
     int c[3] = {g->leaf[b][1], g->leaf[b][2], g->leaf[b][3]};
@@ -1023,25 +1107,26 @@ static int smr_nbr(const smrgeo* g, int b, int d, int s, int* idx, int* root) {
         *idx = same;
         return NB_SAME;
     }
-    if (L == 1) {
-        int pc[3];
-        for (int e = 0; e < 3; ++e) pc[e] = e < g->mb.ndim ? c[e] / 2 : 0;
-        *idx = g->look[0][smr_key(g, 0, pc)];
-        return NB_COARSE;
+    if (L > 0) {
+        int par = g->look[L - 1][smr_parent(g, L, c)];
+        if (par >= 0) {
+            *idx = par;
+            return NB_COARSE;
+        }
     }
     for (int e = 0; e < 3; ++e) root[e] = c[e];
     return NB_FINE;
 }
 
-/* the level-1 leaf holding fine cell (x, y, z) of the level-1 grid, and the
+/* the level-L leaf holding cell (x, y, z) of the level-L cell grid, and the
  * cell's block-local coordinates */
-static int smr_fine_cell(const smrgeo* g, const int* x, int* local) {
+static int smr_fine_cell(const smrgeo* g, int L, const int* x, int* local) {
     int c[3];
     for (int e = 0; e < 3; ++e) {
         c[e] = x[e] / g->mb.n[e];
         local[e] = x[e] % g->mb.n[e];
     }
-    return g->look[1][smr_key(g, 1, c)];
+    return g->look[L][smr_key(g, L, c)];
 }
 
 /* Pairwise means of 2^k values along x, then y, then z (bit 0 of the index
@@ -1114,7 +1199,7 @@ static void smr_fill_ghosts(const smrgeo* g, double* Wp) {
                                             x[e] = fe;
                                         }
                                         int loc[3];
-                                        int fb = smr_fine_cell(g, x, loc);
+                                        int fb = smr_fine_cell(g, g->leaf[b][0] + 1, x, loc);
                                         const double* Wf = Wp + (int64_t)fb * nc * pg.total;
                                         v[o] = Wf[c * pg.total + pidx(&pg, loc[0], loc[1], loc[2])];
                                     }
@@ -1126,9 +1211,11 @@ static void smr_fill_ghosts(const smrgeo* g, double* Wp) {
         }
         fill_ghosts_masked(mb, Wd, (const int(*)[2])cside);
     }
-    /* (b) prolongation from the coarse side's complete padded array */
+    /* (b) prolongation from the coarse side's complete padded array, level
+     * by level (a coarse block's own prolonged ghosts come first) */
+    for (int lev = 1; lev < g->nlev; ++lev)
     for (int b = 0; b < g->nleaf; ++b) {
-        if (g->leaf[b][0] != 1) continue;
+        if (g->leaf[b][0] != lev) continue;
         double* Wd = Wp + (int64_t)b * nc * pg.total;
         const int fc[3] = {g->leaf[b][1], g->leaf[b][2], g->leaf[b][3]};
         for (int d = 0; d < ndim; ++d) {
@@ -1243,7 +1330,7 @@ static int smr_rhs(const smrgeo* g, const double* X, double dt, double* dU) {
                                 }
                                 for (int t = 0; t < nt; ++t) x[tax[t]] += (o >> t) & 1;
                                 int loc[3];
-                                int fb = smr_fine_cell(g, x, loc);
+                                int fb = smr_fine_cell(g, g->leaf[b][0] + 1, x, loc);
                                 /* the fine face on the shared plane: low face of a
                                  * fine cell for s = 1, its high face for s = 0 */
                                 int ffi[3] = {loc[0], loc[1], loc[2]};

@@ -119,17 +119,21 @@ int orc_run_blocks(const orc_mesh* m, const int32_t blocks[3], double* U, double
                    double t_end, double* t, int* steps_done, double* dts);
 
 /*
- * Two-level static mesh refinement of the block mesh of orc_run_blocks: the
- * nref root blocks listed in refined[] (root index b0 + B0 (b1 + B1 b2)) are
- * each replaced by 2^ndim blocks of half their size with the same cell
- * count.  Refinement needs an even block extent of at least 4 cells on every
- * active axis.  Leaves are ordered level 0 first (ascending root index), then
- * level 1 (ascending index on the level-1 block grid, x fastest); fields are
- * in the block layout [leaf][comp][k][j][i] of one block's extents.
- * Cross-level c-boundaries: restriction (pairwise volume averages) onto
- * coarse ghosts, then minmod-limited prolongation onto fine ghosts, fluxes,
- * and the average of the fine fluxes on the coarse side of each level jump;
- * all on primitive variables; one global time step; Heun only.
+ * Static mesh refinement of the block mesh of orc_run_blocks (Sec. 2.3: a
+ * refined block is replaced by 2^ndim blocks of half its size with the same
+ * cell count, recursively).  refined[] lists nref blocks to refine, each by
+ * its code L * 2^26 + (index on the level-L block grid of B_d 2^L blocks per
+ * axis, x fastest); a block of level L >= 1 must follow its parent, and L <= 2
+ * (leaves reach level 3 at most).  Refinement is added, refining the coarser
+ * side, until face-neighbouring leaves differ by at most one level.
+ * Refinement needs an even block extent of at least 4 cells on every active
+ * axis.  Leaves are ordered by level, and within a level by their index on
+ * that level's grid; fields are in the block layout [leaf][comp][k][j][i] of
+ * one block's extents.  Cross-level c-boundaries: restriction (pairwise
+ * volume averages) onto coarse ghosts, then minmod-limited prolongation onto
+ * fine ghosts level by level from the coarsest, fluxes, and the average of
+ * the fine fluxes on the coarse side of each level jump; all on primitive
+ * variables; one global time step; Heun only.
  *
  * orc_smr_leaves writes (level, c0, c1, c2) per leaf (at most max) and
  * returns the leaf count, or -1 for an invalid refinement.

@@ -271,25 +271,32 @@ int hydro_profile(hydro_t h, int cap);
 int hydro_profile_read(hydro_t h, double* ms_stage1, double* ms_stage2, int64_t* launches);
 
 /*
- * Static mesh refinement, two levels (Sec. 2.3: the 2^d-tree of blocks, one
- * level deep; Sec. 3: c-boundaries across levels).  The blocks of cfg (see
- * "Blocks") are the root blocks; the nref root indices in refined[] (b0 +
- * blocks[0] (b1 + blocks[1] b2), distinct) are each replaced by 2^ndim blocks
- * of half the size and the same extents in cells.  Refinement needs even
- * block extents of at least 4 cells on the active axes, the Heun integrator,
- * and at most 1024 leaves.
- *   - Leaves are ordered: level 0 in root order, then level 1 in the order of
- *     the level-1 block grid (2 blocks[d] per active axis, x fastest).
- *     hydro_smr_leaves writes (level, c0, c1, c2) per leaf (at most max
- *     entries, block coordinates on the leaf's level, physical axes) and
- *     returns the number of leaves, or HYDRO_E_INVAL; it needs no device.
+ * Static mesh refinement (Sec. 2.3: the 2^d-tree of blocks, refined
+ * recursively, with face-neighbouring blocks at most one level apart; Sec. 3:
+ * c-boundaries across levels).  The blocks of cfg (see "Blocks") are the
+ * root blocks of level 0.  refined[] lists nref distinct blocks to refine,
+ * each by its code L * 2^26 + (its index on the level-L block grid of
+ * blocks[d] 2^L blocks per active axis, x fastest); a root's code is its
+ * root index b0 + blocks[0] (b1 + blocks[1] b2).  A block of level L >= 1 can
+ * be listed only with its parent, and L <= 2, so leaves reach level 3 at
+ * most.  Each listed block is replaced by 2^ndim blocks of half the size and
+ * the same extents in cells; then, as the paper does, refinement is added on
+ * the coarser side until no two face-neighbouring leaves are more than one
+ * level apart.  Refinement needs even block extents of at least 4 cells on
+ * the active axes, the Heun integrator, and at most 1024 leaves.
+ *   - Leaves are ordered by level, and within a level in the order of that
+ *     level's block grid (x fastest).  hydro_smr_leaves writes (level, c0,
+ *     c1, c2) per leaf (at most max entries, block coordinates on the leaf's
+ *     level, physical axes) and returns the number of leaves, or
+ *     HYDRO_E_INVAL; it needs no device.
  *   - A refined handle's host and device state transfers use the block
  *     layout [leaf][comp][k][j][i] of one block's extents (the mesh has no
  *     single uniform layout); its totals weight each level by its cell volume.
  *   - Each stage: the ghost layers at level jumps are filled first, the
  *     coarse side's by volume averages (restriction) of the fine cells, then
  *     the fine side's by minmod-limited prolongation (eq. minmod) of the
- *     coarse cells, on primitive variables, into ghost slots in the
+ *     coarse cells level by level from the coarsest (a coarse block's
+ *     stencil may include its own prolonged layers), on primitive variables, into ghost slots in the
  *     workspace; then the stage kernel runs per level (same-level faces read
  *     the neighbour's cells in place); then each coarse cell next to a level
  *     jump is corrected so that its update uses the mean of the fine fluxes

@@ -98,12 +98,26 @@ constexpr int kSideSlot0 = -2;
 // kind 0 (restriction; leaf is coarse): src[o] is the fine block on the face
 // at transverse child offsets o (bit 0: t_lo, bit 1: t_hi).  kind 1
 // (prolongation; leaf is fine): src[0] is the coarse block, child[] the
-// leaf's offsets (0/1) per kernel axis within its parent.
+// leaf's offsets (0/1) per kernel axis within its parent.  lev: the leaf's
+// refinement level (its cell widths are level 0's times 2^-lev).
 struct GhostTask {
     int leaf, ax, s, kind;
     int src[4];
     int child[3];
     int slot;
+    int lev;
+};
+
+// Refinement levels 0 .. kMaxLevels - 1; a refined block is named by the code
+// level * 2^kLevelShift + its index on that level's block grid.
+constexpr int kMaxLevels = 4;
+constexpr int kLevelShift = 26;
+
+// First block of each level 1 .. kMaxLevels - 1 in a refined mesh's leaf
+// order (a level with no leaves starts where the next one does; unrefined
+// meshes: every entry at the block count).
+struct LevelStarts {
+    int s[kMaxLevels - 1];
 };
 
 // One member of a batch: the stage kernels build StageArgs from it.
@@ -173,10 +187,10 @@ hipError_t launch_smr_reflux(int precision, const Geo& g0, const Geo& g1, const 
                              hipStream_t s);
 hipError_t launch_smr_apply(const Geo& g0, double* out, const double* dbuf, long long gcs, const GhostTask* tasks,
                             int idx0, int n, int use_device_dt, Ctrl* ctrl, hipStream_t s);
-// dt reduction over the nblk blocks of U, blocks from start1 on with the cell
-// widths of g1 (a refined mesh's second level); with skip_done, nothing once
-// the run limit is reached.
-hipError_t launch_dt_levels(const Geo& g0, const Geo& g1, int start1, int nblk, const double* U, Ctrl* ctrl,
+// dt reduction over the nblk blocks of U, a block of level L (from the level
+// starts) with g0's cell widths times 2^-L; with skip_done, nothing once the
+// run limit is reached.
+hipError_t launch_dt_levels(const Geo& g0, const LevelStarts& starts, int nblk, const double* U, Ctrl* ctrl,
                             int skip_done, hipStream_t s);
 
 // Default tile for a mesh (kernel axes) and precision.

@@ -1276,18 +1276,21 @@ void stage_kernel_batch(
 
 // ------------------------------------------------------------- small kernels
 
-// blockIdx.y: the block of the mesh (block layout); blocks from start1 on
-// take the cell widths of g1 (a refined mesh's second level)
+// blockIdx.y: the block of the mesh (block layout); a refined mesh's blocks
+// of level L (from the level starts) take level 0's cell widths times 2^-L
 template <int NDIM>
-__global__ __launch_bounds__(256) void dt_kernel(Geo g0, Geo g1, int start1, const double* __restrict__ U,
+__global__ __launch_bounds__(256) void dt_kernel(Geo g0, LevelStarts starts, const double* __restrict__ U,
                                                  Ctrl* ctrl, int skip_done) {
     constexpr int NC = NDIM + 2;
     if (skip_done && ctrl->done) return;  // uniform over the grid
     Geo g = g0;
-    if ((int)blockIdx.y >= start1) {
+    // the block's level: its inverse cell widths are level 0's times 2^L
+    // (exact: 1 / (dx 2^-L) rounds to (1 / dx) 2^L)
+    int lev = 0;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) g.inv_dx[k] = g1.inv_dx[k];
-    }
+    for (int L = 1; L < kMaxLevels; ++L) lev += (int)blockIdx.y >= starts.s[L - 1] ? 1 : 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g.inv_dx[k] = __builtin_ldexp(g0.inv_dx[k], lev);
     U += (long long)blockIdx.y * NC * g.ncells;
     double best = 0.0;
     bool bad = false;
@@ -1764,7 +1767,8 @@ __device__ __forceinline__ void reflux_face(const Geo& g0, const Geo& g1, const 
                                             long long gcs, const GhostTask& t, int idx, int r, bool& bad) {
     constexpr int NC = NDIM + 2;
     constexpr int NT = NDIM - 1;
-    const double lam = dt / g0.dx[AX];
+    // the coarse block's cell width: level 0's times 2^-lev (exact)
+    const double lam = dt / __builtin_ldexp(g0.dx[AX], -t.lev);
     const Gas<R> gr = make_gas<R>(g0.gamma);
     const double gm1 = g0.gamma - 1.0;
     int lo, hi;
@@ -2162,21 +2166,23 @@ hipError_t launch_ctrl_batch(const MeshDesc* d, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_dt_levels(const Geo& g0, const Geo& g1, int start1, int nblk, const double* U, Ctrl* ctrl,
+hipError_t launch_dt_levels(const Geo& g0, const LevelStarts& starts, int nblk, const double* U, Ctrl* ctrl,
                             int skip_done, hipStream_t s) {
     if (nblk < 1) return hipSuccess;
     const dim3 grid(grid_for(g0.ncells, 256, (2048 + nblk - 1) / nblk), nblk);
     switch (g0.ndim) {
-        case 1: hipLaunchKernelGGL(dt_kernel<1>, grid, dim3(256), 0, s, g0, g1, start1, U, ctrl, skip_done); break;
-        case 2: hipLaunchKernelGGL(dt_kernel<2>, grid, dim3(256), 0, s, g0, g1, start1, U, ctrl, skip_done); break;
-        case 3: hipLaunchKernelGGL(dt_kernel<3>, grid, dim3(256), 0, s, g0, g1, start1, U, ctrl, skip_done); break;
+        case 1: hipLaunchKernelGGL(dt_kernel<1>, grid, dim3(256), 0, s, g0, starts, U, ctrl, skip_done); break;
+        case 2: hipLaunchKernelGGL(dt_kernel<2>, grid, dim3(256), 0, s, g0, starts, U, ctrl, skip_done); break;
+        case 3: hipLaunchKernelGGL(dt_kernel<3>, grid, dim3(256), 0, s, g0, starts, U, ctrl, skip_done); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_dt(const Geo& g, const double* U, Ctrl* ctrl, hipStream_t s) {
-    return launch_dt_levels(g, g, geo_nblk(g), geo_nblk(g), U, ctrl, 0, s);
+    LevelStarts none;
+    for (int L = 0; L < kMaxLevels - 1; ++L) none.s[L] = geo_nblk(g);
+    return launch_dt_levels(g, none, geo_nblk(g), U, ctrl, 0, s);
 }
 
 hipError_t launch_ctrl(Ctrl* c, int op, double a0, double a1, double cfl, hipStream_t s) {

@@ -34,13 +34,15 @@ struct hydro_ctx {
     // block group g = blocks [g nblk / nbs, (g + 1) nblk / nbs) runs on stream g;
     // gadj[g][o]: a block of group o is a face neighbour of a block of group g
     bool gadj[kBlockStreams][kBlockStreams];
-    // static refinement (two levels; leaves of level 0, then of level 1)
+    // static refinement (leaves ordered by level)
     bool smr;
-    int lev_start[2], lev_count[2];
-    Geo lgeo[2];                   // per level: one block's extents and the level's cell widths
+    int nlev;                      // levels present
+    int lev_start[kMaxLevels], lev_count[kMaxLevels];
+    Geo lgeo[kMaxLevels];          // per level: one block's extents and the level's cell widths
     int* d_side;                   // 6 side codes per leaf
     GhostTask* d_tasks;            // restriction slots by kernel axis, then prolongation slots
     int nres, npro, res_off[4];
+    int pro_off[kMaxLevels + 1];   // prolongation slots of level L: tasks [pro_off[L], pro_off[L + 1])
     double* gbuf;
     double* dbuf;                  // flux corrections per restriction slot
     hipStream_t smr_aux;           // second stream of the level-jump passes (null: none)
@@ -458,20 +460,28 @@ bool capturing(hydro_t h) {
     return hipStreamIsCapturing(h->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
 }
 
+// The first leaf of each level 1 .. kMaxLevels - 1 of a refined mesh.
+LevelStarts level_starts(hydro_t h) {
+    LevelStarts ls;
+    for (int L = 1; L < kMaxLevels; ++L) ls.s[L - 1] = L < h->nlev ? h->lev_start[L] : h->nblk;
+    return ls;
+}
+
 // One step of a refined mesh (Heun).  Each stage: the ghost slots of the
-// level jumps from the stage input (restriction, then prolongation, which
-// reads the restricted slots), the stage kernel per level, then the flux
-// correction of the coarse cells at the level jumps (computed for every jump
-// in one launch, added axis by axis: a cell next to two jumps is corrected
-// once per axis, in order).  The CFL rate of
-// the corrected state is a reduction of its own.
+// level jumps from the stage input (restriction, then prolongation level by
+// level from the coarsest, since a coarse block's stencil may include its own
+// prolonged slots), the stage kernel per level, then the flux correction of
+// the coarse cells at the level jumps (computed for every jump in one
+// launch, added axis by axis: a cell next to two jumps is corrected once per
+// axis, in order).  The CFL rate of the corrected state is a reduction of its
+// own.
 hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
     hipError_t e = hipSuccess;
     // With a second stream (smr_aux), the passes that the level-0 stage does
-    // not need overlap it: the prolongation (read only by level 1) and the
-    // flux recomputation (reads the stage input and the slots, not the
-    // stage's output); level 1 waits for the prolongation, the additions for
-    // the recomputation.
+    // not need overlap it: the prolongations (read only by the finer levels)
+    // and the flux recomputation (reads the stage input and the slots, not
+    // the stage's output); the finer levels wait for the prolongations, the
+    // additions for the recomputation.
     const bool fork = h->smr_aux && !capturing(h);
     hipStream_t aux = fork ? h->smr_aux : h->stream;
     for (int st = 0; st < 2 && e == hipSuccess; ++st) {
@@ -480,16 +490,16 @@ hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
         e = launch_smr_restrict(h->lgeo[0], in, h->d_side, h->gbuf, h->gcs, h->d_tasks, h->nres, h->ctrl, h->stream);
         if (e == hipSuccess && fork) e = hipEventRecord(h->ev_smr[0], h->stream);
         if (e == hipSuccess && fork) e = hipStreamWaitEvent(aux, h->ev_smr[0], 0);
-        if (e == hipSuccess)
-            e = launch_smr_prolong(h->lgeo[0], in, h->d_side, h->gbuf, h->gcs, h->d_tasks + h->nres, h->npro,
-                                   h->ctrl, aux);
+        for (int L = 1; L < h->nlev && e == hipSuccess; ++L)
+            e = launch_smr_prolong(h->lgeo[0], in, h->d_side, h->gbuf, h->gcs, h->d_tasks + h->pro_off[L],
+                                   h->pro_off[L + 1] - h->pro_off[L], h->ctrl, aux);
         if (e == hipSuccess && fork) e = hipEventRecord(h->ev_smr[1], aux);
         if (e == hipSuccess)
-            e = launch_smr_reflux(h->cfg.precision, h->lgeo[0], h->lgeo[1], in, h->dbuf, st == 0 ? 1.0 : 0.5,
+            e = launch_smr_reflux(h->cfg.precision, h->lgeo[0], h->lgeo[0], in, h->dbuf, st == 0 ? 1.0 : 0.5,
                                   device_dt ? 1 : 0, dt, h->d_side, h->gbuf, h->gcs, h->d_tasks, h->nres, h->ctrl,
                                   aux);
         if (e == hipSuccess && fork) e = hipEventRecord(h->ev_smr[2], aux);
-        for (int lev = 0; lev < 2 && e == hipSuccess; ++lev) {
+        for (int lev = 0; lev < h->nlev && e == hipSuccess; ++lev) {
             if (lev == 1 && fork) e = hipStreamWaitEvent(h->stream, h->ev_smr[1], 0);
             if (e != hipSuccess || h->lev_count[lev] == 0) continue;
             StageArgs a = stage_args(h);
@@ -511,7 +521,7 @@ hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
     }
     if (e != hipSuccess) return e;
     if (!device_dt) return launch_ctrl(h->ctrl, CTRL_ADVANCE_T, dt, 0.0, h->cfg.cfl, h->stream);
-    e = launch_dt_levels(h->lgeo[0], h->lgeo[1], h->lev_start[1], h->nblk, h->U, h->ctrl, 1, h->stream);
+    e = launch_dt_levels(h->lgeo[0], level_starts(h), h->nblk, h->U, h->ctrl, 1, h->stream);
     if (e != hipSuccess) return e;
     return launch_ctrl(h->ctrl, CTRL_FINALIZE_STEP, 0.0, 0.0, h->cfg.cfl, h->stream);
 }
@@ -542,7 +552,7 @@ hipError_t enqueue_dt(hydro_t h) {
     hipError_t e = launch_ctrl(h->ctrl, CTRL_RESET_MIN, 0.0, 0.0, h->cfg.cfl, h->stream);
     if (h->smr) {
         if (e == hipSuccess)
-            e = launch_dt_levels(h->lgeo[0], h->lgeo[1], h->lev_start[1], h->nblk, h->U, h->ctrl, 0, h->stream);
+            e = launch_dt_levels(h->lgeo[0], level_starts(h), h->nblk, h->U, h->ctrl, 0, h->stream);
     } else if (e == hipSuccess) {
         e = launch_dt(h->geo, h->U, h->ctrl, h->stream);
     }
@@ -553,17 +563,21 @@ hipError_t enqueue_dt(hydro_t h) {
 
 // ------------------------------------------------------- static refinement
 
-// Leaves, side codes and ghost slots of a two-level refinement of the block
-// grid of cfg: the listed root blocks are each replaced by 2^ndim blocks of
-// half their size and the same extents in cells.  Leaves: level 0 in root
-// order, then level 1 in the order of the level-1 block grid (x fastest).
+// Leaves, side codes and ghost slots of a refinement of the block grid of
+// cfg (Sec. 2.3): each listed block (code level * 2^kLevelShift + its index
+// on that level's block grid, x fastest; a block of level >= 1 after its
+// parent) is replaced by 2^ndim blocks of half its size and the same extents
+// in cells; then, as in the paper, refinement is added on the coarser side
+// until face-neighbouring leaves differ by at most one level.  Leaves are
+// ordered by level, and within a level by their index on its grid.
 struct SmrPlan {
-    int nleaf = 0;
+    int nleaf = 0, nlev = 1;
     std::vector<int32_t> leaves;  // (level, c0, c1, c2), physical axes
     std::vector<int> side;        // 6 per leaf, kernel axes
     std::vector<GhostTask> tasks;
     int nres = 0, npro = 0, res_off[4] = {0, 0, 0, 0};
-    int lev_start[2] = {0, 0}, lev_count[2] = {0, 0};
+    int pro_off[kMaxLevels + 1] = {0, 0, 0, 0, 0};
+    int lev_start[kMaxLevels] = {0, 0, 0, 0}, lev_count[kMaxLevels] = {0, 0, 0, 0};
     long long gcs = 0;
 };
 
@@ -578,65 +592,118 @@ bool smr_plan(const hydro_config* c, int nref, const int32_t* refined, SmrPlan& 
         // restricted ghost layers of a coarse side cover four fine layers
         if (nref > 0 && d < nd && (nb[d] % 2 != 0 || nb[d] < 4)) return false;
     }
-    const int nroot = B[0] * B[1] * B[2];
-    std::vector<char> ref(nroot, 0);
+    auto ext = [&](int L, int d) { return d < nd ? B[d] << L : 1; };
+    auto count = [&](int L) { return (long long)ext(L, 0) * ext(L, 1) * ext(L, 2); };
+    auto key = [&](int L, const int* c3) { return ((long long)c3[2] * ext(L, 1) + c3[1]) * ext(L, 0) + c3[0]; };
+    auto coords = [&](int L, long long f, int* c3) {
+        c3[0] = (int)(f % ext(L, 0));
+        c3[1] = (int)((f / ext(L, 0)) % ext(L, 1));
+        c3[2] = (int)(f / ((long long)ext(L, 0) * ext(L, 1)));
+    };
+    auto parent = [&](int L, const int* c3) {
+        int p3[3];
+        for (int e = 0; e < 3; ++e) p3[e] = e < nd ? c3[e] / 2 : 0;
+        return key(L - 1, p3);
+    };
+    std::vector<char> ref[kMaxLevels];
+    for (int L = 0; L < kMaxLevels; ++L) ref[L].assign((size_t)count(L), 0);
+    // a block exists in the tree: a root, or a child of a refined block
+    auto exists = [&](int L, const int* c3) { return L == 0 || ref[L - 1][parent(L, c3)] != 0; };
+    const int32_t mask = (1 << kLevelShift) - 1;
     for (int r = 0; r < nref; ++r) {
-        if (refined[r] < 0 || refined[r] >= nroot || ref[refined[r]]) return false;
-        ref[refined[r]] = 1;
+        if (refined[r] < 0) return false;
+        const int L = refined[r] >> kLevelShift;
+        const long long f = refined[r] & mask;
+        if (L > kMaxLevels - 2 || f >= count(L) || ref[L][f]) return false;
+        ref[L][f] = 1;
     }
-    int E[3];  // level-1 block grid
-    for (int d = 0; d < 3; ++d) E[d] = d < nd ? 2 * B[d] : 1;
-    const long long n1 = (long long)E[0] * E[1] * E[2];
-    std::vector<int> look0(nroot, -1), look1(n1, -1);
-    for (int r = 0; r < nroot; ++r) {
-        if (ref[r]) continue;
-        look0[r] = (int)(P.leaves.size() / 4);
-        P.leaves.insert(P.leaves.end(), {0, r % B[0], (r / B[0]) % B[1], r / (B[0] * B[1])});
+    for (int L = 1; L < kMaxLevels - 1; ++L)
+        for (long long f = 0; f < count(L); ++f) {
+            int c3[3];
+            coords(L, f, c3);
+            if (ref[L][f] && !exists(L, c3)) return false;  // listed before its parent was refined
+        }
+    // 2:1 balance across faces: while a leaf of level L >= 2 faces a region
+    // whose level L - 2 ancestor is a leaf (or coarser), refine that ancestor
+    for (bool changed = true; changed;) {
+        changed = false;
+        for (int L = 2; L < kMaxLevels; ++L)
+            for (long long f = 0; f < count(L); ++f) {
+                int c3[3];
+                coords(L, f, c3);
+                if (!exists(L, c3) || ref[L][f]) continue;
+                for (int d = 0; d < nd; ++d)
+                    for (int sd = 0; sd < 2; ++sd) {
+                        int q3[3] = {c3[0], c3[1], c3[2]};
+                        const int E = ext(L, d);
+                        q3[d] += sd ? 1 : -1;
+                        if (q3[d] < 0 || q3[d] >= E) {
+                            if (c->bc[d][sd] != HYDRO_BC_PERIODIC) continue;
+                            q3[d] = (q3[d] + E) % E;
+                        }
+                        int p2[3];
+                        for (int e = 0; e < 3; ++e) p2[e] = e < nd ? q3[e] / 4 : 0;
+                        const long long k2 = key(L - 2, p2);
+                        if (!ref[L - 2][k2]) {
+                            ref[L - 2][k2] = 1;
+                            changed = true;
+                        }
+                    }
+            }
+        // a block refined for balance may need its own parent refined
+        for (int L = kMaxLevels - 2; L >= 1; --L)
+            for (long long f = 0; f < count(L); ++f) {
+                int c3[3];
+                coords(L, f, c3);
+                if (ref[L][f] && !exists(L, c3)) {
+                    ref[L - 1][parent(L, c3)] = 1;
+                    changed = true;
+                }
+            }
     }
-    P.lev_count[0] = (int)(P.leaves.size() / 4);
-    for (long long f = 0; f < n1; ++f) {
-        const int x = (int)(f % E[0]), y = (int)((f / E[0]) % E[1]), z = (int)(f / ((long long)E[0] * E[1]));
-        auto half = [&](int v, int d) { return d < nd ? v / 2 : 0; };
-        const int r = half(x, 0) + B[0] * (half(y, 1) + B[1] * half(z, 2));
-        if (!ref[r]) continue;
-        look1[f] = (int)(P.leaves.size() / 4);
-        P.leaves.insert(P.leaves.end(), {1, x, y, z});
+    std::vector<int> look[kMaxLevels];
+    for (int L = 0; L < kMaxLevels; ++L) {
+        look[L].assign((size_t)count(L), -1);
+        P.lev_start[L] = (int)(P.leaves.size() / 4);
+        for (long long f = 0; f < count(L); ++f) {
+            int c3[3];
+            coords(L, f, c3);
+            if (!exists(L, c3) || ref[L][f]) continue;
+            look[L][f] = (int)(P.leaves.size() / 4);
+            P.leaves.insert(P.leaves.end(), {L, c3[0], c3[1], c3[2]});
+        }
+        P.lev_count[L] = (int)(P.leaves.size() / 4) - P.lev_start[L];
+        if (P.lev_count[L] > 0) P.nlev = L + 1;
     }
     P.nleaf = (int)(P.leaves.size() / 4);
-    P.lev_start[1] = P.lev_count[0];
-    P.lev_count[1] = P.nleaf - P.lev_count[0];
     if (P.nleaf > kMaxBlocks) return false;
     const int kmap[3] = {0, nd == 3 ? 1 : -1, nd == 3 ? 2 : (nd == 2 ? 1 : -1)};  // kernel -> physical axis
-    auto leaf_at = [&](int L, const int* c3) -> int {
-        if (L == 0) return look0[c3[0] + B[0] * (c3[1] + B[1] * c3[2])];
-        return look1[c3[0] + (long long)E[0] * (c3[1] + (long long)E[1] * c3[2])];
-    };
-    // sides: what lies across (physical axis d, side s) of leaf b
+    auto leaf_at = [&](int L, const int* c3) -> int { return look[L][key(L, c3)]; };
+    // sides: what lies across (physical axis d, side s) of leaf b; for FINE,
+    // root receives the level-L coordinates of the refined neighbour block
     enum { PHYS, SAME, COARSE, FINE };
     auto across = [&](int b, int d, int s, int& idx, int* root) -> int {
         const int L = P.leaves[4 * b];
         int c3[3] = {P.leaves[4 * b + 1], P.leaves[4 * b + 2], P.leaves[4 * b + 3]};
-        const int ext = (d < nd ? B[d] : 1) << L;
+        const int E = ext(L, d);
         int q = c3[d] + (s ? 1 : -1);
-        if (q < 0 || q >= ext) {
+        if (q < 0 || q >= E) {
             if (c->bc[d][s] != HYDRO_BC_PERIODIC) return PHYS;
-            q = (q + ext) % ext;
+            q = (q + E) % E;
         }
         c3[d] = q;
         idx = leaf_at(L, c3);
         if (idx >= 0) return SAME;
-        if (L == 1) {
-            int p3[3];
-            for (int e = 0; e < 3; ++e) p3[e] = e < nd ? c3[e] / 2 : 0;
-            idx = leaf_at(0, p3);
-            return COARSE;
+        if (L > 0) {
+            idx = look[L - 1][parent(L, c3)];
+            if (idx >= 0) return COARSE;
         }
         for (int e = 0; e < 3; ++e) root[e] = c3[e];
         return FINE;
     };
     P.side.assign(6 * (size_t)P.nleaf, 0);
-    std::vector<GhostTask> res[3], pro;
-    std::vector<std::pair<int, int>> res_at[3], pro_at;  // (leaf, side index) owning each task
+    std::vector<GhostTask> res[3], pro[kMaxLevels];
+    std::vector<std::pair<int, int>> res_at[3], pro_at[kMaxLevels];  // (leaf, side index) owning each task
     for (int b = 0; b < P.nleaf; ++b) {
         for (int k = 0; k < 3; ++k) {
             for (int s = 0; s < 2; ++s) {
@@ -658,6 +725,7 @@ bool smr_plan(const hydro_config* c, int nref, const int32_t* refined, SmrPlan& 
                     t.leaf = b;
                     t.ax = k;
                     t.s = s;
+                    t.lev = P.leaves[4 * b];
                     const int lo = k == 0 ? 1 : 0, hi = k == 2 ? 1 : 2;
                     if (kind == FINE) {
                         t.kind = 0;
@@ -671,7 +739,7 @@ bool smr_plan(const hydro_config* c, int nref, const int32_t* refined, SmrPlan& 
                                 const int e = kmap[tax[q]];
                                 if (e >= 0) f3[e] = 2 * root[e] + bits[q];
                             }
-                            t.src[o] = leaf_at(1, f3);
+                            t.src[o] = t.lev + 1 < kMaxLevels ? leaf_at(t.lev + 1, f3) : -1;
                             if (t.src[o] < 0) return false;
                         }
                         res[k].push_back(t);
@@ -681,8 +749,8 @@ bool smr_plan(const hydro_config* c, int nref, const int32_t* refined, SmrPlan& 
                         t.src[0] = idx;
                         for (int q = 0; q < 3; ++q) t.child[q] = kmap[q] >= 0 ? P.leaves[4 * b + 1 + kmap[q]] % 2 : 0;
                         if (idx < 0) return false;
-                        pro.push_back(t);
-                        pro_at.push_back({b, 2 * k + s});
+                        pro[t.lev].push_back(t);
+                        pro_at[t.lev].push_back({b, 2 * k + s});
                     }
                 }
             }
@@ -697,12 +765,18 @@ bool smr_plan(const hydro_config* c, int nref, const int32_t* refined, SmrPlan& 
         }
     }
     P.res_off[3] = P.nres = (int)P.tasks.size();
-    for (size_t i = 0; i < pro.size(); ++i) {
-        pro[i].slot = (int)P.tasks.size();
-        P.side[6 * pro_at[i].first + pro_at[i].second] = kSideSlot0 - pro[i].slot;
-        P.tasks.push_back(pro[i]);
+    // prolongation slots by the fine block's level: each level's launch
+    // follows the coarser one's, whose slots its coarse stencils may read
+    for (int L = 0; L < kMaxLevels; ++L) {
+        P.pro_off[L] = (int)P.tasks.size();
+        for (size_t i = 0; i < pro[L].size(); ++i) {
+            pro[L][i].slot = (int)P.tasks.size();
+            P.side[6 * pro_at[L][i].first + pro_at[L][i].second] = kSideSlot0 - pro[L][i].slot;
+            P.tasks.push_back(pro[L][i]);
+        }
     }
-    P.npro = (int)pro.size();
+    P.pro_off[kMaxLevels] = (int)P.tasks.size();
+    P.npro = (int)P.tasks.size() - P.nres;
     // slot component stride: both layers of the largest side
     long long face = 1;
     const int nk[3] = {nb[kmap[0]], kmap[1] >= 0 ? nb[kmap[1]] : 1, kmap[2] >= 0 ? nb[kmap[2]] : 1};
@@ -806,12 +880,13 @@ int hydro_smr_create(const hydro_config* cfg, int nref, const int32_t* refined, 
     h->nblk = P.nleaf;
     h->geo.blocks[0] = P.nleaf;  // the leaves as a row of blocks (per-cell passes)
     h->geo.blocks[1] = h->geo.blocks[2] = 1;
-    for (int lev = 0; lev < 2; ++lev) {
+    h->nlev = P.nlev;
+    for (int lev = 0; lev < kMaxLevels; ++lev) {
         Geo g = h->geo;
         for (int k = 0; k < 3; ++k) {
             const bool active = k == 0 || (k == 1 && cfg->ndim == 3) || (k == 2 && cfg->ndim >= 2);
             if (!active) continue;
-            g.dx[k] = lev ? 0.5 * h->geo.dx[k] : h->geo.dx[k];
+            g.dx[k] = std::ldexp(h->geo.dx[k], -lev);  // exact: level 0's width times 2^-lev
             g.inv_dx[k] = 1.0 / g.dx[k];
         }
         g.blocks[0] = P.lev_count[lev];
@@ -819,6 +894,7 @@ int hydro_smr_create(const hydro_config* cfg, int nref, const int32_t* refined, 
         h->lev_start[lev] = P.lev_start[lev];
         h->lev_count[lev] = P.lev_count[lev];
     }
+    for (int L = 0; L <= kMaxLevels; ++L) h->pro_off[L] = P.pro_off[L];
     h->tile[0] = default_tile(h->geo, cfg->precision, MODE_STAGE1);
     h->tile[1] = default_tile(h->geo, cfg->precision, MODE_STAGE2);
     h->stream = (hipStream_t)hip_stream;
@@ -1055,7 +1131,7 @@ int hydro_conserved_totals(hydro_t h, double* totals) {
         const long long BS = (long long)h->ncomp * h->geo.ncells;
         for (int c = 0; c < h->ncomp; ++c) totals[c] = 0.0;
         double dV = h->dV;
-        for (int lev = 0; lev < 2; ++lev, dV *= 1.0 / (1 << h->cfg.ndim)) {
+        for (int lev = 0; lev < h->nlev; ++lev, dV *= 1.0 / (1 << h->cfg.ndim)) {
             if (h->lev_count[lev] == 0) continue;
             hipError_t e = launch_totals(h->lgeo[lev], h->U + h->lev_start[lev] * BS, h->parts, kTotalsParts,
                                          h->ctrl, h->stream);

@@ -143,7 +143,9 @@ def _refined_arr(refined):
 
 
 def smr_leaves(cfg, refined):
-    """(level, c0, c1, c2) per leaf of a two-level refinement of cfg's blocks."""
+    """(level, c0, c1, c2) per leaf of a refinement of cfg's blocks (refined:
+    codes level * 2^26 + index on that level's block grid; root indices for
+    level 0)."""
     r = _refined_arr(refined)
     cap = 1 << 12
     out = (C.c_int32 * (4 * cap))()

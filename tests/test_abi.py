@@ -154,3 +154,30 @@ def test_refinement_validation_and_leaves(H):
         assert H.workspace_bytes(c, ref) == 0, ref
         with pytest.raises(H.HydroError):
             H.smr_leaves(c, ref)
+
+
+def test_deeper_refinement_plans_match_the_oracle(H):
+    """Refinement deeper than one level, planned on the host: the library's
+    leaves (with the balance refinement it adds) equal the oracle's for the
+    same codes, and the codes the oracle refuses are refused."""
+    import numpy as np
+    import oracle as O
+    LS = 26
+    cases = [
+        ((32,), (4,), [1, (1 << LS) | 3], ((1, 1),)),
+        ((32, 16), (4, 2), [1, 6, (1 << LS) | 3, (1 << LS) | 20], ((0, 0), (0, 0))),
+        ((32, 16), (4, 2), [1, 2, 5, 6, (1 << LS) | 3, (1 << LS) | 4], ((3, 3), (0, 0))),
+        ((16, 16, 8), (2, 2, 1), [0, (1 << LS) | 0, (1 << LS) | 5], ((0, 0), (0, 0), (1, 1))),
+        ((16, 16, 16), (2, 2, 2), [0, (1 << LS) | 0, (2 << LS) | 0], ((0, 0), (0, 0), (0, 0))),
+    ]
+    for n, B, codes, bc in cases:
+        cfg = H.make_config(n, 1.4, 0.4, bc=bc, blocks=B)
+        got = H.smr_leaves(cfg, codes)
+        want = O.SMR(O.Mesh(n, 1.4, bc=bc), B, codes).leaves
+        assert np.array_equal(got, want), (n, codes)
+        assert H.workspace_bytes(cfg, codes) > 0
+    cfg = H.make_config((32, 16), 1.4, 0.4, blocks=(4, 2))
+    for bad in ([(1 << LS) | 0], [(3 << LS) | 0], [0, (1 << LS) | 64], [-1]):
+        assert H.workspace_bytes(cfg, bad) == 0, bad
+        with pytest.raises(O.OracleError):
+            O.SMR(O.Mesh((32, 16), 1.4), (4, 2), bad)

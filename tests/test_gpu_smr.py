@@ -256,3 +256,103 @@ def test_shock_across_level_jumps_matches_oracle(H, name, n, B, ref, bc, steps, 
     rel = np.abs(a - b).sum(axis=1) / np.abs(b).sum(axis=1)
     print(name, precision, "relL1", rel, "steps", s)
     assert np.all(rel <= (1e-12 if precision == 0 else 1e-4)), rel
+
+
+# ---- refinement deeper than one level (codes: level << 26 | index on that
+# level's block grid; the library adds the balance refinement the oracle does)
+LS = 26
+LEVEL_CASES = [
+    ("1d three levels", (64,), (4,), [1, (1 << LS) | 3], ((F, OUT),)),
+    ("2d three levels", (64, 32), (4, 2), [1, 6, (1 << LS) | 3, (1 << LS) | 20], ((P, P), (P, P))),
+    ("2d walls, balance added", (64, 32), (4, 2), [1, 2, 5, 6, (1 << LS) | 3, (1 << LS) | 4],
+     ((R, R), (OUT, F))),
+    ("3d three levels", (32, 32, 16), (2, 2, 2), [0, (1 << LS) | 0, (1 << LS) | 5], ((P, P), (P, P), (F, R))),
+    ("3d four levels", (32, 32, 32), (2, 2, 2), [0, (1 << LS) | 0, (2 << LS) | 0], ((P, P), (P, P), (P, P))),
+]
+
+
+@pytest.mark.parametrize("name,n,B,ref,bc", LEVEL_CASES, ids=[c[0] for c in LEVEL_CASES])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_deeper_refinement_matches_oracle(H, name, n, B, ref, bc, precision):
+    m = O.Mesh(n, 1.4, bc=bc)
+    S = O.SMR(m, B, ref)
+    assert S.leaves[:, 0].max() >= 2
+    W = smooth_state(S, seed=67)
+    steps = 6
+    U_o, t_o, s_o, _ = S.run(S.prim_to_cons(W), 0.4, max_steps=steps)
+    say("smr levels vs oracle", name, precision)
+    U, t, s, T = run_gpu(H, S, W, precision, steps, 0.4)
+    assert s == s_o == steps
+    assert abs(t - t_o) <= (1e-14 if precision == 0 else 1e-6) * t_o
+    a = U.transpose(1, 0, 2, 3, 4).reshape(m.ncomp, -1)
+    b = U_o.transpose(1, 0, 2, 3, 4).reshape(m.ncomp, -1)
+    rel = np.abs(a - b).sum(axis=1) / np.abs(b).sum(axis=1)
+    print(name, precision, "leaves per level", np.bincount(S.leaves[:, 0]), "relL1", rel)
+    assert np.all(rel <= TOL[precision]), rel
+    T_o = S.totals(U)
+    assert np.allclose(T, T_o, rtol=1e-12, atol=1e-12 * np.abs(T_o).max())
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_deeper_refinement_conserves_and_keeps_uniform_state(H, precision):
+    n, B, ref = (32, 32, 16), (2, 2, 2), [0, 3, (1 << LS) | 0, (1 << LS) | 27]
+    m = O.Mesh(n, 5.0 / 3.0)
+    S = O.SMR(m, B, ref)
+    assert S.leaves[:, 0].max() == 2
+    W = smooth_state(S, seed=68, amp=0.3, mach=1.0)
+    say("smr levels conservation", precision)
+    h = H.Hydro(n, m.gamma, 0.3, precision=precision, blocks=B, refined=ref)
+    h.set_primitive(W)
+    T0 = h.totals()
+    h.step_auto(15)
+    T1 = h.totals()
+    h.close()
+    scale = S.totals(np.abs(S.prim_to_cons(W)))
+    print("drift", (T1 - T0) / scale)
+    assert np.all(np.abs(T1 - T0) <= 1e-13 * scale)
+    Wu = np.empty(S.shape)
+    Wu[:, 0], Wu[:, 1], Wu[:, 2], Wu[:, 3], Wu[:, 4] = 1.3, 0.7, -0.4, 0.2, 0.9
+    h = H.Hydro(n, 1.4, 0.4, precision=precision, blocks=B, refined=ref)
+    h.set_primitive(Wu)
+    U0 = h.get_state()
+    h.step_auto(4)
+    assert bitwise_equal(h.get_state(), U0)
+    h.close()
+
+
+def test_everything_refined_twice_is_the_mesh_four_times_finer(H):
+    c = wl.turbulence_3d(n=(32, 32, 32), mach=1.0, seed=69)
+    say("smr everything refined twice")
+    a = H.Hydro(c.n, c.gamma, c.cfl, precision=0, blocks=(4, 4, 4))
+    a.set_primitive(c.W)
+    a.step_auto(3)
+    Ua = a.state_view().cpu().numpy()
+    codes = list(range(1)) + [(1 << LS) | i for i in range(8)]
+    b = H.Hydro((8, 8, 8), c.gamma, c.cfl, precision=0, blocks=(1, 1, 1), refined=codes)
+    assert np.all(b.leaves[:, 0] == 2)
+    Wb = np.ascontiguousarray(c.W.reshape(5, 4, 8, 4, 8, 4, 8).transpose(1, 3, 5, 0, 2, 4, 6).reshape(b.shape))
+    b.set_primitive(Wb)
+    b.step_auto(3)
+    assert a.time() == b.time()
+    assert bitwise_equal(b.get_state(), Ua)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_shock_across_two_levels_of_jumps_matches_oracle(H, precision):
+    """Sod's shock through a band refined twice (1-D, to t = 0.2)."""
+    n, B, ref, bc = (64,), (8,), [3, 4, (1 << LS) | 7, (1 << LS) | 8], ((F, F),)
+    m = O.Mesh(n, 1.4, bc=bc)
+    S = O.SMR(m, B, ref)
+    assert S.leaves[:, 0].max() == 2
+    W = sod_state(S)
+    U_o, t_o, s_o, _ = S.run(S.prim_to_cons(W), 0.4, t_end=0.2)
+    say("smr shock two levels", precision)
+    U, t, s, T = run_gpu(H, S, W, precision, s_o + 4, 0.4, 0.2)
+    assert s == s_o and t == 0.2
+    a = U.transpose(1, 0, 2, 3, 4).reshape(m.ncomp, -1)
+    b = U_o.transpose(1, 0, 2, 3, 4).reshape(m.ncomp, -1)
+    rel = np.abs(a - b).sum(axis=1) / np.abs(b).sum(axis=1)
+    print("shock two levels", precision, "relL1", rel, "steps", s)
+    assert np.all(rel <= (1e-12 if precision == 0 else 1e-4)), rel

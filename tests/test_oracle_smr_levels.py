@@ -97,19 +97,18 @@ def test_leaves_are_balanced(ndim):
     assert len(S.leaves) > np.prod(B) - 1 + listed - 1    # balance added blocks
 
 
-@pytest.mark.parametrize("bad", [
-    [code(1, 0)],                          # a level-1 block whose parent is not listed
-    [code(0, 0), code(1, 0), code(2, 0)],  # a level-2 block listed: leaves would reach level 3 ... allowed?
+@pytest.mark.parametrize("spec", [
+    [code(1, 0)],                          # a level-1 block whose parent is not listed: refused
+    [code(0, 0), code(1, 0), code(2, 0)],  # a level-2 block with its ancestors: leaves reach level 3
 ])
-def test_refused_or_accepted_specs(bad):
+def test_refused_or_accepted_specs(spec):
     m = O.Mesh((32, 16), 1.4)
-    if bad[-1] >> LS == 2:
-        # level-2 blocks may be listed (leaves then reach level 3, the deepest)
-        S = O.SMR(m, (4, 2), bad)
+    if spec[-1] >> LS == 2:
+        S = O.SMR(m, (4, 2), spec)
         assert S.leaves[:, 0].max() == 3
     else:
         with pytest.raises(O.OracleError):
-            O.SMR(m, (4, 2), bad)
+            O.SMR(m, (4, 2), spec)
 
 
 @pytest.mark.parametrize("bad", [[code(3, 0)], [code(0, 8)], [code(0, 1), code(0, 1)], [-1]])

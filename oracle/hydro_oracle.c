@@ -1266,8 +1266,10 @@ static void smr_fill_ghosts(const smrgeo* g, double* Wp) {
     }
 }
 
-/* Stage right-hand side of every leaf from X (conserved, block layout). */
-static int smr_rhs(const smrgeo* g, const double* X, double dt, double* dU) {
+/* Stage right-hand side of every leaf from X (conserved, block layout), with
+ * PLM face states (order 2) or piecewise-constant ones (order 1).  The
+ * cross-level ghosts are the same for both orders. */
+static int smr_rhs(const smrgeo* g, const double* X, double dt, int order, double* dU) {
     const orc_mesh* mb = &g->mb;
     int ndim = mb->ndim, nc = ndim + 2;
     int n0 = mb->n[0], n1 = mb->n[1], n2 = mb->n[2];
@@ -1298,7 +1300,7 @@ static int smr_rhs(const smrgeo* g, const double* X, double dt, double* dU) {
     int rc = bad;
     if (rc == 0) smr_fill_ghosts(g, Wp);
     for (int b = 0; b < g->nleaf && rc == 0; ++b)
-        rc = block_fluxes(mb, Wp + (int64_t)b * nc * pg.total, 2, &ff[b]);
+        rc = block_fluxes(mb, Wp + (int64_t)b * nc * pg.total, order, &ff[b]);
     /* (d) coarse faces shared with finer blocks take the fine fluxes' average */
     for (int b = 0; b < g->nleaf && rc == 0; ++b) {
         for (int d = 0; d < ndim; ++d) {
@@ -1414,7 +1416,7 @@ int orc_run_smr(const orc_mesh* m, const int32_t blocks[3], int nref, const int3
                 double cfl, int max_steps, double t_end, double* t, int* steps_done, double* dts) {
     smrgeo g;
     if (!smr_geometry(m, blocks, nref, refined, &g) || !t || !(cfl > 0.0) ||
-        (max_steps <= 0 && !(t_end > 0.0)) || m->integrator != ORC_HEUN) {
+        (max_steps <= 0 && !(t_end > 0.0)) || (m->integrator != ORC_HEUN && m->integrator != ORC_VL2)) {
         smr_free(&g);
         return -1;
     }
@@ -1434,12 +1436,25 @@ int orc_run_smr(const orc_mesh* m, const int32_t blocks[3], int nref, const int3
             dt = t_end - *t;
             last = 1;
         }
-        rc = smr_rhs(&g, U, dt, dU);
-        if (rc) break;
-        for (int64_t q = 0; q < tot; ++q) U1[q] = U[q] + dU[q];
-        rc = smr_rhs(&g, U1, dt, dU);
-        if (rc) break;
-        for (int64_t q = 0; q < tot; ++q) U[q] = 0.5 * U[q] + 0.5 * (U1[q] + dU[q]);
+        if (m->integrator == ORC_VL2) {
+            /* van Leer (Sec. 3.3): the half-step predictor from
+             * piecewise-constant states, U* = U^n + (dt/2) L_1(U^n), then
+             * U^{n+1} = U^n + dt L_2(U*) from PLM states of W(U*); both
+             * stages with the level-jump ghosts and flux corrections */
+            rc = smr_rhs(&g, U, 0.5 * dt, 1, dU);
+            if (rc) break;
+            for (int64_t q = 0; q < tot; ++q) U1[q] = U[q] + dU[q];
+            rc = smr_rhs(&g, U1, dt, 2, dU);
+            if (rc) break;
+            for (int64_t q = 0; q < tot; ++q) U[q] = U[q] + dU[q];
+        } else {
+            rc = smr_rhs(&g, U, dt, 2, dU);
+            if (rc) break;
+            for (int64_t q = 0; q < tot; ++q) U1[q] = U[q] + dU[q];
+            rc = smr_rhs(&g, U1, dt, 2, dU);
+            if (rc) break;
+            for (int64_t q = 0; q < tot; ++q) U[q] = 0.5 * U[q] + 0.5 * (U1[q] + dU[q]);
+        }
         if (dts) dts[s] = dt;
         *t = last ? t_end : *t + dt;
         ++s;

@@ -133,7 +133,9 @@ int orc_run_blocks(const orc_mesh* m, const int32_t blocks[3], double* U, double
  * volume averages) onto coarse ghosts, then minmod-limited prolongation onto
  * fine ghosts level by level from the coarsest, fluxes, and the average of
  * the fine fluxes on the coarse side of each level jump; all on primitive
- * variables; one global time step; Heun only.
+ * variables; one global time step.  Both integrators: Heun, or van Leer
+ * with both stages (the piecewise-constant predictor and the PLM corrector)
+ * taking the same cross-level ghosts and flux averages.
  *
  * orc_smr_leaves writes (level, c0, c1, c2) per leaf (at most max) and
  * returns the leaf count, or -1 for an invalid refinement.

@@ -283,7 +283,12 @@ int hydro_profile_read(hydro_t h, double* ms_stage1, double* ms_stage2, int64_t*
  * the same extents in cells; then, as the paper does, refinement is added on
  * the coarser side until no two face-neighbouring leaves are more than one
  * level apart.  Refinement needs even block extents of at least 4 cells on
- * the active axes, the Heun integrator, and at most 1024 leaves.
+ * the active axes and at most 1024 leaves; both integrators are supported.
+ * The van Leer integrator (Sec. 3.3) keeps its predicted state on a refined
+ * handle as conserved FP64 values in the second field (not primitive values
+ * of the compute type), so the level-jump passes below apply to its
+ * predictor (fluxes of piecewise-constant states, half a step) and corrector
+ * alike; the workspace is the same for both integrators.
  *   - Leaves are ordered by level, and within a level in the order of that
  *     level's block grid (x fastest).  hydro_smr_leaves writes (level, c0,
  *     c1, c2) per leaf (at most max entries, block coordinates on the leaf's

@@ -130,8 +130,19 @@ struct MeshDesc {
 };
 
 // Stage kernels: the Heun stages (and the stage right-hand side), and the
-// van Leer predictor and corrector (Sec. 3.3).
-enum StageMode : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2, MODE_VL2_PRED = 3, MODE_VL2_CORR = 4 };
+// van Leer predictor and corrector (Sec. 3.3).  The _C forms keep the
+// predicted state conserved in FP64 (a refined mesh, whose level-jump passes
+// read conserved stage inputs): the predictor writes U* = U^n + (dt/2) L_1(U^n)
+// and the corrector reads U* as its stencil input.
+enum StageMode : int {
+    MODE_RHS = 0,
+    MODE_STAGE1 = 1,
+    MODE_STAGE2 = 2,
+    MODE_VL2_PRED = 3,
+    MODE_VL2_CORR = 4,
+    MODE_VL2_PRED_C = 5,
+    MODE_VL2_CORR_C = 6
+};
 
 hipError_t launch_stage(int precision, int mode, const Tile& tile, StageArgs a, hipStream_t s);
 // The same launch described (kernel, grid, block, arguments) instead of
@@ -174,15 +185,16 @@ hipError_t launch_riemann(int precision, int ntan, double gamma, long long n, co
 // kind): restriction or prolongation of the stage input U into gbuf
 // (conserved FP64 values); the fine-flux corrections of the coarse cells next
 // to every level jump, from the stage input in, into dbuf (factor * lam *
-// (coarse flux - mean of the fine fluxes), [slot][comp][face]); and their
+// (coarse flux - mean of the fine fluxes), [slot][comp][face]; first: fluxes
+// of piecewise-constant states, as in the van Leer predictor); and their
 // addition to out for the restriction slots idx0 .. idx0 + n - 1 of one
 // kernel axis.  g0 and g1 are the coarse and fine levels' geometries.
 hipError_t launch_smr_restrict(const Geo& g, const double* U, const int* side, double* gbuf, long long gcs,
                                const GhostTask* tasks, int n, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_smr_prolong(const Geo& g, const double* U, const int* side, double* gbuf, long long gcs,
                               const GhostTask* tasks, int n, Ctrl* ctrl, hipStream_t s);
-hipError_t launch_smr_reflux(int precision, const Geo& g0, const Geo& g1, const double* in, double* dbuf,
-                             double factor, int use_device_dt, double dt_host, const int* side,
+hipError_t launch_smr_reflux(int precision, int first, const Geo& g0, const Geo& g1, const double* in,
+                             double* dbuf, double factor, int use_device_dt, double dt_host, const int* side,
                              const double* gbuf, long long gcs, const GhostTask* tasks, int n, Ctrl* ctrl,
                              hipStream_t s);
 hipError_t launch_smr_apply(const Geo& g0, double* out, const double* dbuf, long long gcs, const GhostTask* tasks,

@@ -769,13 +769,15 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
     constexpr bool HZ = (NDIM >= 2);
     constexpr int NT = TX * TY;
     // van Leer modes: the predictor (piecewise-constant states, half step,
-    // writes the predicted primitive state of type R into a.out) and the
-    // corrector (reads that state as its stencil input, PLM, full step from
-    // U^n in a.base, writes U^{n+1} to a.out)
-    constexpr bool PRED = MODE == MODE_VL2_PRED;
-    constexpr bool CORR = MODE == MODE_VL2_CORR;
+    // writes the predicted primitive state of type R into a.out; _C: the
+    // predicted conserved state in FP64) and the corrector (reads that state
+    // as its stencil input, PLM, full step from U^n in a.base, writes
+    // U^{n+1} to a.out)
+    constexpr bool PRED = MODE == MODE_VL2_PRED || MODE == MODE_VL2_PRED_C;
+    constexpr bool CORR = MODE == MODE_VL2_CORR || MODE == MODE_VL2_CORR_C;
+    constexpr bool PRIM_OUT = MODE == MODE_VL2_PRED;
     constexpr bool FIRST = PRED;
-    constexpr bool PRIM_IN = CORR;
+    constexpr bool PRIM_IN = MODE == MODE_VL2_CORR;
     constexpr bool NEED_UIN = MODE == MODE_STAGE1 || MODE == MODE_STAGE2 || PRED;
     constexpr bool NEED_BASE = MODE == MODE_STAGE2 || CORR;
     constexpr bool EPILOGUE = MODE == MODE_STAGE2 || CORR;
@@ -908,7 +910,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
     auto load_halo = [&](int k, double (&u)[NC]) {
         const long long o = hcol + (long long)k * hk;
         if constexpr (PRIM_IN) {
-            // (refined meshes, whose ghost slots hold conserved values, run Heun only)
+            // (a refined mesh's ghost slots hold conserved values: its van
+            // Leer corrector reads the conserved predictor, not this form)
             const R* F = reinterpret_cast<const R*>(a.in) + o;
 #pragma unroll
             for (int c = 0; c < NC; ++c) u[c] = (double)F[c * hc];
@@ -1164,10 +1167,10 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
                     r = ubase[c] + acc;
                 else
                     r = 0.5 * ubase[c] + 0.5 * (uin[c] + acc);
-                if (!PRED) plane_store<double, EPILOGUE ? kNonTemporal : 0>(a.out, c * N + kuP, ext8, colb, r);
+                if (!PRIM_OUT) plane_store<double, EPILOGUE ? kNonTemporal : 0>(a.out, c * N + kuP, ext8, colb, r);
                 unew[c] = r;
             }
-            if (PRED) {
+            if (PRIM_OUT) {
                 // the predicted state is kept only as primitive variables of type R
                 double w[NC];
                 bad |= !cons_to_prim<NDIM>(gm1, unew, w);
@@ -1760,7 +1763,7 @@ __global__ __launch_bounds__(64) void smr_prolong_kernel(Geo g, const double* __
 // recomputed from the same stage input, ghosts and operations as in the
 // stage kernel, so F_coarse cancels exactly.  The correction goes to
 // dbuf[idx][comp][r]; smr_apply_kernel adds it.
-template <int NDIM, typename R, int AX>
+template <int NDIM, typename R, bool FIRST, int AX>
 __device__ __forceinline__ void reflux_face(const Geo& g0, const Geo& g1, const double* __restrict__ in,
                                             double* __restrict__ dbuf, double factor, double dt,
                                             const int* __restrict__ side, const double* __restrict__ gbuf,
@@ -1793,7 +1796,7 @@ __device__ __forceinline__ void reflux_face(const Geo& g0, const Geo& g1, const 
         in_to_w<NDIM, R, false>(gm1, u, vax, vm, w[j], bad);
     }
     R Fc[NC];
-    face_flux<NDIM, AX, R>(gr, w[0], w[1], w[2], w[3], Fc);
+    face_flux<NDIM, AX, R, FIRST>(gr, w[0], w[1], w[2], w[3], Fc);
     // the fine fluxes through it, by transverse child offsets
     // pairwise means as the fluxes arrive (offsets 0, 1 -> a; 2, 3 -> b),
     // the same operations as a tree of pairwise means
@@ -1828,7 +1831,7 @@ __device__ __forceinline__ void reflux_face(const Geo& g0, const Geo& g1, const 
             in_to_w<NDIM, R, false>(gm1, u, vax, vm, v[j], bad);
         }
         R F[NC];
-        face_flux<NDIM, AX, R>(gr, v[0], v[1], v[2], v[3], F);
+        face_flux<NDIM, AX, R, FIRST>(gr, v[0], v[1], v[2], v[3], F);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const double f = (double)F[c];
@@ -1849,7 +1852,8 @@ __device__ __forceinline__ void reflux_face(const Geo& g0, const Geo& g1, const 
 
 // The corrections of every restriction slot, one launch for all axes:
 // blockIdx.x the slot (in slot order), one thread per coarse face.
-template <int NDIM, typename R>
+// FIRST: the fluxes of piecewise-constant states (the van Leer predictor).
+template <int NDIM, typename R, bool FIRST>
 __global__ __launch_bounds__(64) void smr_reflux_kernel(Geo g0, Geo g1, const double* __restrict__ in,
                                                          double* __restrict__ dbuf, double factor,
                                                          int use_device_dt, double dt_host,
@@ -1862,13 +1866,13 @@ __global__ __launch_bounds__(64) void smr_reflux_kernel(Geo g0, Geo g1, const do
     const int r = blockIdx.y * blockDim.x + threadIdx.x;
     bool bad = false;
     if (t.ax == 0) {
-        reflux_face<NDIM, R, 0>(g0, g1, in, dbuf, factor, dt, side, gbuf, gcs, t, blockIdx.x, r, bad);
+        reflux_face<NDIM, R, FIRST, 0>(g0, g1, in, dbuf, factor, dt, side, gbuf, gcs, t, blockIdx.x, r, bad);
     } else if (t.ax == 1) {
         if constexpr (NDIM == 3)
-            reflux_face<NDIM, R, 1>(g0, g1, in, dbuf, factor, dt, side, gbuf, gcs, t, blockIdx.x, r, bad);
+            reflux_face<NDIM, R, FIRST, 1>(g0, g1, in, dbuf, factor, dt, side, gbuf, gcs, t, blockIdx.x, r, bad);
     } else {
         if constexpr (NDIM >= 2)
-            reflux_face<NDIM, R, 2>(g0, g1, in, dbuf, factor, dt, side, gbuf, gcs, t, blockIdx.x, r, bad);
+            reflux_face<NDIM, R, FIRST, 2>(g0, g1, in, dbuf, factor, dt, side, gbuf, gcs, t, blockIdx.x, r, bad);
     }
     if (bad) atomicOr(&ctrl->flags, FLAG_NONPHYSICAL);
 }
@@ -2003,12 +2007,27 @@ hipError_t launch_stage_t(const LaunchCtx& L, hipStream_t s) {
             return hipSuccess;
         }
         hipLaunchKernelGGL((stage_kernel<NDIM, R, MODE, TX, TY>), dim3((unsigned)nb), dim3(TX * TY), 0, s, a);
+    } else if constexpr (MODE == MODE_RHS || MODE == MODE_VL2_PRED_C || MODE == MODE_VL2_CORR_C) {
+        return hipErrorInvalidValue;  // not a batch member's stage
     } else {
         if (L.nblk <= 0) return hipSuccess;
         hipLaunchKernelGGL((stage_kernel_batch<NDIM, R, MODE, TX, TY>), dim3(L.nblk), dim3(TX * TY), 0, s,
                            L.d, L.blk);
     }
     return hipGetLastError();
+}
+
+// The van Leer stages of a refined mesh (conserved predictor) take one tile
+// each: a refined handle is not autotuned.
+template <int NDIM, typename R, int MODE>
+hipError_t launch_stage_refined(const Tile& t, const LaunchCtx& L, hipStream_t s) {
+    if (!L.a) return hipErrorInvalidValue;
+    if constexpr (NDIM == 3) {
+        if (t.tx == 32 && t.ty == 8) return launch_stage_t<NDIM, R, MODE, 32, 8>(L, s);
+    } else {
+        if (t.tx == 64 && t.ty == 1) return launch_stage_t<NDIM, R, MODE, 64, 1>(L, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int NDIM, typename R, int MODE>
@@ -2038,6 +2057,8 @@ hipError_t launch_stage_mode(int mode, const Tile& t, const LaunchCtx& L, hipStr
         case MODE_STAGE2: return launch_stage_tile<NDIM, R, MODE_STAGE2>(t, L, s);
         case MODE_VL2_PRED: return launch_stage_tile<NDIM, R, MODE_VL2_PRED>(t, L, s);
         case MODE_VL2_CORR: return launch_stage_tile<NDIM, R, MODE_VL2_CORR>(t, L, s);
+        case MODE_VL2_PRED_C: return launch_stage_refined<NDIM, R, MODE_VL2_PRED_C>(t, L, s);
+        case MODE_VL2_CORR_C: return launch_stage_refined<NDIM, R, MODE_VL2_CORR_C>(t, L, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -2062,7 +2083,11 @@ hipError_t launch_any(int ndim, int precision, int mode, const Tile& t, const La
 
 Tile default_tile(const Geo& g, int precision, int mode) {
     Tile t;
-    if (g.ndim == 3) {
+    if (mode == MODE_VL2_PRED_C || mode == MODE_VL2_CORR_C) {
+        // the one tile of the refined mesh's van Leer stages
+        t.tx = g.ndim == 3 ? 32 : 64;
+        t.ty = g.ndim == 3 ? 8 : 1;
+    } else if (g.ndim == 3) {
         // From a sweep at 256^3: 32 x 16 halves the share of halo cells and
         // extra faces where the occupancy allows it; 32 x 8 where a larger
         // work-group would cost occupancy (the mixed Heun stage 2 beside its
@@ -2299,21 +2324,28 @@ hipError_t launch_smr_prolong(const Geo& g, const double* U, const int* side, do
     return hipGetLastError();
 }
 
-hipError_t launch_smr_reflux(int precision, const Geo& g0, const Geo& g1, const double* in, double* dbuf,
-                             double factor, int use_device_dt, double dt_host, const int* side,
+hipError_t launch_smr_reflux(int precision, int first, const Geo& g0, const Geo& g1, const double* in,
+                             double* dbuf, double factor, int use_device_dt, double dt_host, const int* side,
                              const double* gbuf, long long gcs, const GhostTask* tasks, int n, Ctrl* ctrl,
                              hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const dim3 grid(n, (unsigned)((gcs / 2 + 63) / 64));  // one thread per face of the largest side
-#define RF(ND, RT) hipLaunchKernelGGL((smr_reflux_kernel<ND, RT>), grid, dim3(64), 0, s, g0, g1, in, dbuf, factor, \
-                                      use_device_dt, dt_host, side, gbuf, gcs, tasks, ctrl)
-    switch (g0.ndim * 2 + (precision == 0 ? 0 : 1)) {
-        case 2: RF(1, double); break;
-        case 3: RF(1, float); break;
-        case 4: RF(2, double); break;
-        case 5: RF(2, float); break;
-        case 6: RF(3, double); break;
-        case 7: RF(3, float); break;
+#define RF(ND, RT, FO)                                                                                          \
+    hipLaunchKernelGGL((smr_reflux_kernel<ND, RT, FO>), grid, dim3(64), 0, s, g0, g1, in, dbuf, factor, \
+                       use_device_dt, dt_host, side, gbuf, gcs, tasks, ctrl)
+    switch ((g0.ndim * 2 + (precision == 0 ? 0 : 1)) * 2 + (first ? 1 : 0)) {
+        case 4: RF(1, double, false); break;
+        case 5: RF(1, double, true); break;
+        case 6: RF(1, float, false); break;
+        case 7: RF(1, float, true); break;
+        case 8: RF(2, double, false); break;
+        case 9: RF(2, double, true); break;
+        case 10: RF(2, float, false); break;
+        case 11: RF(2, float, true); break;
+        case 12: RF(3, double, false); break;
+        case 13: RF(3, double, true); break;
+        case 14: RF(3, float, false); break;
+        case 15: RF(3, float, true); break;
         default: return hipErrorInvalidValue;
     }
 #undef RF

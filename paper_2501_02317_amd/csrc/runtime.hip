@@ -128,6 +128,12 @@ size_t second_bytes(const hydro_config* c) {
 
 int stage1_mode(const hydro_config* c) { return c->integrator == HYDRO_VL2 ? MODE_VL2_PRED : MODE_STAGE1; }
 int stage2_mode(const hydro_config* c) { return c->integrator == HYDRO_VL2 ? MODE_VL2_CORR : MODE_STAGE2; }
+// Stage st of a refined mesh: the van Leer predictor stays conserved FP64,
+// since the level-jump passes read conserved stage inputs.
+int smr_mode(const hydro_config* c, int st) {
+    if (c->integrator == HYDRO_VL2) return st == 0 ? MODE_VL2_PRED_C : MODE_VL2_CORR_C;
+    return st == 0 ? MODE_STAGE1 : MODE_STAGE2;
+}
 
 // Kernel-axis geometry of one block (see hydro_internal.h).
 Geo make_geo(const hydro_config* c) {
@@ -432,7 +438,7 @@ hipError_t free_tmp(hydro_t h, double* d, hipError_t e) {
 
 // Launch one stage, bracketed by events when profiling is on.
 hipError_t timed_stage(hydro_t h, int mode, const StageArgs& a) {
-    const int st = (mode == MODE_STAGE2 || mode == MODE_VL2_CORR) ? 1 : 0;
+    const int st = (mode == MODE_STAGE2 || mode == MODE_VL2_CORR || mode == MODE_VL2_CORR_C) ? 1 : 0;
     const bool rec = h->prof_cap > 0 && h->prof_n[st] < h->prof_cap;
     hipError_t e = hipSuccess;
     if (rec) e = hipEventRecord(h->prof_ev[st][2 * h->prof_n[st]], h->stream);
@@ -467,14 +473,17 @@ LevelStarts level_starts(hydro_t h) {
     return ls;
 }
 
-// One step of a refined mesh (Heun).  Each stage: the ghost slots of the
-// level jumps from the stage input (restriction, then prolongation level by
-// level from the coarsest, since a coarse block's stencil may include its own
-// prolonged slots), the stage kernel per level, then the flux correction of
-// the coarse cells at the level jumps (computed for every jump in one
-// launch, added axis by axis: a cell next to two jumps is corrected once per
-// axis, in order).  The CFL rate of the corrected state is a reduction of its
-// own.
+// One step of a refined mesh (Heun, or van Leer with its predicted state
+// conserved in U1).  Each stage: the ghost slots of the level jumps from the
+// stage input (restriction, then prolongation level by level from the
+// coarsest, since a coarse block's stencil may include its own prolonged
+// slots), the stage kernel per level, then the flux correction of the coarse
+// cells at the level jumps (computed for every jump in one launch, added axis
+// by axis: a cell next to two jumps is corrected once per axis, in order).
+// The correction's weight: Heun 1 after stage 1 and 1/2 after stage 2 (the
+// stage-2 update averages with U^n); van Leer 1/2 after the predictor (half
+// a step, fluxes of piecewise-constant states) and 1 after the corrector.
+// The CFL rate of the corrected state is a reduction of its own.
 hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
     hipError_t e = hipSuccess;
     // With a second stream (smr_aux), the passes that the level-0 stage does
@@ -484,7 +493,10 @@ hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
     // additions for the recomputation.
     const bool fork = h->smr_aux && !capturing(h);
     hipStream_t aux = fork ? h->smr_aux : h->stream;
+    const bool vl2 = h->cfg.integrator == HYDRO_VL2;
     for (int st = 0; st < 2 && e == hipSuccess; ++st) {
+        const int first = vl2 && st == 0 ? 1 : 0;
+        const double factor = vl2 ? (st == 0 ? 0.5 : 1.0) : (st == 0 ? 1.0 : 0.5);
         const double* in = st == 0 ? h->U : h->U1;
         double* out = st == 0 ? h->U1 : h->U;
         e = launch_smr_restrict(h->lgeo[0], in, h->d_side, h->gbuf, h->gcs, h->d_tasks, h->nres, h->ctrl, h->stream);
@@ -495,7 +507,7 @@ hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
                                    h->pro_off[L + 1] - h->pro_off[L], h->ctrl, aux);
         if (e == hipSuccess && fork) e = hipEventRecord(h->ev_smr[1], aux);
         if (e == hipSuccess)
-            e = launch_smr_reflux(h->cfg.precision, h->lgeo[0], h->lgeo[0], in, h->dbuf, st == 0 ? 1.0 : 0.5,
+            e = launch_smr_reflux(h->cfg.precision, first, h->lgeo[0], h->lgeo[0], in, h->dbuf, factor,
                                   device_dt ? 1 : 0, dt, h->d_side, h->gbuf, h->gcs, h->d_tasks, h->nres, h->ctrl,
                                   aux);
         if (e == hipSuccess && fork) e = hipEventRecord(h->ev_smr[2], aux);
@@ -512,7 +524,7 @@ hipError_t enqueue_step_smr(hydro_t h, bool device_dt, double dt) {
             a.base = h->U;
             a.out = out;
             a.want_dt = 0;
-            e = timed_stage(h, st == 0 ? MODE_STAGE1 : MODE_STAGE2, a);
+            e = timed_stage(h, smr_mode(&h->cfg, st), a);
         }
         if (e == hipSuccess && fork) e = hipStreamWaitEvent(h->stream, h->ev_smr[2], 0);
         for (int ax = 0; ax < 3 && e == hipSuccess; ++ax)
@@ -582,7 +594,7 @@ struct SmrPlan {
 };
 
 bool smr_plan(const hydro_config* c, int nref, const int32_t* refined, SmrPlan& P) {
-    if (!config_ok(c) || c->integrator != HYDRO_HEUN || nref < 0 || (nref > 0 && !refined)) return false;
+    if (!config_ok(c) || nref < 0 || (nref > 0 && !refined)) return false;
     const int nd = c->ndim;
     int B[3], nb[3];
     for (int d = 0; d < 3; ++d) {
@@ -895,8 +907,8 @@ int hydro_smr_create(const hydro_config* cfg, int nref, const int32_t* refined, 
         h->lev_count[lev] = P.lev_count[lev];
     }
     for (int L = 0; L <= kMaxLevels; ++L) h->pro_off[L] = P.pro_off[L];
-    h->tile[0] = default_tile(h->geo, cfg->precision, MODE_STAGE1);
-    h->tile[1] = default_tile(h->geo, cfg->precision, MODE_STAGE2);
+    h->tile[0] = default_tile(h->geo, cfg->precision, smr_mode(cfg, 0));
+    h->tile[1] = default_tile(h->geo, cfg->precision, smr_mode(cfg, 1));
     h->stream = (hipStream_t)hip_stream;
     h->ncomp = cfg->ndim + 2;
     h->dV = 1.0;

@@ -148,12 +148,19 @@ def test_refinement_validation_and_leaves(H):
         (cfg, [1, 1]),                                                       # listed twice
         (H.make_config((24, 16), 1.4, 0.4, blocks=(8, 2)), [0]),             # blocks of 3 cells
         (H.make_config((8, 16), 1.4, 0.4, blocks=(4, 2)), [0]),              # blocks of 2 cells
-        (H.make_config((32, 16), 1.4, 0.4, blocks=(4, 2), integrator=1), [0]),  # van Leer
     ]
     for c, ref in bad:
         assert H.workspace_bytes(c, ref) == 0, ref
         with pytest.raises(H.HydroError):
             H.smr_leaves(c, ref)
+    # the van Leer integrator refines the same way, in the same workspace
+    # (its predicted state stays conserved FP64 on a refined handle)
+    vl = H.make_config((32, 16), 1.4, 0.4, blocks=(4, 2), integrator=1)
+    for prec in (0, 1):
+        vp = H.make_config((64, 32), 1.4, 0.4, precision=prec, blocks=(4, 2), integrator=1)
+        hp = H.make_config((64, 32), 1.4, 0.4, precision=prec, blocks=(4, 2))
+        assert H.workspace_bytes(vp, [1, 6]) == H.workspace_bytes(hp, [1, 6]) > 0
+    assert np.array_equal(H.smr_leaves(vl, [1, 6]), L)
 
 
 def test_deeper_refinement_plans_match_the_oracle(H):

@@ -40,6 +40,7 @@ CASES = [pytest.param("single", None, None, False, 1, 0, 0.0, id="single"),
          pytest.param("fp64", None, None, False, 0, 0, 0.0, id="fp64"),
          pytest.param("van Leer", (1, 2, 2), None, False, 1, 1, 0.0, id="van Leer"),
          pytest.param("refined fp64", (2, 2, 2), [1, 2, 7], False, 0, 0, 0.0, id="refined fp64"),
+         pytest.param("refined van Leer", (2, 2, 2), [0, 6], False, 1, 1, 0.0, id="refined van Leer"),
          # the end time falls inside the second replay: the step that would
          # pass it lands on it, and the third replay changes nothing
          pytest.param("to t_end", (2, 1, 1), None, False, 1, 0, 0.0135, id="to t_end")]

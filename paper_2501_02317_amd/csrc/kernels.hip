@@ -90,6 +90,15 @@ struct Ops<double> {
     static __device__ __forceinline__ double minmod(double a, double b) {
         return __builtin_fmax(__builtin_fmin(a, b), __builtin_fmin(__builtin_fmax(a, b), 0.0));
     }
+    // The slopes of the two cells beside a face, minmod(a, m) and
+    // minmod(m, b), with m the difference across the face: the median of
+    // (x, m, 0) is x clamped to [min(m, 0), max(m, 0)], and the two bounds
+    // serve both slopes (FP64 min and max issue at half rate).
+    static __device__ __forceinline__ void minmod2(double a, double m, double b, double& sa, double& sb) {
+        const double lo = __builtin_fmin(m, 0.0), hi = __builtin_fmax(m, 0.0);
+        sa = __builtin_fmin(__builtin_fmax(a, lo), hi);
+        sb = __builtin_fmin(__builtin_fmax(b, lo), hi);
+    }
 };
 
 template <>
@@ -101,6 +110,10 @@ struct Ops<float> {
     static __device__ __forceinline__ float rsq1(float x) { return __builtin_amdgcn_rsqf(x); }
     static __device__ __forceinline__ float max0(float x) { return __builtin_fmaxf(x, 0.0f); }
     static __device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
+    static __device__ __forceinline__ void minmod2(float a, float m, float b, float& sa, float& sb) {
+        sa = __builtin_amdgcn_fmed3f(a, m, 0.0f);
+        sb = __builtin_amdgcn_fmed3f(m, b, 0.0f);
+    }
 };
 
 // Gas constants in the compute precision.
@@ -164,7 +177,9 @@ __device__ __forceinline__ bool cons_to_prim(double gm1, const double (&u)[NDIM 
 //   s_* from the bracketed form of eq. hllc-contact-spd.  Only the selected
 //   side's star state and flux are evaluated; E_K/rho_K = c_K^2/(g (g-1)) +
 //   |v_K|^2 / 2 and one reciprocal of (s_K - s_*) rho_K ds_K serve the star
-//   state, so a face costs six reciprocal(-square-root) evaluations.
+//   state, so a face costs six reciprocal(-square-root) evaluations; the
+//   tangential fluxes are the mass flux times the upwind side's tangential
+//   velocities (the star state carries them unchanged).
 template <typename R, int NT>
 __device__ __forceinline__ void hllc(const Gas<R>& gas, const R (&WL)[NT + 3], const R (&WR)[NT + 3],
                                      R (&F)[NT + 3]) {
@@ -199,44 +214,35 @@ __device__ __forceinline__ void hllc(const Gas<R>& gas, const R (&WL)[NT + 3], c
 
     const R rho = W[0], u = W[1], p = W[NC - 1];
     const R mu = rho * u;
-    R tsq = R(0);
-    R Uk[NC], Fk[NC];
-    Uk[0] = rho;
-    Uk[1] = mu;
     // tangential |t|^2 as a sum of rounded squares: symmetric in the
     // tangential components, so interchanging two axes is bitwise
+    R tsq = R(0);
 #pragma unroll
-    for (int k = 0; k < NT; ++k) {
-        Uk[2 + k] = rho * W[2 + k];
-        tsq = tsq + W[2 + k] * W[2 + k];
-    }
+    for (int k = 0; k < NT; ++k) tsq = tsq + W[2 + k] * W[2 + k];
     const R vsq = O::fma(u, u, tsq);
     const R E = O::fma(p, gas.inv_gm1, R(0.5) * rho * vsq);
-    Uk[NC - 1] = E;
-    Fk[0] = mu;
-    Fk[1] = O::fma(mu, u, p);
-#pragma unroll
-    for (int k = 0; k < NT; ++k) Fk[2 + k] = mu * W[2 + k];
-    Fk[NC - 1] = (E + p) * u;
 
     // star state chi (1, s_*, t, E/rho + (s_* - u)(s_* + p/(rho ds))),
-    // chi = rho ds / (s - s_*), with 1/(s - s_*) and 1/(rho ds) from one reciprocal
+    // chi = rho ds / (s - s_*), with 1/(s - s_*) and 1/(rho ds) from one
+    // reciprocal; F*_K = F_K + s_K (U*_K - U_K) for mass, normal momentum and
+    // energy (the upwind flux where no star state applies: there the star
+    // quantities may not be finite, so the choice is a select)
     const R t1 = sK - ss;
     const R q = O::rcp1(t1 * mK);
     const R chi = mK * (mK * q);
     const R p_m = p * (t1 * q);
     const R e_rho = O::fma(cK * cK, gas.inv_g_gm1, R(0.5) * vsq);
-    R Us[NC];
-    Us[0] = chi;
-    Us[1] = chi * ss;
+    const R f0 = O::fma(sK, chi - rho, mu);
+    const R f1 = O::fma(sK, chi * ss - mu, O::fma(mu, u, p));
+    const R f4 = O::fma(sK, chi * O::fma(ss - u, ss + p_m, e_rho) - E, (E + p) * u);
+    F[0] = star ? f0 : mu;
+    F[1] = star ? f1 : O::fma(mu, u, p);
+    F[NC - 1] = star ? f4 : (E + p) * u;
+    // the tangential velocities are carried by the mass flux: in the star
+    // regions U*_t = chi t and U_t = rho t give F_t = t (rho u + s_K (chi -
+    // rho)) = t F_0, and outside them F_t = rho u t = t F_0 as well
 #pragma unroll
-    for (int k = 0; k < NT; ++k) Us[2 + k] = chi * W[2 + k];
-    Us[NC - 1] = chi * O::fma(ss - u, ss + p_m, e_rho);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const R fs = O::fma(sK, Us[c] - Uk[c], Fk[c]);
-        F[c] = star ? fs : Fk[c];
-    }
+    for (int k = 0; k < NT; ++k) F[2 + k] = W[2 + k] * F[0];
 }
 
 // Flux through the face between cells w1 and w2 along kernel axis AX from the
@@ -258,8 +264,8 @@ __device__ __forceinline__ void face_flux(const Gas<R>& g, const R (&w0)[NDIM + 
             wl[c] = w1[c];
             wr[c] = w2[c];
         } else {
-            const R dj = minmod(w1[c] - w0[c], w2[c] - w1[c]);
-            const R dj1 = minmod(w2[c] - w1[c], w3[c] - w2[c]);
+            R dj, dj1;
+            Ops<R>::minmod2(w1[c] - w0[c], w2[c] - w1[c], w3[c] - w2[c], dj, dj1);
             wl[c] = Ops<R>::fma(R(0.5), dj, w1[c]);
             wr[c] = Ops<R>::fma(R(-0.5), dj1, w2[c]);
         }
@@ -308,8 +314,8 @@ __device__ __forceinline__ void face_flux_xy(const Gas<R>& g, bool yaxis, const 
             wl[c] = w1[c];
             wr[c] = w2[c];
         } else {
-            const R dj = minmod(w1[c] - w0[c], w2[c] - w1[c]);
-            const R dj1 = minmod(w2[c] - w1[c], w3[c] - w2[c]);
+            R dj, dj1;
+            Ops<R>::minmod2(w1[c] - w0[c], w2[c] - w1[c], w3[c] - w2[c], dj, dj1);
             wl[c] = Ops<R>::fma(R(0.5), dj, w1[c]);
             wr[c] = Ops<R>::fma(R(-0.5), dj1, w2[c]);
         }
@@ -959,7 +965,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const R d0 = w[1][c] - w[0][c], d1 = w[2][c] - w[1][c], d2 = w[3][c] - w[2][c];
-            const R s1 = minmod(d0, d1), s2 = minmod(d1, d2);
+            R s1, s2;
+            Ops<R>::minmod2(d0, d1, d2, s1, s2);
             wl[c] = FIRST ? w[1][c] : Ops<R>::fma(R(0.5), s1, w[1][c]);
             wr[c] = FIRST ? w[2][c] : Ops<R>::fma(R(-0.5), s2, w[2][c]);
             lz[c] = Ops<R>::fma(R(0.5), s2, w[2][c]);

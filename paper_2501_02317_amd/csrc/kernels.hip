@@ -1183,8 +1183,10 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
             double unew[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                double acc = 0.0;
-                acc = acc + lam0 * ((double)sFx[bu][c][ly][lx] - (double)sFx[bu][c][ly][lx + 1]);
+                // the axis terms summed in x, y, z order from the first one
+                // (a sum of two rounded products is the same either way round,
+                // so interchanging two axes leaves the update bitwise unchanged)
+                double acc = lam0 * ((double)sFx[bu][c][ly][lx] - (double)sFx[bu][c][ly][lx + 1]);
                 if (HY)
                     acc = acc + lam1 * ((double)sFy[bu][HY ? c : 0][HY ? ly : 0][lx] -
                                         (double)sFy[bu][HY ? c : 0][HY ? ly + 1 : 0][lx]);

@@ -16,7 +16,10 @@ events on the launch stream inside the timed region.  cpu_baseline = the
 FP64 oracle on the host cores for one Heun step of the same 256^3 state.
 by_precision.*.host_inclusive = the same run with the state handed over in
 host memory (upload over PCIe, the steps, download), measured after the timed
-region; it is never the value.
+region; it is never the value.  Further legs (each with a --no-* switch): the
+van Leer integrator, the mesh split into blocks, a statically refined mesh,
+the paper's Table 1 grid (2-D 4096 x 1024, with the paper's own figures for
+context), the 512-mesh batch and the serving loop.
 """
 import argparse
 import hashlib
@@ -48,6 +51,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--no-blocks", action="store_true", help="skip the multi-block leg")
     ap.add_argument("--no-smr", action="store_true", help="skip the static-refinement leg")
+    ap.add_argument("--no-paper-grid", action="store_true",
+                    help="skip the 2-D 4096x1024 leg on the grid of the paper's Table 1")
     ap.add_argument("--smr-only", action="store_true",
                     help="run only the static-refinement leg and print its record (for kernel traces)")
     ap.add_argument("--batch-count", type=int, default=512)
@@ -257,6 +262,39 @@ def run_smr(H, wl, steps, warmup):
     return {"value": v, "ms_per_step": ms, "leaves": nl, "cells": cells, "precision": "mixed",
             "split_value": v0, "split_ms_per_step": ms0, "split_cells": cells0,
             "config": "128^3 level 0 in 4x4x4 blocks of 32^3, central 2x2x2 refined, smooth Mach-1 field"}
+
+
+# The paper's own throughput on its Table 1 workload (2-D double Mach
+# reflection on a 4096 x 1024 grid, Sec. 4.3), in 1e8 cells per second for
+# one full step, by device: (single, mixed, double).  Context only: other
+# hardware, and that run has reflecting and time-dependent boundaries where
+# this leg's box is periodic.
+PAPER_TABLE1 = {
+    "RTX 4090 (CUDA)": (21.0, 16.0, 2.9),
+    "Tesla A100 (CUDA)": (16.0, 14.0, 8.3),
+    "RX 7900 XTX (HIP)": (8.9, 7.7, 2.8),
+    "MI100 (HIP)": (8.2, 6.8, 3.0),
+}
+
+
+def run_paper_grid(H, wl, steps, warmup, tune=True):
+    """The paper's Table 1 grid, 4096 x 1024 square cells on [0,4] x [0,1],
+    gamma = 1.4, CFL 0.4: a seeded periodic random field (Mach 1) in place of
+    the double Mach reflection, both precisions, autotuned tiles."""
+    import dataclasses
+    case = wl.turbulence_3d(n=(4096, 1024), mach=1.0, seed=601, gamma=1.4, cfl=0.4, steps=steps)
+    case = dataclasses.replace(case, hi=(4.0, 1.0))
+    out = {"grid": [4096, 1024], "cells": case.ncells, "data": "synthetic periodic random field, Mach 1",
+           "alg_bytes_per_cell_update": bytes_per_update(2)}
+    for name, prec in (("mixed", H.MIXED), ("fp64", H.FP64)):
+        r = run_precision(H, case, prec, steps, warmup, None, tune)
+        out[name] = {"value": r["rate"], "ms_per_step": r["ms_per_step"], "roofline_frac": r["frac"],
+                     "tiles": r["tiles"]}
+        print(f"[bench] paper grid {name}: {r['rate']:.3e} cell-updates/s, {r['ms_per_step']:.3f} ms/step",
+              file=sys.stderr, flush=True)
+    out["paper_table1_1e8_cells_per_s"] = {k: {"single": v[0], "mixed": v[1], "double": v[2]}
+                                           for k, v in PAPER_TABLE1.items()}
+    return out
 
 
 def run_serving(count, calib):
@@ -500,6 +538,8 @@ def main():
         out["smr"] = run_smr(H, wl, args.steps, args.warmup)
         print(f"[bench] smr: {out['smr']['value']:.3e} cell-updates/s ({out['smr']['leaves']} leaves), "
               f"split mesh {out['smr']['split_value']:.3e}", file=sys.stderr, flush=True)
+    if not args.no_paper_grid and "mixed" in res:
+        out["paper_grid"] = run_paper_grid(H, wl, args.steps, args.warmup, not args.no_tune)
     if not args.no_batch:
         print("[bench] batched 2-D workload ...", file=sys.stderr, flush=True)
         out["batch"] = run_batch(H, wl, args.batch_count, 300, H.MIXED)

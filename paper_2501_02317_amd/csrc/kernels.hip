@@ -883,7 +883,9 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
     constexpr int NB = ONE ? 2 : 1;
     constexpr int RS = ONE ? 4 : 3;  // ring slots: planes k-1 .. k+2 live at once
     __shared__ double sRaw[RING ? RS : 1][RING ? NC : 1][RING ? NT : 1];
-    __shared__ R sW[NB][NC][TY + 4][TX + 4];
+    // rows of the W tile: in 1-D and 2-D a tile is one row (row offset RO)
+    constexpr int RO = HY ? 0 : -2;
+    __shared__ R sW[NB][NC][HY ? TY + 4 : 1][TX + 4];
     using FT = R;
     __shared__ FT sFx[NB][NC][TY][TX + 1];
     __shared__ FT sFy[NB][HY ? NC : 1][HY ? TY + 1 : 1][TX];
@@ -1066,7 +1068,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
                 in_to_w<NDIM, R, PRIM_IN>(gm1, u, -1, VM_NONE, wc, bad);
             }
 #pragma unroll
-            for (int c = 0; c < NC; ++c) sW[bw][c][ly + 2][lx + 2] = wc[c];
+            for (int c = 0; c < NC; ++c) sW[bw][c][ly + 2 + RO][lx + 2] = wc[c];
         }
         if (live && hact) {
             if constexpr (PRIO) __builtin_amdgcn_s_setprio(2);
@@ -1077,7 +1079,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
             // not checked here: every cell is checked by the tile that owns it
             in_to_w<NDIM, R, PRIM_IN, false>(gm1, uhalo, halo_vm ? hvax : -1, hvm, wh, bad);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) sW[bw][c][hy + 2][hx + 2] = wh[c];
+            for (int c = 0; c < NC; ++c) sW[bw][c][hy + 2 + RO][hx + 2] = wh[c];
             if (HALO_PF && k + 1 < z1) load_halo(k + 1, uhalo);
         }
         __syncthreads();
@@ -1088,10 +1090,10 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
                 R w0[NC], w1[NC], w2[NC], w3[NC], F[NC];
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                    w0[c] = sW[bw][c][ly + 2][lx];
-                    w1[c] = sW[bw][c][ly + 2][lx + 1];
-                    w2[c] = sW[bw][c][ly + 2][lx + 2];
-                    w3[c] = sW[bw][c][ly + 2][lx + 3];
+                    w0[c] = sW[bw][c][ly + 2 + RO][lx];
+                    w1[c] = sW[bw][c][ly + 2 + RO][lx + 1];
+                    w2[c] = sW[bw][c][ly + 2 + RO][lx + 2];
+                    w3[c] = sW[bw][c][ly + 2 + RO][lx + 3];
                 }
                 face_flux<NDIM, 0, R, FIRST>(gr, w0, w1, w2, w3, F);
 #pragma unroll
@@ -1101,10 +1103,10 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
                 R w0[NC], w1[NC], w2[NC], w3[NC], F[NC];
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                    w0[c] = sW[bw][c][ly][lx + 2];
-                    w1[c] = sW[bw][c][ly + 1][lx + 2];
-                    w2[c] = sW[bw][c][ly + 2][lx + 2];
-                    w3[c] = sW[bw][c][ly + 3][lx + 2];
+                    w0[c] = sW[bw][c][HY ? ly : 0][lx + 2];
+                    w1[c] = sW[bw][c][HY ? ly + 1 : 0][lx + 2];
+                    w2[c] = sW[bw][c][ly + 2 + RO][lx + 2];
+                    w3[c] = sW[bw][c][HY ? ly + 3 : 0][lx + 2];
                 }
                 face_flux<NDIM, 1, R, FIRST>(gr, w0, w1, w2, w3, F);
 #pragma unroll
@@ -1124,10 +1126,10 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
                     const int dr = yaxis ? 1 : 0, dc = yaxis ? 0 : 1;
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
-                        w0[c] = sW[bw][c][r0][c0];
-                        w1[c] = sW[bw][c][r0 + dr][c0 + dc];
-                        w2[c] = sW[bw][c][r0 + 2 * dr][c0 + 2 * dc];
-                        w3[c] = sW[bw][c][r0 + 3 * dr][c0 + 3 * dc];
+                        w0[c] = sW[bw][c][HY ? r0 : 0][c0];
+                        w1[c] = sW[bw][c][HY ? r0 + dr : 0][c0 + dc];
+                        w2[c] = sW[bw][c][HY ? r0 + 2 * dr : 0][c0 + 2 * dc];
+                        w3[c] = sW[bw][c][HY ? r0 + 3 * dr : 0][c0 + 3 * dc];
                     }
                     face_flux_xy<R, FIRST>(gr, yaxis, w0, w1, w2, w3, F);
                     if (yaxis) {
@@ -1140,10 +1142,10 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, int b, int blk) {
                 } else {
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
-                        w0[c] = sW[bw][c][e + 2][TX];
-                        w1[c] = sW[bw][c][e + 2][TX + 1];
-                        w2[c] = sW[bw][c][e + 2][TX + 2];
-                        w3[c] = sW[bw][c][e + 2][TX + 3];
+                        w0[c] = sW[bw][c][e + 2 + RO][TX];
+                        w1[c] = sW[bw][c][e + 2 + RO][TX + 1];
+                        w2[c] = sW[bw][c][e + 2 + RO][TX + 2];
+                        w3[c] = sW[bw][c][e + 2 + RO][TX + 3];
                     }
                     face_flux<NDIM, 0, R, FIRST>(gr, w0, w1, w2, w3, F);
 #pragma unroll

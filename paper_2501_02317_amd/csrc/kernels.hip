@@ -728,18 +728,21 @@ struct StageOccupancy {
     // Input ring: the raw input values of a cell, read for its conversion
     // when its plane enters the z stencil, are kept in a three-plane LDS ring
     // until the update of that plane instead of being read again.  It pays
-    // in the mixed stage 2, whose update also reads U^n: there the ring's
-    // LDS sets the occupancy to three work-groups per CU, which the
-    // register use of that kernel allows without spills.
-    static constexpr bool kRing = sizeof(R) == 4 && MODE == MODE_STAGE2 && (NDIM == 3 || kRing2D);
+    // in the mixed stages (measured at 256^3 at the sustained clock: stage 1
+    // 392 -> 371 us with 32 x 8 tiles in place of 32 x 16 and one barrier
+    // per plane): there the ring's LDS sets the occupancy to three
+    // work-groups per CU, which their register use allows without spills.
+    // The FP64 stage 1 loses a wave per SIMD to it and does without.
+    static constexpr bool kRing =
+        sizeof(R) == 4 && (MODE == MODE_STAGE2 || MODE == MODE_STAGE1) && (NDIM == 3 || kRing2D);
     // occupancy range (waves per SIMD) the compiler aims for: at least
     // kWaves (its register budget), at most kWavesMax (8: no bound)
     static constexpr int kWaves =
         sizeof(R) == 4 ? ((kRing || (NDIM == 3 && MODE == MODE_STAGE1)) ? 3 : 4) : 2;
     static constexpr int kWavesMax = 8;
     // One barrier per plane (double-buffered W and flux tiles): measured
-    // faster for the mixed stage 1 and the FP64 stage 2; the mixed stage 2
-    // would need a fourth ring plane and lose a work-group per CU.
+    // faster for the FP64 stage 2; the mixed stages would need a fourth ring
+    // plane and lose a work-group per CU.
     // The marching loop unrolled by two with two prefetch buffers, so that
     // the prefetched plane is not copied between loop-carried registers
     // (which makes the compiler wait for the load in the iteration that
@@ -748,14 +751,12 @@ struct StageOccupancy {
     static constexpr bool kUnroll2 = NDIM == 3 && sizeof(R) == 4 && MODE == MODE_STAGE2;
     static constexpr bool kOneBarrier =
         (NDIM == 3 || kOne2D) &&
-        ((sizeof(R) == 4 && MODE == MODE_STAGE1) || (sizeof(R) == 8 && MODE == MODE_STAGE2));
+        sizeof(R) == 8 && MODE == MODE_STAGE2;
     // The raw halo cell of the next plane loaded one iteration ahead, so the
     // barrier after the plane's W does not wait for it: ten more registers.
     // Measured at 256^3: the Heun stage 2 holds them without losing
     // occupancy (mixed 598 -> 556 us; FP64 unchanged); the mixed stage 1
-    // gains about 2 % even at three waves per SIMD instead of four (its LDS
-    // already limits it to two 512-thread work-groups per CU); the FP64
-    // stage 1 loses 6 % and does without.
+    // gains about 2 %; the FP64 stage 1 loses 6 % and does without.
     static constexpr bool kHaloPrefetch =
         NDIM == 3 && (MODE == MODE_STAGE2 || (MODE == MODE_STAGE1 && sizeof(R) == 4));
     // U^n of the next updated plane loaded during this plane's update,
@@ -2125,10 +2126,10 @@ Tile default_tile(const Geo& g, int precision, int mode) {
     } else if (g.ndim == 3) {
         // From a sweep at 256^3: 32 x 16 halves the share of halo cells and
         // extra faces where the occupancy allows it; 32 x 8 where a larger
-        // work-group would cost occupancy (the mixed Heun stage 2 beside its
-        // input ring; the FP64 kernels other than the double-buffered Heun
+        // work-group would cost occupancy (the mixed Heun stages beside their
+        // input rings; the FP64 kernels other than the double-buffered Heun
         // stage 2).
-        const bool narrow = precision == 1 ? mode == MODE_STAGE2 : mode != MODE_STAGE2;
+        const bool narrow = precision == 1 ? (mode == MODE_STAGE2 || mode == MODE_STAGE1) : mode != MODE_STAGE2;
         t.tx = 32;
         t.ty = narrow ? 8 : 16;
     } else if (g.ndim == 2) {

@@ -1,7 +1,8 @@
 """Whole-run parity at the benchmark sizes: 128^3 Mach-1 for 200 steps (FP64)
-and 256^3 Mach-2 for 100 steps (FP64 and mixed), GPU against the FP64
-oracle run on the host cores (about four minutes of oracle time at 16
-threads).  The oracle prints a progress line every ten steps straight to the
+and 256^3 Mach-2 for 100 steps (FP64 and mixed), and the van Leer integrator
+(Sec. 3.3) on 128^3 Mach-1 for 100 steps (FP64 and mixed), GPU against the
+FP64 oracle run on the host cores (about four and a half minutes of oracle
+time at 16 threads).  The oracle prints a progress line every ten steps straight to the
 terminal (past pytest's output capture), so the run is never silent for long.
 """
 import os
@@ -26,17 +27,20 @@ def H():
     return hydro
 
 
+# name: (workload, integrator)
 CASES = {
-    "c2_128_mach1_200": lambda: wl.turbulence_3d(n=128, mach=1.0, seed=201, steps=200, cfl=0.3),
-    "c3_256_mach2_100": lambda: wl.turbulence_3d(n=256, mach=2.0, seed=301, steps=100, cfl=0.3),
+    "c2_128_mach1_200": (lambda: wl.turbulence_3d(n=128, mach=1.0, seed=201, steps=200, cfl=0.3), 0),
+    "c3_256_mach2_100": (lambda: wl.turbulence_3d(n=256, mach=2.0, seed=301, steps=100, cfl=0.3), 0),
+    "vl2_128_mach1_100": (lambda: wl.turbulence_3d(n=128, mach=1.0, seed=211, steps=100, cfl=0.3), 1),
 }
 _oracle_cache = {}
 
 
 def oracle_result(name):
     if name not in _oracle_cache:
-        c = CASES[name]()
-        m = oracle_mesh(c)
+        make, integ = CASES[name]
+        c = make()
+        m = oracle_mesh(c, integ)
         U0 = O.prim_to_cons(m, c.W)
         t0 = time.perf_counter()
         # in chunks of 10 steps (each dt comes from the state it starts from,
@@ -58,12 +62,14 @@ def oracle_result(name):
 
 @pytest.mark.parametrize("name,precision,tol", [("c2_128_mach1_200", 0, 1e-12),
                                                 ("c3_256_mach2_100", 0, 1e-12),
-                                                ("c3_256_mach2_100", 1, 1e-5)])
+                                                ("c3_256_mach2_100", 1, 1e-5),
+                                                ("vl2_128_mach1_100", 0, 1e-12),
+                                                ("vl2_128_mach1_100", 1, 1e-5)])
 def test_full_run_against_oracle(H, capsys, name, precision, tol):
     with capsys.disabled():
         c, m, U0, U_o, t_o, s_o = oracle_result(name)
     say("full run", name, precision)
-    h = gpu_mesh(c, precision)
+    h = gpu_mesh(c, precision, CASES[name][1])
     h.step_auto(c.steps)
     U = h.get_state()
     t, s = h.time(), h.steps_done()

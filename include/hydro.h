@@ -349,7 +349,15 @@ const char* hydro_strerror(int status);
  * and run limit (hydro_set_run_limit), and members that reached it are
  * skipped.  With use_graph != 0 and a non-default stream, the nsteps-step
  * sequence is captured once into a HIP graph and replayed (recaptured when
- * nsteps changes).  hydro_batch_step is async; read results through the
+ * nsteps changes).  Without a graph, and when the stream is not being
+ * captured, a batch of several groups spreads them over its stream and up
+ * to three more streams of its own (made at the first such step, freed by
+ * hydro_batch_destroy): each group's stages and its members' time / dt
+ * update follow one another on one stream, step after step, forked from the
+ * members' stream at the call and joined back to it before the call
+ * returns, so work enqueued on that stream afterwards sees every step.
+ * The device workspace also holds the member order by group.
+ * hydro_batch_step is async; read results through the
  * member handles after synchronising the stream.  Results equal those of
  * stepping each member alone with hydro_step_auto.
  */

@@ -1527,13 +1527,23 @@ struct hydro_batch_ctx {
     std::vector<hydro_t> members;
     hipStream_t stream;
     MeshDesc* d_desc;  // descriptor table in the caller's workspace
+    int* d_order;      // member indices in group order
     int2* d_blk;       // work-group table, grouped
     struct Group {
         int ndim, precision, integrator;
         Tile tile;
         int blk_off, nblk;
+        int mem_off, nmem;  // the group's members: d_order[mem_off .. mem_off + nmem)
+        double cells;       // cells of its members
     };
     std::vector<Group> groups;
+    // Direct launches spread the groups over the batch's stream and up to
+    // kBatchSideStreams more (group_stream[g]: 0 the batch's stream, i > 0
+    // side[i - 1]), forked from and joined back to the batch's stream by events.
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev_join;
+    hipEvent_t ev_fork;
+    std::vector<int> group_stream;
     hipGraph_t graph;
     hipGraphExec_t exec;
     int graph_steps;
@@ -1547,9 +1557,14 @@ namespace {
 
 struct BatchPlan {
     std::vector<MeshDesc> desc;
+    std::vector<int> order;
     std::vector<int2> blk;
     std::vector<hydro_batch_ctx::Group> groups;
 };
+
+// Three more streams: with the batch's own, one per hardware queue of a
+// process at HIP's default queue count.
+constexpr int kBatchSideStreams = 3;
 
 // Tile rules of the batch autotuner for members of one or two dimensions:
 // a row width for every such member (0: the member's own) and a chunk length
@@ -1604,9 +1619,15 @@ bool plan_batch(int n, const hydro_t* members, BatchPlan& P, int rule = 0) {
             g.tile = tiles[i];
             g.blk_off = (int)P.blk.size();
             g.nblk = 0;
+            g.mem_off = idx;
+            g.nmem = 0;
+            g.cells = 0.0;
             P.groups.push_back(g);
         }
         const MeshDesc& d = P.desc[i];
+        P.order.push_back(i);
+        P.groups.back().nmem += 1;
+        P.groups.back().cells += (double)d.geo.ncells;
         const long long nb = (long long)d.tiles_x * d.tiles_y * d.chunks_z;
         if (nb > (1ll << 28) || (long long)P.blk.size() + nb > (1ll << 30)) return false;
         for (int b = 0; b < (int)nb; ++b) P.blk.push_back(make_int2(i, b));
@@ -1615,9 +1636,71 @@ bool plan_batch(int n, const hydro_t* members, BatchPlan& P, int rule = 0) {
     return true;
 }
 
+// Workspace: descriptors, member order, work-group table, status table.
 size_t batch_bytes(const BatchPlan& P) {
-    return align_up(P.desc.size() * sizeof(MeshDesc)) + align_up(P.blk.size() * sizeof(int2)) +
-           align_up(P.desc.size() * 3 * sizeof(unsigned long long));
+    return align_up(P.desc.size() * sizeof(MeshDesc)) + align_up(P.desc.size() * sizeof(int)) +
+           align_up(P.blk.size() * sizeof(int2)) + align_up(P.desc.size() * 3 * sizeof(unsigned long long));
+}
+
+// Groups onto streams, largest first onto the least loaded (by cells), over
+// as many streams as there are groups, at most 1 + kBatchSideStreams.
+void assign_group_streams(hydro_batch_t b) {
+    const int ng = (int)b->groups.size();
+    const int ns = std::min(ng, 1 + kBatchSideStreams);
+    std::vector<int> by(ng);
+    for (int g = 0; g < ng; ++g) by[g] = g;
+    std::stable_sort(by.begin(), by.end(), [&](int x, int y) { return b->groups[x].cells > b->groups[y].cells; });
+    std::vector<double> load(ns > 0 ? ns : 1, 0.0);
+    b->group_stream.assign(ng, 0);
+    for (int g : by) {
+        int best = 0;
+        for (int k = 1; k < ns; ++k)
+            if (load[k] < load[best]) best = k;
+        b->group_stream[g] = best;
+        load[best] += b->groups[g].cells;
+    }
+}
+
+void side_streams_free(hydro_batch_t b) {
+    for (hipEvent_t ev : b->ev_join) (void)hipEventDestroy(ev);
+    for (hipStream_t st : b->side) (void)hipStreamDestroy(st);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    b->ev_join.clear();
+    b->side.clear();
+    b->ev_fork = nullptr;
+}
+
+// The side streams and events, made on first use (default priority, not
+// synchronising with the legacy default stream).  On failure none are kept
+// and the batch launches on its own stream.
+bool side_streams_ready(hydro_batch_t b) {
+    if (!b->side.empty()) return true;
+    hipError_t e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+    if (e != hipSuccess) b->ev_fork = nullptr;
+    for (int i = 0; i < kBatchSideStreams && e == hipSuccess; ++i) {
+        hipStream_t st = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess) break;
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(st);
+            break;
+        }
+        b->side.push_back(st);
+        b->ev_join.push_back(ev);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        side_streams_free(b);
+        return false;
+    }
+    return true;
+}
+
+bool stream_capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
 }
 
 bool members_ok(int n, const hydro_t* members) {
@@ -1644,7 +1727,38 @@ hipError_t enqueue_batch_step(hydro_batch_t b) {
         if (e == hipSuccess)
             e = launch_stage_batch(g.ndim, g.precision, g.integrator == HYDRO_VL2 ? MODE_VL2_CORR : MODE_STAGE2,
                                    g.tile, b->d_desc, b->d_blk + g.blk_off, g.nblk, b->stream);
-    if (e == hipSuccess) e = launch_ctrl_batch(b->d_desc, (int)b->members.size(), b->stream);
+    if (e == hipSuccess) e = launch_ctrl_batch(b->d_desc, nullptr, (int)b->members.size(), b->stream);
+    return e;
+}
+
+// nsteps batched steps with the groups spread over streams: each group's
+// stage 1, stage 2 and members' time / dt update on its stream, step after
+// step (a member's steps depend on no other group), forked from the batch's
+// stream and joined back to it at the end.  The same results as
+// enqueue_batch_step nsteps times.
+hipError_t enqueue_batch_steps_streams(hydro_batch_t b, int nsteps) {
+    hipError_t e = hipEventRecord(b->ev_fork, b->stream);
+    const int nside = (int)b->side.size();
+    for (int i = 0; i < nside && e == hipSuccess; ++i) e = hipStreamWaitEvent(b->side[i], b->ev_fork, 0);
+    for (int s = 0; s < nsteps && e == hipSuccess; ++s)
+        for (size_t gi = 0; gi < b->groups.size() && e == hipSuccess; ++gi) {
+            const auto& g = b->groups[gi];
+            const int k = b->group_stream[gi];
+            hipStream_t st = k > 0 && k <= nside ? b->side[k - 1] : b->stream;
+            const bool vl2 = g.integrator == HYDRO_VL2;
+            e = launch_stage_batch(g.ndim, g.precision, vl2 ? MODE_VL2_PRED : MODE_STAGE1, g.tile, b->d_desc,
+                                   b->d_blk + g.blk_off, g.nblk, st);
+            if (e == hipSuccess)
+                e = launch_stage_batch(g.ndim, g.precision, vl2 ? MODE_VL2_CORR : MODE_STAGE2, g.tile, b->d_desc,
+                                       b->d_blk + g.blk_off, g.nblk, st);
+            if (e == hipSuccess) e = launch_ctrl_batch(b->d_desc, b->d_order + g.mem_off, g.nmem, st);
+        }
+    // joined whatever happened above, so no side-stream work outlives a call
+    for (int i = 0; i < nside; ++i) {
+        hipError_t x = hipEventRecord(b->ev_join[i], b->side[i]);
+        if (x == hipSuccess) x = hipStreamWaitEvent(b->stream, b->ev_join[i], 0);
+        if (e == hipSuccess) e = x;
+    }
     return e;
 }
 
@@ -1684,8 +1798,11 @@ int hydro_batch_create(int n, const hydro_t* members, void* d_workspace, size_t 
     b->members.assign(members, members + n);
     b->stream = members[0]->stream;
     b->d_desc = (MeshDesc*)d_workspace;
-    b->d_blk = (int2*)((char*)d_workspace + align_up(P.desc.size() * sizeof(MeshDesc)));
+    b->d_order = (int*)((char*)d_workspace + align_up(P.desc.size() * sizeof(MeshDesc)));
+    b->d_blk = (int2*)((char*)b->d_order + align_up(P.desc.size() * sizeof(int)));
     b->groups = P.groups;
+    b->ev_fork = nullptr;
+    assign_group_streams(b);
     b->graph = nullptr;
     b->exec = nullptr;
     b->graph_steps = 0;
@@ -1699,6 +1816,9 @@ int hydro_batch_create(int n, const hydro_t* members, void* d_workspace, size_t 
     b->h_status.assign((size_t)n * 3, 0ull);
     hipError_t e = hipMemcpyAsync(b->d_desc, P.desc.data(), P.desc.size() * sizeof(MeshDesc),
                                   hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_order, P.order.data(), P.order.size() * sizeof(int), hipMemcpyHostToDevice,
+                           b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_blk, P.blk.data(), P.blk.size() * sizeof(int2), hipMemcpyHostToDevice,
                            b->stream);
@@ -1738,6 +1858,11 @@ int hydro_batch_step(hydro_batch_t b, int nsteps) {
             }
         }
         if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
+    } else if (e == hipSuccess && b->groups.size() > 1 && !stream_capturing(b->stream) &&
+               side_streams_ready(b)) {
+        // (a caller's capture of the forked form is not attempted: the
+        // refined-mesh step avoids it for the same reason)
+        e = enqueue_batch_steps_streams(b, nsteps);
     } else {
         for (int s = 0; s < nsteps && e == hipSuccess; ++s) e = enqueue_batch_step(b);
     }
@@ -1768,10 +1893,14 @@ int hydro_batch_autotune(hydro_batch_t b, int steps_per_rule, int* rule_out, dou
         hipError_t x = hipMemcpyAsync(b->d_desc, P.desc.data(), P.desc.size() * sizeof(MeshDesc),
                                       hipMemcpyHostToDevice, b->stream);
         if (x == hipSuccess)
+            x = hipMemcpyAsync(b->d_order, P.order.data(), P.order.size() * sizeof(int), hipMemcpyHostToDevice,
+                               b->stream);
+        if (x == hipSuccess)
             x = hipMemcpyAsync(b->d_blk, P.blk.data(), P.blk.size() * sizeof(int2), hipMemcpyHostToDevice,
                                b->stream);
         if (x == hipSuccess) x = hipStreamSynchronize(b->stream);  // P's host data in use until here
         b->groups = P.groups;
+        assign_group_streams(b);
         return x;
     };
     for (hydro_t h : b->members)
@@ -1856,6 +1985,7 @@ int hydro_batch_destroy(hydro_batch_t b) {
     if (!b) return HYDRO_E_INVAL;
     if (!b->broken) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
+    side_streams_free(b);
     delete b;
     return HYDRO_OK;
 }

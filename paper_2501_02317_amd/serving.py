@@ -139,8 +139,14 @@ class Server:
         self.pool = torch.empty(hbm_bytes, dtype=torch.uint8, device=self.device)
         self.arena = Arena(hbm_bytes)
         self.stream = torch.cuda.Stream(device=self.device)
+        self.setup_stream = torch.cuda.Stream(device=self.device)
         self.K = steps_per_iter
         self.max_members = max_members
+        # host time for request set-up per iteration: short while the device
+        # is idle, longer while it steps the resident requests (set-up enqueues
+        # its work without waiting for the stream)
+        self.idle_admit_s = 0.02
+        self.busy_admit_s = 0.05
         self.keep = set(keep_results)
         self.iterations = 0
 
@@ -154,9 +160,14 @@ class Server:
         wsb = H.workspace_bytes(cfg)
         ws = self.pool[off: off + wsb]
         h = H.Hydro(nn, r.gamma, r.cfl, precision=r.precision, stream=self.stream, workspace=ws)
-        with torch.cuda.stream(self.stream):
+        # the initial state on the set-up stream, beside the steps enqueued on
+        # the batch's streams; its conversion on the batch's stream waits for it
+        with torch.cuda.stream(self.setup_stream):
             W = wl.random_field_device(r.ndim, r.n, r.mach, r.gamma, r.seed, kmax=r.kmax,
                                        device=self.device)
+        ready = torch.cuda.Event()
+        ready.record(self.setup_stream)
+        self.stream.wait_event(ready)
         h.set_primitive_device(W)
         h.set_run_limit(r.steps, 0.0)
         r.admitted = now
@@ -168,10 +179,11 @@ class Server:
 
         One iteration: (re)build the batch when its membership changed, enqueue
         K batched steps, admit the requests that arrived meanwhile (their
-        set-up is host work that overlaps the steps on the device; their
-        initial states are enqueued behind the steps), then read every
-        member's status (the one synchronisation) and retire the finished
-        ones.  Host time per phase is accumulated in self.phase_s."""
+        set-up is host work that overlaps the steps on the device, for at
+        most busy_admit_s; their initial states are generated on a stream of
+        their own beside the steps, and converted behind the steps), then
+        read every member's status (the one synchronisation) and retire the
+        finished ones.  Host time per phase is accumulated in self.phase_s."""
         pending = collections.deque(sorted(requests, key=lambda q: q.arrival))
         total, finished, next_log = len(pending), 0, log_every
         queue = collections.deque()
@@ -181,11 +193,15 @@ class Server:
         ph = self.phase_s = collections.defaultdict(float)
         start = time.perf_counter()
 
-        def admit(now):
+        def admit(now, limit_s=None):
+            # limit_s: host time after which no further request is set up in
+            # this call (the device is waiting for work)
             t = time.perf_counter()
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
             while queue and len(active) + len(joining) < self.max_members:
+                if limit_s is not None and joining and time.perf_counter() - t > limit_s:
+                    break
                 m = self._admit(queue[0], now)
                 if m is None:
                     break
@@ -198,7 +214,9 @@ class Server:
             if time_limit is not None and now > time_limit:
                 break
             if not active and not joining:
-                admit(now)
+                # the device is idle: start it on the first requests, and set
+                # up the others while it steps them
+                admit(now, self.idle_admit_s)
                 if not joining:
                     if pending:
                         time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - start)))
@@ -214,7 +232,7 @@ class Server:
             t = time.perf_counter()
             batch.step(self.K)
             ph["enqueue"] += time.perf_counter() - t
-            admit(time.perf_counter() - start)          # overlaps the steps
+            admit(time.perf_counter() - start, self.busy_admit_s)   # overlaps the steps
             t = time.perf_counter()
             done, steps, flags = batch.status()        # synchronises the stream
             ph["wait"] += time.perf_counter() - t

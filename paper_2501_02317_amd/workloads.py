@@ -307,16 +307,23 @@ def random_field_device(ndim, n, mach, gamma, seed, kmax=16, sigma=0.1, modes=48
         k = cand[pick]
         a = kn[pick] ** s * rng.standard_normal(modes)
         ph = rng.uniform(0.0, 2 * np.pi, modes)
+        # the mode table (k, amplitude, phase) in one copy that does not wait
+        # for the stream (from page-locked memory on a GPU)
+        tab = torch.from_numpy(np.concatenate([k.astype(np.float64), a[:, None], ph[:, None]], axis=1))
+        if torch.device(device).type == "cuda":
+            tab = tab.pin_memory().to(device, non_blocking=True)
+        # 2 pi k_d x_d of every mode along each axis, then the modes eight
+        # at a time: phase plus the axis terms, cosine, amplitude, summed
+        axis = [(2 * np.pi) * (tab[:, d].reshape(modes, 1) * x.view(1, n)) for d in range(ndim)]
         out = torch.zeros((n,) * ndim, device=device, dtype=torch.float64)
         for c0 in range(0, modes, 8):
-            kk = torch.as_tensor(k[c0:c0 + 8], dtype=torch.float64, device=device)
-            m = kk.shape[0]
-            arg = torch.as_tensor(ph[c0:c0 + 8], dtype=torch.float64, device=device).view(m, *[1] * ndim)
+            m = min(8, modes - c0)
+            arg = tab[c0:c0 + m, ndim + 1].reshape(m, *[1] * ndim)
             for d in range(ndim):
                 shp = [m] + [1] * ndim
                 shp[1 + d] = n
-                arg = arg + (2 * np.pi) * (kk[:, d].view(m, 1) * x.view(1, n)).view(shp)
-            amp = torch.as_tensor(a[c0:c0 + 8], dtype=torch.float64, device=device).view(m, *[1] * ndim)
+                arg = arg + axis[d][c0:c0 + m].view(shp)
+            amp = tab[c0:c0 + m, ndim].reshape(m, *[1] * ndim)
             out += (amp * torch.cos(arg)).sum(0)
         return out
 

@@ -60,12 +60,15 @@ def run_batch(H, cases, nsteps, use_graph, calls=1):
     return outs, times, steps, info
 
 
-def test_batch_equals_each_mesh_alone(H):
+@pytest.mark.parametrize("use_graph", [True, False], ids=["graph", "streams"])
+def test_batch_equals_each_mesh_alone(H, use_graph):
+    """Captured (one stream), or launched directly with the groups spread
+    over the batch's streams."""
     import torch
     cases = member_cases()
-    say("batch vs alone")
-    outs, times, steps, info = run_batch(H, cases, 16, use_graph=True)
-    assert info["groups"] >= 4 and info["graph"]
+    say("batch vs alone", use_graph)
+    outs, times, steps, info = run_batch(H, cases, 16, use_graph=use_graph)
+    assert info["groups"] >= 4 and info["graph"] == use_graph
     for (c, prec, ks, te), U, t, k in zip(cases, outs[0], times, steps):
         s = torch.cuda.Stream()
         h = make(H, c, prec, s)

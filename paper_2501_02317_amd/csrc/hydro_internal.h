@@ -161,9 +161,8 @@ hipError_t launch_stage_batch(int ndim, int precision, int mode, const Tile& til
                               const int2* blk, int nblk, hipStream_t s);
 // (done, flags, steps) of members [0, n) of a descriptor table into out[3 i ..].
 hipError_t launch_status_gather(const MeshDesc* d, int n, unsigned long long* out, hipStream_t s);
-// CTRL_FINALIZE_STEP for members order[0 .. n) of a descriptor table
-// (members [0, n) when order is null).
-hipError_t launch_ctrl_batch(const MeshDesc* d, const int* order, int n, hipStream_t s);
+// CTRL_FINALIZE_STEP for members [0, n) of a descriptor table.
+hipError_t launch_ctrl_batch(const MeshDesc* d, int n, hipStream_t s);
 hipError_t launch_dt(const Geo& g, const double* U, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_ctrl(Ctrl* c, int op, double a0, double a1, double cfl, hipStream_t s);
 hipError_t launch_totals(const Geo& g, const double* U, double* partials, int nparts, Ctrl* ctrl,

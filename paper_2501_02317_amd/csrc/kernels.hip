@@ -1405,14 +1405,9 @@ __global__ void status_gather_kernel(const MeshDesc* __restrict__ d, int n, unsi
     }
 }
 
-// Members order[0 .. n) of a batch (all members in table order without an
-// order table).
-__global__ void ctrl_batch_kernel(const MeshDesc* __restrict__ d, const int* __restrict__ order, int n) {
+__global__ void ctrl_batch_kernel(const MeshDesc* __restrict__ d, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        const int m = order ? order[i] : i;
-        finalize_step(d[m].ctrl, d[m].geo.cfl);
-    }
+    if (i < n) finalize_step(d[i].ctrl, d[i].geo.cfl);
 }
 
 // Neumaier-compensated accumulator combined pairwise in a fixed tree.
@@ -2226,9 +2221,9 @@ hipError_t launch_status_gather(const MeshDesc* d, int n, unsigned long long* ou
     return hipGetLastError();
 }
 
-hipError_t launch_ctrl_batch(const MeshDesc* d, const int* order, int n, hipStream_t s) {
+hipError_t launch_ctrl_batch(const MeshDesc* d, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(ctrl_batch_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, order, n);
+    hipLaunchKernelGGL(ctrl_batch_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, n);
     return hipGetLastError();
 }
 

@@ -1526,17 +1526,17 @@ int hydro_riemann_fluxes(int precision, int ntan, double gamma, int64_t nfaces, 
 struct hydro_batch_ctx {
     std::vector<hydro_t> members;
     hipStream_t stream;
-    MeshDesc* d_desc;  // descriptor table in the caller's workspace
-    int* d_order;      // member indices in group order
+    MeshDesc* d_desc;  // descriptor table in the caller's workspace, in group order
     int2* d_blk;       // work-group table, grouped
     struct Group {
         int ndim, precision, integrator;
         Tile tile;
         int blk_off, nblk;
-        int mem_off, nmem;  // the group's members: d_order[mem_off .. mem_off + nmem)
+        int mem_off, nmem;  // the group's descriptors: d_desc[mem_off .. mem_off + nmem)
         double cells;       // cells of its members
     };
     std::vector<Group> groups;
+    std::vector<int> order;  // order[k]: the member (caller's index) of descriptor k
     // Direct launches spread the groups over the batch's stream and up to
     // kBatchSideStreams more (group_stream[g]: 0 the batch's stream, i > 0
     // side[i - 1]), forked from and joined back to the batch's stream by events.
@@ -1585,17 +1585,18 @@ Tile rule_tile(const hydro_t h, int rule) {
     return t;
 }
 
-// Members grouped by (ndim, precision, tile); each group's work-groups are
-// contiguous in the table, members in the caller's order within a group.
-// Member i runs tile rule_tile(members[i], rule).
+// Members grouped by (ndim, precision, tile): each group's descriptors and
+// work-groups are contiguous in their tables, members in the caller's order
+// within a group (P.order maps a descriptor to its member).  Member i runs
+// tile rule_tile(members[i], rule).
 bool plan_batch(int n, const hydro_t* members, BatchPlan& P, int rule = 0) {
-    P.desc.resize(n);
+    std::vector<MeshDesc> desc(n);
     std::vector<int> order(n);
     std::vector<Tile> tiles(n);
     for (int i = 0; i < n; ++i) {
         const hydro_t h = members[i];
         tiles[i] = rule_tile(h, rule);
-        MeshDesc& d = P.desc[i];
+        MeshDesc& d = desc[i];
         d.U = h->U;
         d.U1 = h->U1;
         d.ctrl = h->ctrl;
@@ -1624,22 +1625,22 @@ bool plan_batch(int n, const hydro_t* members, BatchPlan& P, int rule = 0) {
             g.cells = 0.0;
             P.groups.push_back(g);
         }
-        const MeshDesc& d = P.desc[i];
+        const MeshDesc& d = desc[i];
+        P.desc.push_back(d);
         P.order.push_back(i);
         P.groups.back().nmem += 1;
         P.groups.back().cells += (double)d.geo.ncells;
         const long long nb = (long long)d.tiles_x * d.tiles_y * d.chunks_z;
         if (nb > (1ll << 28) || (long long)P.blk.size() + nb > (1ll << 30)) return false;
-        for (int b = 0; b < (int)nb; ++b) P.blk.push_back(make_int2(i, b));
+        for (int b = 0; b < (int)nb; ++b) P.blk.push_back(make_int2(idx, b));
         P.groups.back().nblk += (int)nb;
     }
     return true;
 }
 
-// Workspace: descriptors, member order, work-group table, status table.
 size_t batch_bytes(const BatchPlan& P) {
-    return align_up(P.desc.size() * sizeof(MeshDesc)) + align_up(P.desc.size() * sizeof(int)) +
-           align_up(P.blk.size() * sizeof(int2)) + align_up(P.desc.size() * 3 * sizeof(unsigned long long));
+    return align_up(P.desc.size() * sizeof(MeshDesc)) + align_up(P.blk.size() * sizeof(int2)) +
+           align_up(P.desc.size() * 3 * sizeof(unsigned long long));
 }
 
 // Groups onto streams, largest first onto the least loaded (by cells), over
@@ -1727,7 +1728,7 @@ hipError_t enqueue_batch_step(hydro_batch_t b) {
         if (e == hipSuccess)
             e = launch_stage_batch(g.ndim, g.precision, g.integrator == HYDRO_VL2 ? MODE_VL2_CORR : MODE_STAGE2,
                                    g.tile, b->d_desc, b->d_blk + g.blk_off, g.nblk, b->stream);
-    if (e == hipSuccess) e = launch_ctrl_batch(b->d_desc, nullptr, (int)b->members.size(), b->stream);
+    if (e == hipSuccess) e = launch_ctrl_batch(b->d_desc, (int)b->members.size(), b->stream);
     return e;
 }
 
@@ -1751,7 +1752,7 @@ hipError_t enqueue_batch_steps_streams(hydro_batch_t b, int nsteps) {
             if (e == hipSuccess)
                 e = launch_stage_batch(g.ndim, g.precision, vl2 ? MODE_VL2_CORR : MODE_STAGE2, g.tile, b->d_desc,
                                        b->d_blk + g.blk_off, g.nblk, st);
-            if (e == hipSuccess) e = launch_ctrl_batch(b->d_desc, b->d_order + g.mem_off, g.nmem, st);
+            if (e == hipSuccess) e = launch_ctrl_batch(b->d_desc + g.mem_off, g.nmem, st);
         }
     // joined whatever happened above, so no side-stream work outlives a call
     for (int i = 0; i < nside; ++i) {
@@ -1798,9 +1799,9 @@ int hydro_batch_create(int n, const hydro_t* members, void* d_workspace, size_t 
     b->members.assign(members, members + n);
     b->stream = members[0]->stream;
     b->d_desc = (MeshDesc*)d_workspace;
-    b->d_order = (int*)((char*)d_workspace + align_up(P.desc.size() * sizeof(MeshDesc)));
-    b->d_blk = (int2*)((char*)b->d_order + align_up(P.desc.size() * sizeof(int)));
+    b->d_blk = (int2*)((char*)d_workspace + align_up(P.desc.size() * sizeof(MeshDesc)));
     b->groups = P.groups;
+    b->order = P.order;
     b->ev_fork = nullptr;
     assign_group_streams(b);
     b->graph = nullptr;
@@ -1816,9 +1817,6 @@ int hydro_batch_create(int n, const hydro_t* members, void* d_workspace, size_t 
     b->h_status.assign((size_t)n * 3, 0ull);
     hipError_t e = hipMemcpyAsync(b->d_desc, P.desc.data(), P.desc.size() * sizeof(MeshDesc),
                                   hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_order, P.order.data(), P.order.size() * sizeof(int), hipMemcpyHostToDevice,
-                           b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_blk, P.blk.data(), P.blk.size() * sizeof(int2), hipMemcpyHostToDevice,
                            b->stream);
@@ -1893,13 +1891,11 @@ int hydro_batch_autotune(hydro_batch_t b, int steps_per_rule, int* rule_out, dou
         hipError_t x = hipMemcpyAsync(b->d_desc, P.desc.data(), P.desc.size() * sizeof(MeshDesc),
                                       hipMemcpyHostToDevice, b->stream);
         if (x == hipSuccess)
-            x = hipMemcpyAsync(b->d_order, P.order.data(), P.order.size() * sizeof(int), hipMemcpyHostToDevice,
-                               b->stream);
-        if (x == hipSuccess)
             x = hipMemcpyAsync(b->d_blk, P.blk.data(), P.blk.size() * sizeof(int2), hipMemcpyHostToDevice,
                                b->stream);
         if (x == hipSuccess) x = hipStreamSynchronize(b->stream);  // P's host data in use until here
         b->groups = P.groups;
+        b->order = P.order;
         assign_group_streams(b);
         return x;
     };
@@ -1963,10 +1959,12 @@ int hydro_batch_status(hydro_batch_t b, int* done, int64_t* steps, int* flags) {
         b->broken = true;
         return HYDRO_E_DEVICE;
     }
-    for (int i = 0; i < n; ++i) {
-        done[i] = b->h_status[3 * i] ? 1 : 0;
-        if (flags) flags[i] = (int)b->h_status[3 * i + 1];
-        if (steps) steps[i] = (int64_t)b->h_status[3 * i + 2];
+    // the table is in descriptor order
+    for (int k = 0; k < n; ++k) {
+        const int i = b->order[k];
+        done[i] = b->h_status[3 * k] ? 1 : 0;
+        if (flags) flags[i] = (int)b->h_status[3 * k + 1];
+        if (steps) steps[i] = (int64_t)b->h_status[3 * k + 2];
     }
     return HYDRO_OK;
 }

@@ -66,7 +66,10 @@ def run_pair(H, c, max_steps=0, t_end=0.0):
     h.close()
     T0 = O.totals(m, U0)
     dV = np.prod(m.dx)
-    drift = np.abs(T - T0) / (dV * np.abs(U0).reshape(m.ncomp, -1).sum(axis=1))
+    # (a component that starts at zero everywhere, as the Sod tube's momentum,
+    # has no relative drift; that test does not use it)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        drift = np.abs(T - T0) / (dV * np.abs(U0).reshape(m.ncomp, -1).sum(axis=1))
     return rel_l1(U, U_o), drift, (t, t_o, s, s_o)
 
 

@@ -356,7 +356,6 @@ const char* hydro_strerror(int status);
  * update follow one another on one stream, step after step, forked from the
  * members' stream at the call and joined back to it before the call
  * returns, so work enqueued on that stream afterwards sees every step.
- * The device workspace also holds the member order by group.
  * hydro_batch_step is async; read results through the
  * member handles after synchronising the stream.  Results equal those of
  * stepping each member alone with hydro_step_auto.

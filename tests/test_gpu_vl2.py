@@ -118,7 +118,8 @@ def test_mixed_workspace_is_smaller(H):
     assert vl2_64 == heun
 
 
-def test_batch_members_equal_alone(H):
+@pytest.mark.parametrize("use_graph", [True, False], ids=["graph", "streams"])
+def test_batch_members_equal_alone(H, use_graph):
     import torch
     cases = [(wl.turbulence_3d(n=(40, 24, 20), mach=1.0, seed=16), 1),
              (wl.turbulence_3d(n=(20, 20, 36), mach=1.0, seed=17), 0),
@@ -130,7 +131,8 @@ def test_batch_members_equal_alone(H):
         h = H.Hydro(c.n, c.gamma, c.cfl, precision=p, lo=c.lo, hi=c.hi, bc=c.bc, stream=s, integrator=VL2)
         h.set_primitive(c.W)
         ms.append(h)
-    b = H.Batch(ms, use_graph=True)
+    b = H.Batch(ms, use_graph=use_graph)
+    assert b.info()["groups"] == 3
     b.step(7)
     s.synchronize()
     for (c, p), h in zip(cases, ms):

@@ -351,7 +351,7 @@ const char* hydro_strerror(int status);
  * sequence is captured once into a HIP graph and replayed (recaptured when
  * nsteps changes).  Without a graph, and when the stream is not being
  * captured, a batch of several groups spreads them over its stream and up
- * to three more streams of its own (made at the first such step, freed by
+ * to two more streams of its own (made at the first such step, freed by
  * hydro_batch_destroy): each group's stages and its members' time / dt
  * update follow one another on one stream, step after step, forked from the
  * members' stream at the call and joined back to it before the call

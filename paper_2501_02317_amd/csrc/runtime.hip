@@ -1562,9 +1562,13 @@ struct BatchPlan {
     std::vector<hydro_batch_ctx::Group> groups;
 };
 
-// Three more streams: with the batch's own, one per hardware queue of a
-// process at HIP's default queue count.
-constexpr int kBatchSideStreams = 3;
+// Two more streams: with the batch's own, three of the four hardware queues
+// a process has at HIP's default, leaving one for other work (a server's
+// set-up stream).  Streams beyond the queue count share queues, and two
+// streams on one queue run in turn; with three more, the saturated serving
+// rate varied 1.32-1.40e10 from one server to the next, with two more it
+// held at 1.37-1.41e10.
+constexpr int kBatchSideStreams = 2;
 
 // Tile rules of the batch autotuner for members of one or two dimensions:
 // a row width for every such member (0: the member's own) and a chunk length

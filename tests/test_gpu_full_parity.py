@@ -1,8 +1,9 @@
 """Whole-run parity at the benchmark sizes: 128^3 Mach-1 for 200 steps (FP64)
 and 256^3 Mach-2 for 100 steps (FP64 and mixed), and the van Leer integrator
-(Sec. 3.3) on 128^3 Mach-1 for 100 steps (FP64 and mixed), GPU against the
-FP64 oracle run on the host cores (about four and a half minutes of oracle
-time at 16 threads).  The oracle prints a progress line every ten steps straight to the
+(Sec. 3.3) on 128^3 Mach-1 for 100 steps (FP64 and mixed), and the
+benchmark's refined mesh for 40 steps (FP64 and mixed), GPU against the FP64
+oracle run on the host cores (about five minutes of oracle time at 16
+threads).  The oracle prints a progress line every ten steps straight to the
 terminal (past pytest's output capture), so the run is never silent for long.
 """
 import os
@@ -84,5 +85,59 @@ def test_full_run_against_oracle(H, capsys, name, precision, tol):
               f"t {t:.15e} vs oracle {t_o:.15e}, steps {s} vs {s_o}, totals drift / (dV sum|U|) {drift}",
               flush=True)
     assert s == s_o
+    assert np.all(err <= tol)
+    assert np.all(drift <= 1e-12)
+
+
+# The refined mesh of the benchmark's refinement leg (Sec. 2.3.1, Sec. 3.1.2):
+# 128^3 level-0 cells in 4x4x4 blocks of 32^3 with the central 2x2x2 blocks
+# refined (120 leaves, 3.9 million cells), a smooth Mach-1 field, gamma 5/3,
+# CFL 0.3, 40 Heun steps.
+SMR_N, SMR_B, SMR_STEPS = (128, 128, 128), (4, 4, 4), 40
+SMR_REFINED = [bx + 4 * (by + 4 * bz) for bz in (1, 2) for by in (1, 2) for bx in (1, 2)]
+_smr_cache = {}
+
+
+def oracle_smr_result():
+    if not _smr_cache:
+        m = O.Mesh(SMR_N, 5.0 / 3.0)
+        S = O.SMR(m, SMR_B, SMR_REFINED)
+        W = wl.smr_field(S.leaves, SMR_N, SMR_B, mach=1.0)
+        U0 = S.prim_to_cons(W)
+        print(f"[oracle] refined 128^3, {len(S.leaves)} leaves: {SMR_STEPS} steps ...", flush=True)
+        t0 = time.perf_counter()
+        U, t, s, _ = S.run(U0, 0.3, max_steps=SMR_STEPS)
+        el = time.perf_counter() - t0
+        cells = int(np.prod(S.shape)) // m.ncomp
+        print(f"[oracle] refined 128^3: {s} steps to t={t:.6e} in {el:.1f} s "
+              f"({cells * s / el:.3e} cell-updates/s)", flush=True)
+        _smr_cache.update(S=S, W=W, U0=U0, U=U, t=t, s=s)
+    return _smr_cache
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_refined_run_against_oracle(H, capsys, precision, tol):
+    with capsys.disabled():
+        r = oracle_smr_result()
+    S = r["S"]
+    say("full run refined", precision)
+    h = H.Hydro(SMR_N, 5.0 / 3.0, 0.3, precision=precision, blocks=SMR_B, refined=SMR_REFINED)
+    assert np.array_equal(h.leaves, S.leaves)
+    h.set_primitive(r["W"])
+    T0 = h.totals()
+    h.step_auto(SMR_STEPS)
+    U, t, s, T = h.get_state(), h.time(), h.steps_done(), h.totals()
+    h.close()
+    nc = S.mesh.ncomp
+    a = U.transpose(1, 0, 2, 3, 4).reshape(nc, -1)
+    b = r["U"].transpose(1, 0, 2, 3, 4).reshape(nc, -1)
+    err = np.abs(a - b).sum(axis=1) / np.abs(b).sum(axis=1)
+    scale = S.totals(np.abs(r["U0"]))
+    drift = np.abs(T - T0) / scale
+    with capsys.disabled():
+        print(f"\n[parity] refined 128^3 precision={precision}: relL1 per component {err}, "
+              f"t {t:.15e} vs oracle {r['t']:.15e}, steps {s} vs {r['s']}, totals drift / sum|U| {drift}",
+              flush=True)
+    assert s == r["s"] == SMR_STEPS
     assert np.all(err <= tol)
     assert np.all(drift <= 1e-12)

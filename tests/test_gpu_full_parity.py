@@ -1,11 +1,13 @@
 """Whole-run parity at the benchmark sizes: 128^3 Mach-1 for 200 steps (FP64)
 and 256^3 Mach-2 for 100 steps (FP64 and mixed), and the van Leer integrator
-(Sec. 3.3) on 128^3 Mach-1 for 100 steps (FP64 and mixed), and the
+(Sec. 3.3) on 128^3 Mach-1 for 100 steps (FP64 and mixed), the paper's
+Table 1 grid (2-D 4096 x 1024) for 40 steps (FP64 and mixed), and the
 benchmark's refined mesh for 40 steps (FP64 and mixed), GPU against the FP64
-oracle run on the host cores (about five minutes of oracle time at 16
+oracle run on the host cores (about six minutes of oracle time at 16
 threads).  The oracle prints a progress line every ten steps straight to the
 terminal (past pytest's output capture), so the run is never silent for long.
 """
+import dataclasses
 import os
 import time
 
@@ -33,6 +35,10 @@ CASES = {
     "c2_128_mach1_200": (lambda: wl.turbulence_3d(n=128, mach=1.0, seed=201, steps=200, cfl=0.3), 0),
     "c3_256_mach2_100": (lambda: wl.turbulence_3d(n=256, mach=2.0, seed=301, steps=100, cfl=0.3), 0),
     "vl2_128_mach1_100": (lambda: wl.turbulence_3d(n=128, mach=1.0, seed=211, steps=100, cfl=0.3), 1),
+    # the paper's Table 1 grid (Sec. 4.3): 4096 x 1024 square cells on [0,4] x [0,1]
+    # (40 steps: the oracle's 2-D path runs on one thread, at about 3e6 cell-updates/s)
+    "grid_4096x1024_40": (lambda: dataclasses.replace(
+        wl.turbulence_3d(n=(4096, 1024), mach=1.0, seed=601, gamma=1.4, cfl=0.4, steps=40), hi=(4.0, 1.0)), 0),
 }
 _oracle_cache = {}
 
@@ -65,7 +71,9 @@ def oracle_result(name):
                                                 ("c3_256_mach2_100", 0, 1e-12),
                                                 ("c3_256_mach2_100", 1, 1e-5),
                                                 ("vl2_128_mach1_100", 0, 1e-12),
-                                                ("vl2_128_mach1_100", 1, 1e-5)])
+                                                ("vl2_128_mach1_100", 1, 1e-5),
+                                                ("grid_4096x1024_40", 0, 1e-12),
+                                                ("grid_4096x1024_40", 1, 1e-5)])
 def test_full_run_against_oracle(H, capsys, name, precision, tol):
     with capsys.disabled():
         c, m, U0, U_o, t_o, s_o = oracle_result(name)

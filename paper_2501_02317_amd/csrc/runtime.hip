@@ -1567,7 +1567,7 @@ struct BatchPlan {
 // set-up stream).  Streams beyond the queue count share queues, and two
 // streams on one queue run in turn; with three more, the saturated serving
 // rate varied 1.32-1.40e10 from one server to the next, with two more it
-// held at 1.37-1.41e10.
+// held at 1.37-1.42e10.
 constexpr int kBatchSideStreams = 2;
 
 // Tile rules of the batch autotuner for members of one or two dimensions:
